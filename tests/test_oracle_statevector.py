@@ -1,0 +1,104 @@
+"""Pins of the oracle's state-vector simulator: brute-force full unitaries on 1-3 qubits
+built from Kronecker products and explicit basis loops, the norm, the empty circuit,
+the Porter-Thomas collision ratio (main text, Fig. 3 discussion) and the projector form
+of slicing (Appendix B.2: the slices sum to the whole)."""
+
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import gates, statevector
+from oracle.metrics import collision_ratio
+
+
+def _circuit(n, layers, theta=math.pi / 2, phi=math.pi / 6):
+    return {"n_qubits": n, "fsim": {"theta": theta, "phi": phi},
+            "layers": [{"oneq": o, "couplers": c} for o, c in layers]}
+
+
+def _full_oneq_layer(names):
+    m = np.eye(1)
+    for nm in names:                      # qubit 0 is the leftmost (most significant) factor
+        m = np.kron(m, gates.ONEQ[nm])
+    return m
+
+
+def _full_two_qubit(n, qa, qb, f):
+    dim = 1 << n
+    m = np.zeros((dim, dim), dtype=complex)
+    for x in range(dim):                  # x = input basis state, y = output basis state
+        for y in range(dim):
+            same = all(((x >> (n - 1 - q)) & 1) == ((y >> (n - 1 - q)) & 1)
+                       for q in range(n) if q not in (qa, qb))
+            if not same:
+                continue
+            ai, bi = (x >> (n - 1 - qa)) & 1, (x >> (n - 1 - qb)) & 1
+            ao, bo = (y >> (n - 1 - qa)) & 1, (y >> (n - 1 - qb)) & 1
+            m[y, x] = f[2 * ao + bo, 2 * ai + bi]
+    return m
+
+
+def _brute(c):
+    n = c["n_qubits"]
+    f = gates.fsim(c["fsim"]["theta"], c["fsim"]["phi"])
+    u = np.eye(1 << n, dtype=complex)
+    for layer in c["layers"]:
+        u = _full_oneq_layer(layer["oneq"]) @ u
+        for qa, qb in layer["couplers"]:
+            u = _full_two_qubit(n, qa, qb, f) @ u
+    return u[:, 0]
+
+
+@pytest.mark.parametrize("n,layers", [
+    (1, [(["sqrt_x"], []), (["sqrt_w"], []), (["sqrt_y"], [])]),
+    (2, [(["sqrt_x", "sqrt_y"], [(0, 1)]), (["sqrt_w", "sqrt_x"], [(0, 1)])]),
+    (3, [(["sqrt_y", "sqrt_w", "sqrt_x"], [(0, 1)]), (["sqrt_x", "sqrt_y", "sqrt_w"], [(1, 2)]),
+         (["sqrt_w", "sqrt_x", "sqrt_y"], [(0, 2)])]),
+])
+def test_statevector_matches_brute_force(n, layers):
+    c = _circuit(n, layers, theta=1.1, phi=0.7)
+    assert np.allclose(statevector.simulate(c), _brute(c), atol=1e-14)
+
+
+def test_empty_circuit_is_all_zero_state():
+    c = _circuit(4, [])
+    psi = statevector.simulate(c)
+    assert psi[0] == 1 and np.count_nonzero(psi) == 1
+
+
+def test_norm_and_porter_thomas():
+    psi = statevector.simulate(synth.make_circuit(3, 4, 8, 1001))
+    assert abs(np.sum(np.abs(psi) ** 2) - 1.0) < 1e-12
+    deep = statevector.simulate(synth.make_circuit(4, 4, 14, 11))
+    # Porter-Thomas: 2^n sum p^2 -> 2 for deep random circuits
+    assert abs(collision_ratio(np.abs(deep) ** 2) - 2.0) < 0.1
+
+
+def test_projector_slices_sum_to_state():
+    c = synth.make_circuit(2, 3, 6, 5)
+    full = statevector.simulate(c)
+    bonds = [(0, 0), (2, 1), (4, 0)]
+    acc = np.zeros_like(full)
+    parts = []
+    for vals in itertools.product((0, 1), repeat=len(bonds)):
+        part = statevector.simulate(c, projectors=dict(zip(bonds, vals)))
+        parts.append(part)
+        acc += part
+    assert np.allclose(acc, full, atol=1e-14)
+    # slices are different pieces, not copies
+    assert min(np.linalg.norm(p) for p in parts) < 0.9 * np.linalg.norm(full)
+
+
+def test_sparse_from_state_bit_order():
+    n = 3
+    psi = np.arange(8, dtype=complex)
+    # open qubit 2 (least significant); group closed bits 0b110 -> indices 6, 7
+    out = statevector.sparse_from_state(psi, n, [2], [0b110])
+    assert list(out[0]) == [6, 7]
+    # open qubits [2, 0] (qubit 2 is the most significant bit of mu)
+    out = statevector.sparse_from_state(psi, n, [2, 0], [0b010])
+    # mu = (s2, s0): (0,0)->x=010=2, (0,1)->110=6, (1,0)->011=3, (1,1)->111=7
+    assert list(out[0]) == [2, 6, 3, 7]
