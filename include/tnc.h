@@ -1,0 +1,164 @@
+/* tnc.h - C ABI of the sliced sparse-state tensor-network contractor for MI355X (gfx950).
+ *
+ * The library contracts the tensor network of a random quantum circuit once per slice
+ * and sums the slices, in FP64, into a sparse set of output amplitudes psi_hat(s), then
+ * draws bitstrings by |psi_hat(s)|^2 - the sampling method of Pan, Chen & Zhang,
+ * "Solving the sampling problem of the Sycamore quantum circuits" (arXiv:2111.03011).
+ *
+ * Conventions shared by every call
+ *   - Every call returns tnc_status; no exception or abort crosses the ABI.  On an error
+ *     tnc_last_error() describes it (thread-local, valid until the next tnc_* call on the
+ *     same thread).
+ *   - Host arrays passed in are copied during the call; the caller keeps ownership.
+ *   - Device memory is never allocated by the library for results or intermediates: the
+ *     caller passes a workspace of tnc_plan_workspace_bytes() bytes and the output
+ *     buffer (device pointers, e.g. from torch tensors).  Streams are hipStream_t passed
+ *     as void* (NULL = the default stream).
+ *   - Bit order: in a uint64 bitstring, bit (n-1-q) holds qubit q's value s_q, so qubit 0
+ *     is the most significant of the n bits.  The open configuration of a group is
+ *     mu = sum_t s_{open[t]} 2^(n_open-1-t): the first listed open qubit is the most
+ *     significant bit of mu.
+ *   - Complex numbers are interleaved (re, im).
+ */
+#ifndef TNC_H
+#define TNC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tnc_status;
+enum {
+  TNC_OK = 0,
+  TNC_E_INVALID = -1,      /* bad argument, network, path, slices or targets */
+  TNC_E_OOM = -2,          /* workspace or arena too small */
+  TNC_E_HIP = -3,          /* a HIP runtime call failed */
+  TNC_E_UNSUPPORTED = -4,  /* valid request the library does not implement */
+  TNC_E_BUSY = -5,         /* result not ready yet */
+  TNC_E_NOT_FOUND = -6,    /* unknown handle or id */
+  TNC_E_INTERNAL = -7
+};
+
+const char* tnc_last_error(void);
+
+/* Arithmetic of the contraction steps.  The slice sum and the sampler are FP64 in every
+ * case.  TNC_C64: complex64 operands, FP32 accumulation on the FP32 matrix cores. */
+typedef enum {
+  TNC_C64 = 0,
+  TNC_FP16X3 = 1,
+  TNC_BF16X3 = 2,
+  TNC_FP16X3_3M = 3,
+  TNC_BF16X3_3M = 4
+} tnc_precision;
+
+typedef struct tnc_net_s* tnc_net;    /* opaque; freed by tnc_net_destroy */
+typedef struct tnc_plan_s* tnc_plan;  /* opaque; freed by tnc_plan_destroy */
+
+/* The tensor network of a circuit (paper, "Method": gates are matrices and four-way
+ * tensors, the initial state a set of vectors, the final state a boundary).  Every bond
+ * has dimension 2.  All pointers are host memory.
+ *   ranks[n_tensors]      rank of each tensor (0..40)
+ *   labels[sum(ranks)]    label ids (>= 0) of each tensor, concatenated; a label is held
+ *                         by exactly two tensors (a bond) or by one tensor (an output leg)
+ *   data                  complex128 entries of each tensor, concatenated, 2^rank each,
+ *                         row-major in label order (first label slowest)
+ *   out_label[n_qubits]   output-leg label of each qubit; every label held by one tensor
+ *                         must be an output leg */
+typedef struct {
+  int32_t n_qubits;
+  int32_t n_tensors;
+  const int32_t* ranks;
+  const int32_t* labels;
+  const double* data;
+  const int32_t* out_label;
+} tnc_network_desc;
+
+/* Copy a network (validated) for use on HIP device `device`. */
+tnc_status tnc_net_create(int device, const tnc_network_desc* desc, tnc_net* out);
+
+/* Contraction order (Appendix E format): n pairs (i, j); the contraction of tensors i and
+ * j is stored at position i and j is retired.  After the last pair exactly one tensor must
+ * remain.  out_orders must be NULL (the library chooses every result's label order). */
+tnc_status tnc_net_set_path(tnc_net net, const int32_t* pairs, int32_t n,
+                            const int32_t* out_orders);
+
+/* Slicing (Appendix B.2): fix the k labels sliced_labels[0..k) and sum over the slice
+ * ids.  Bit b of a slice id is the value of sliced_labels[b].  Each sliced label must be
+ * a bond.  k = 0 with n_ids = 1 (id 0) means unsliced.  Ids must be < 2^k. */
+tnc_status tnc_net_set_slices(tnc_net net, const int32_t* sliced_labels, int32_t k,
+                              const uint64_t* slice_ids, int64_t n_ids);
+
+/* Sparse-state targets (Appendix A): L groups; group i is closed_bits[i] on the closed
+ * qubits joined with all 2^n_open configurations of the open qubits.  Bits of open
+ * qubits in closed_bits are ignored.  Closed parts must be distinct.  n_qubits <= 64. */
+tnc_status tnc_net_set_targets(tnc_net net, const int32_t* open_qubits, int32_t n_open,
+                               const uint64_t* closed_bits, int64_t L);
+
+/* Compile the step program of a network whose path, slices and targets are set.
+ * max_batch_slices >= 1: slices contracted together per launch sequence. */
+tnc_status tnc_plan_create(tnc_net net, tnc_precision precision, int32_t max_batch_slices,
+                           tnc_plan* out);
+
+/* Bytes of device workspace tnc_contract needs. */
+tnc_status tnc_plan_workspace_bytes(tnc_plan plan, uint64_t* bytes);
+
+/* Algorithmic cost of one slice: flops = 8 x complex multiply-adds (Table I caption),
+ * bytes = operands read + results written by every step.  Steps that touch no sliced
+ * tensor are run once per tnc_contract call and are not included. */
+tnc_status tnc_plan_stats(tnc_plan plan, double* flops_per_slice, double* bytes_per_slice,
+                          int32_t* n_steps);
+
+/* Contract all slice ids and write the FP64 sum to d_amps (device, [L][2^n_open]
+ * complex128, caller-owned).  h_norm (host, nullable) receives sum |amp|^2 (paper,
+ * Results: the norm of the sparse state); it synchronises the stream. */
+tnc_status tnc_contract(tnc_plan plan, void* d_workspace, uint64_t ws_bytes, void* hip_stream,
+                        double* d_amps, double* h_norm);
+
+/* Contract slice ids [first, first + count) of the slice list.  accumulate = 0 overwrites
+ * d_amps with their sum, 1 adds their sum to it (summation order: ascending position). */
+tnc_status tnc_contract_range(tnc_plan plan, void* d_workspace, uint64_t ws_bytes,
+                              void* hip_stream, double* d_amps, int64_t first, int64_t count,
+                              int32_t accumulate);
+
+/* Draw bitstrings by |amp|^2 (main text, sampling paragraph).  d_amps: device
+ * [L][2^n_open] complex128.  L == 1: n_samples draws from the one group; L > 1: n_samples
+ * must equal L, one draw per group.  Uniforms: u_j = (SplitMix64 output j+1 from state
+ * `seed`) >> 11 times 2^-53, j = draw index (L == 1) or group index (L > 1); the draw is the
+ * smallest mu with c_mu > u * c_{l-1}, c the FP64 running sum of re^2 + im^2 in mu order.
+ * h_bitstrings (host, [n_samples]) receives full bitstrings.  The workspace is the one
+ * tnc_contract uses (its scratch holds the running sums).  Synchronises the stream. */
+tnc_status tnc_sample(tnc_plan plan, void* d_workspace, uint64_t ws_bytes, const double* d_amps,
+                      uint64_t seed, int64_t n_samples, uint64_t* h_bitstrings, void* hip_stream);
+
+tnc_status tnc_plan_destroy(tnc_plan plan);
+tnc_status tnc_net_destroy(tnc_net net);
+
+/* Per-step description for reporting: kind 0 = permute, 1 = GEMM, 2 = small-operand
+ * stream, 3 = slice leaves, 4 = slice sum, 5 = split-K reduction; rows, m, n, k in
+ * elements; flops and bytes algorithmic; invariant = 1 if run once per call. */
+typedef struct {
+  int32_t kind;
+  int32_t invariant;
+  int64_t rows, m, n, k;
+  double flops;
+  double bytes;
+} tnc_step_info;
+
+tnc_status tnc_plan_n_launches(tnc_plan plan, int32_t* n);
+tnc_status tnc_plan_launch_info(tnc_plan plan, int32_t i, tnc_step_info* info);
+
+/* Timing of launches by kind on the contraction stream.  enable = 1 makes later
+ * tnc_contract calls record a HIP event pair around every launch; tnc_plan_timing then
+ * returns, per kind (array of 6), the summed milliseconds, summed algorithmic bytes and
+ * flops and the launch count since the last reset (synchronises on the events). */
+tnc_status tnc_plan_set_timing(tnc_plan plan, int32_t enable);
+tnc_status tnc_plan_timing(tnc_plan plan, double* ms, double* bytes, double* flops,
+                           int64_t* launches, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TNC_H */

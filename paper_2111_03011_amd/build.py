@@ -1,0 +1,70 @@
+"""Build libtnc.so in-tree with hipcc for gfx950.
+
+Every HIP translation unit is compiled with packed-FP32 instructions disabled.
+"""
+
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+LIB = os.path.join(HERE, "libtnc.so")
+BUILD_DIR = os.path.join(HERE, "_build")
+
+HIP_FLAGS = [
+    "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+]
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall"]
+
+
+def _hipcc() -> str:
+    for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found; ROCm is required to build libtnc")
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError(f"command failed ({res.returncode}): {' '.join(cmd[:3])} ...")
+    if verbose and res.stderr.strip():
+        # hipcc's host pass warns about the packed-fp32 feature name; that is expected
+        lines = [l for l in res.stderr.splitlines() if "packed-fp32-ops" not in l]
+        if any(l.strip() for l in lines):
+            print("\n".join(lines))
+
+
+def build(verbose: bool = False) -> str:
+    hipcc = _hipcc()
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    inc = ["-I", INCLUDE, "-I", CSRC]
+    objs = []
+    for src in ("kernels.hip", "tnc.cpp"):
+        obj = os.path.join(BUILD_DIR, src.replace(".", "_") + ".o")
+        path = os.path.join(CSRC, src)
+        if src.endswith(".hip"):
+            cmd = [hipcc, *HIP_FLAGS, *inc, "-c", path, "-o", obj]
+        else:
+            cmd = [hipcc, *HOST_FLAGS, *inc, "-D__HIP_PLATFORM_AMD__", "-c", path, "-o", obj]
+        _run(cmd, verbose)
+        objs.append(obj)
+    tmp = LIB + ".tmp"
+    _run([hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp], verbose)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

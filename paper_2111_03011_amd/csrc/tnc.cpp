@@ -1,0 +1,1172 @@
+// libtnc host runtime: C ABI, validation, step compiler, workspace planner, executor.
+//
+// The contraction of one slice is compiled once into a list of kernel launches:
+//   * leaves carrying sliced bonds are instantiated per slice (paper, Appendix B.2);
+//   * every path pair (Appendix E format) becomes either a fused small-operand stream, or
+//     permutes (only when an operand's labels are interleaved) followed by a complex GEMM,
+//     optionally split along K with a fixed-order reduction;
+//   * tensors that carry closed final qubits keep one row per distinct restriction of the
+//     requested bitstrings (Appendix A: only the configurations some target needs), and
+//     a contraction of two such tensors gathers the matching operand rows;
+//   * the last tensor is added in FP64 to psi_hat (the sum over slices, Results).
+// Steps whose subtree holds no sliced leaf are identical in every slice and run once per
+// call.  All device memory is the caller's workspace: a constants block (leaves, row maps,
+// tables) followed by an arena whose buffers are packed by lifetime.
+#include "tnc.h"
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <set>
+#include <stdexcept>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "tnc_kernels.h"
+
+using namespace tnc;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Error {
+  tnc_status code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(tnc_status c, const std::string& m) { throw Error{c, m}; }
+
+#define HIPCHK(x)                                                                   \
+  do {                                                                              \
+    hipError_t e_ = (x);                                                            \
+    if (e_ != hipSuccess) fail(TNC_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <class F>
+tnc_status guard(F&& f) {
+  try {
+    f();
+    g_err.clear();
+    return TNC_OK;
+  } catch (const Error& e) {
+    g_err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_err = "host out of memory";
+    return TNC_E_OOM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return TNC_E_INTERNAL;
+  }
+}
+
+constexpr uint64_t kAlign = 256;
+uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------
+struct tnc_net_s {
+  int device = 0;
+  int n_qubits = 0;
+  std::vector<std::vector<int32_t>> labels;
+  std::vector<std::vector<double>> data;
+  std::vector<int32_t> out_label;
+  std::map<int32_t, std::vector<int>> holders;
+  bool has_path = false;
+  std::vector<std::pair<int, int>> path;
+  bool has_slices = false;
+  std::vector<int32_t> sliced;
+  std::vector<uint64_t> slice_ids;
+  bool has_targets = false;
+  std::vector<int32_t> open;
+  std::vector<uint64_t> closed;
+};
+
+namespace {
+
+enum Kind { K_PERMUTE = 0, K_GEMM = 1, K_STREAM = 2, K_LEAVES = 3, K_SUM = 4, K_REDUCE = 5 };
+constexpr int kKinds = 6;
+
+struct Buf {
+  uint64_t bytes = 0;
+  bool is_const = false;
+  uint64_t off = 0;       // absolute byte offset in the workspace
+  int t0 = INT_MAX, t1 = -1;
+  bool to_end = false;    // produced once, read by every slice
+};
+
+struct Launch {
+  int kind = 0;
+  bool inv = false;
+  std::vector<int> bufs;  // buffers touched (for lifetimes)
+  int b_in0 = -1, b_in1 = -1, b_out = -1, b_tmp = -1;
+  int64_t g0 = -1, g1 = -1;   // byte offsets of row gathers in the constants block
+  PermuteArgs perm{};
+  StreamArgs st{};
+  GemmArgs gm{};
+  ReduceArgs rd{};
+  tnc_step_info info{};
+};
+
+struct TState {
+  std::vector<int32_t> dense;   // slowest first
+  uint64_t q = 0;
+  std::vector<uint64_t> keys;
+  bool dep = false;
+  int buf = -1;
+  bool alive = true;
+  int64_t rows() const { return int64_t(keys.size()); }
+  int64_t elems() const { return rows() << dense.size(); }
+};
+
+struct TimingRec {
+  int kind;
+  double bytes, flops;
+  hipEvent_t e0, e1;
+};
+
+}  // namespace
+
+struct tnc_plan_s {
+  int device = 0;
+  int n_qubits = 0;
+  tnc_precision precision = TNC_C64;
+  int64_t L = 1;
+  int n_open = 0;
+  std::vector<int32_t> open;
+  std::vector<uint64_t> closed;
+  std::vector<uint64_t> slice_ids;
+
+  std::vector<Buf> bufs;
+  std::vector<uint8_t> consts;
+  uint64_t consts_bytes = 0, ws_bytes = 0;
+  std::vector<Launch> inv, dep;
+
+  // slice leaves
+  std::vector<SliceLeafEntry> sl_table;
+  std::vector<int64_t> sl_prefix;
+  int64_t sl_total = 0;
+  int64_t sl_table_off = -1, sl_prefix_off = -1;
+  int64_t slice_ids_off = 0;
+  // final sum
+  SliceSumArgs ss{};
+  int final_buf = -1;
+  int64_t row_of_off = 0;
+  // sampling and norm scratch
+  int64_t closed_off = 0, open_off = 0;
+  int norm_parts = 1024;
+  int b_norm = -1, b_cum = -1, b_samples = -1;
+  int64_t sample_chunk = 0;
+
+  double flops_slice = 0, bytes_slice = 0, flops_inv = 0, bytes_inv = 0;
+  int n_steps = 0;
+
+  const void* uploaded_ws = nullptr;
+
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<TimingRec> pending;
+  double t_ms[kKinds] = {}, t_bytes[kKinds] = {}, t_flops[kKinds] = {};
+  int64_t t_n[kKinds] = {};
+  ~tnc_plan_s() {
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
+  }
+};
+
+// ------------------------------------------------------------------------------------
+// helpers
+namespace {
+
+std::vector<uint64_t> row_keys(const std::vector<uint64_t>& closed, uint64_t q) {
+  std::vector<uint64_t> k;
+  if (q == 0) return {0};
+  k.reserve(closed.size());
+  for (uint64_t c : closed) k.push_back(c & q);
+  std::sort(k.begin(), k.end());
+  k.erase(std::unique(k.begin(), k.end()), k.end());
+  return k;
+}
+
+int pos_of(const std::vector<int32_t>& dense, int32_t label) {
+  for (size_t i = 0; i < dense.size(); ++i)
+    if (dense[i] == label) return int(dense.size() - 1 - i);
+  return -1;
+}
+
+struct Compiler {
+  tnc_net_s& net;
+  tnc_plan_s& plan;
+  std::vector<TState> T;
+  std::set<int32_t> sliced_set;
+  std::map<int32_t, int> sliced_bit;
+
+  Compiler(tnc_net_s& n, tnc_plan_s& p) : net(n), plan(p) {}
+
+  int new_buf(uint64_t bytes, bool is_const = false) {
+    Buf b;
+    b.bytes = align_up(std::max<uint64_t>(bytes, 8));
+    b.is_const = is_const;
+    plan.bufs.push_back(b);
+    return int(plan.bufs.size() - 1);
+  }
+
+  int64_t add_const(const void* p, uint64_t bytes) {
+    const uint64_t off = align_up(plan.consts.size());
+    plan.consts.resize(off + bytes);
+    if (bytes) std::memcpy(plan.consts.data() + off, p, bytes);
+    plan.consts.resize(align_up(plan.consts.size()));
+    return int64_t(off);
+  }
+
+  int const_buf(const void* p, uint64_t bytes) {
+    const int64_t off = add_const(p, bytes);
+    const int b = new_buf(bytes, true);
+    plan.bufs[b].off = uint64_t(off);
+    return b;
+  }
+
+  std::vector<Launch>& list(bool inv) { return inv ? plan.inv : plan.dep; }
+
+  // gather map of an operand into output rows; -1 = none needed
+  int64_t gather(const TState& op, const TState& out) {
+    if (op.q == out.q || op.q == 0) return -1;
+    std::vector<int32_t> g(out.keys.size());
+    for (size_t r = 0; r < out.keys.size(); ++r) {
+      const uint64_t k = out.keys[r] & op.q;
+      auto it = std::lower_bound(op.keys.begin(), op.keys.end(), k);
+      if (it == op.keys.end() || *it != k) fail(TNC_E_INTERNAL, "row map lookup failed");
+      g[r] = int32_t(it - op.keys.begin());
+    }
+    return add_const(g.data(), g.size() * sizeof(int32_t));
+  }
+
+  void leaves() {
+    const int n = net.n_qubits;
+    std::set<int32_t> open_set(net.open.begin(), net.open.end());
+    std::map<int32_t, int> closed_leg;
+    for (int q = 0; q < n; ++q)
+      if (!open_set.count(q)) closed_leg[net.out_label[q]] = q;
+    for (size_t b = 0; b < net.sliced.size(); ++b) {
+      sliced_set.insert(net.sliced[b]);
+      sliced_bit[net.sliced[b]] = int(b);
+    }
+    T.resize(net.labels.size());
+    for (size_t t = 0; t < net.labels.size(); ++t) {
+      const auto& lab = net.labels[t];
+      const int rank = int(lab.size());
+      TState s;
+      std::vector<int32_t> full;       // dense incl. sliced
+      std::vector<int> full_w, cl_w, cl_q;
+      for (int p = 0; p < rank; ++p) {
+        const int64_t w = int64_t(1) << (rank - 1 - p);
+        auto it = closed_leg.find(lab[p]);
+        if (it != closed_leg.end()) {
+          s.q |= uint64_t(1) << (n - 1 - it->second);
+          cl_w.push_back(int(rank - 1 - p));
+          cl_q.push_back(it->second);
+        } else {
+          full.push_back(lab[p]);
+          full_w.push_back(int(rank - 1 - p));
+        }
+        (void)w;
+      }
+      s.keys = row_keys(net.closed, s.q);
+      const int df = int(full.size());
+      std::vector<float> host(size_t(s.rows()) * (size_t(1) << df) * 2);
+      for (int64_t r = 0; r < s.rows(); ++r) {
+        int64_t base = 0;
+        for (size_t c = 0; c < cl_q.size(); ++c)
+          if ((s.keys[r] >> (n - 1 - cl_q[c])) & 1) base += int64_t(1) << cl_w[c];
+        for (int64_t d = 0; d < (int64_t(1) << df); ++d) {
+          int64_t o = base;
+          for (int j = 0; j < df; ++j)
+            if ((d >> (df - 1 - j)) & 1) o += int64_t(1) << full_w[j];
+          const size_t h = size_t((r << df) + d) * 2;
+          host[h] = float(net.data[t][2 * o]);
+          host[h + 1] = float(net.data[t][2 * o + 1]);
+        }
+      }
+      std::vector<int32_t> dense;
+      std::vector<std::pair<int, int>> sl;   // (position in full dense, slice bit)
+      for (int j = 0; j < df; ++j) {
+        if (sliced_set.count(full[j]))
+          sl.push_back({df - 1 - j, sliced_bit[full[j]]});
+        else
+          dense.push_back(full[j]);
+      }
+      s.dense = dense;
+      if (sl.empty()) {
+        s.buf = const_buf(host.data(), host.size() * sizeof(float));
+      } else {
+        if (sl.size() > 8) fail(TNC_E_UNSUPPORTED, "a leaf holds more than 8 sliced labels");
+        std::sort(sl.begin(), sl.end());
+        SliceLeafEntry e{};
+        e.src_off = add_const(host.data(), host.size() * sizeof(float)) / 8;
+        e.elems_out = s.rows() << dense.size();
+        e.dense_out = int32_t(dense.size());
+        e.n_sl = int32_t(sl.size());
+        for (size_t j = 0; j < sl.size(); ++j) {
+          e.pos[j] = int8_t(sl[j].first);
+          e.bit[j] = int8_t(sl[j].second);
+        }
+        s.dep = true;
+        s.buf = new_buf(uint64_t(e.elems_out) * 8);
+        e.dst_off = s.buf;    // resolved after packing
+        plan.sl_table.push_back(e);
+      }
+      T[t] = std::move(s);
+    }
+    if (!plan.sl_table.empty()) {
+      Launch L;
+      L.kind = K_LEAVES;
+      L.inv = false;
+      for (auto& e : plan.sl_table) L.bufs.push_back(int(e.dst_off));
+      int64_t tot = 0;
+      plan.sl_prefix.push_back(0);
+      for (auto& e : plan.sl_table) {
+        tot += e.elems_out;
+        plan.sl_prefix.push_back(tot);
+      }
+      plan.sl_total = tot;
+      L.info.kind = K_LEAVES;
+      L.info.bytes = 16.0 * double(tot);
+      plan.dep.push_back(L);
+    }
+  }
+
+  void account(const Launch& L) {
+    if (L.inv) {
+      plan.flops_inv += L.info.flops;
+      plan.bytes_inv += L.info.bytes;
+    } else {
+      plan.flops_slice += L.info.flops;
+      plan.bytes_slice += L.info.bytes;
+    }
+  }
+
+  // permute operand s (rows kept) into label order `to`; returns the new buffer
+  int emit_permute(const TState& s, const std::vector<int32_t>& to, bool inv, int step_out_buf) {
+    (void)step_out_buf;
+    const int d = int(s.dense.size());
+    std::vector<int> pi(d);   // input position -> output position
+    for (int p = 0; p < d; ++p) pi[p] = pos_of(to, s.dense[d - 1 - p]);
+    Launch L;
+    L.kind = K_PERMUTE;
+    L.inv = inv;
+    PermuteArgs& a = L.perm;
+    a.rows = s.rows();
+    a.row_elems = int64_t(1) << d;
+    // tile bits: the lowest input bits and the input bits that land lowest in the output
+    int ia = std::min(d, 5), ib = std::min(d, 5);
+    auto tile_set = [&](int na, int nb) {
+      std::vector<int> u;
+      for (int p = 0; p < na; ++p) u.push_back(p);
+      for (int p = 0; p < d; ++p)
+        if (pi[p] < nb && p >= na) u.push_back(p);
+      return u;
+    };
+    std::vector<int> U = tile_set(ia, ib);
+    while (true) {
+      bool grew = false;
+      if (ia < d) {
+        auto u2 = tile_set(ia + 1, ib);
+        if (int(u2.size()) <= kMaxTileBits) { ia++; U = u2; grew = true; }
+      }
+      if (ib < d) {
+        auto u2 = tile_set(ia, ib + 1);
+        if (int(u2.size()) <= kMaxTileBits) { ib++; U = u2; grew = true; }
+      }
+      if (!grew) break;
+    }
+    a.n_tile = int(U.size());
+    for (int j = 0; j < a.n_tile; ++j) a.e_in[j] = int8_t(U[j]);
+    std::vector<int> byout = U;
+    std::sort(byout.begin(), byout.end(), [&](int x, int y) { return pi[x] < pi[y]; });
+    for (int j = 0; j < a.n_tile; ++j) {
+      a.f_out[j] = int8_t(pi[byout[j]]);
+      a.f_to_e[j] = int8_t(std::find(U.begin(), U.end(), byout[j]) - U.begin());
+    }
+    int nr = 0;
+    for (int p = 0; p < d; ++p) {
+      if (std::find(U.begin(), U.end(), p) != U.end()) continue;
+      a.r_in[nr] = int8_t(p);
+      a.r_out[nr] = int8_t(pi[p]);
+      nr++;
+    }
+    a.n_rest = nr;
+    const int out = new_buf(uint64_t(s.elems()) * 8);
+    L.b_in0 = s.buf;
+    L.b_out = out;
+    L.bufs = {s.buf, out};
+    L.info.kind = K_PERMUTE;
+    L.info.invariant = inv;
+    L.info.rows = s.rows();
+    L.info.m = int64_t(1) << d;
+    L.info.bytes = 16.0 * double(s.elems());
+    account(L);
+    list(inv).push_back(L);
+    return out;
+  }
+
+  TState step(TState& A, TState& B) {
+    TState C;
+    C.dep = A.dep || B.dep;
+    const bool inv = !C.dep;
+    C.q = A.q | B.q;
+    C.keys = row_keys(net.closed, C.q);
+    std::set<int32_t> sa(A.dense.begin(), A.dense.end()), sb(B.dense.begin(), B.dense.end());
+    std::vector<int32_t> K, MA, NB;
+    for (auto x : A.dense) (sb.count(x) ? K : MA).push_back(x);
+    for (auto x : B.dense)
+      if (!sa.count(x)) NB.push_back(x);
+    const int nk = int(K.size());
+    const double macs = double(C.rows()) * std::ldexp(1.0, int(MA.size() + NB.size() + K.size()));
+
+    // fused stream: one operand small enough to sit in registers/LDS
+    auto stream_ok = [&](const TState& S, const std::vector<int32_t>& Sfree) {
+      return nk <= 6 && int(Sfree.size()) <= 4;
+    };
+    const bool a_small = stream_ok(A, MA), b_small = stream_ok(B, NB);
+    if (a_small || b_small) {
+      bool x_is_a;
+      if (a_small && b_small) x_is_a = A.elems() >= B.elems();
+      else x_is_a = b_small;
+      TState& X = x_is_a ? A : B;
+      TState& S = x_is_a ? B : A;
+      const std::vector<int32_t>& MX = x_is_a ? MA : NB;
+      const std::vector<int32_t>& NS = x_is_a ? NB : MA;
+      Launch L;
+      L.kind = K_STREAM;
+      L.inv = inv;
+      StreamArgs& a = L.st;
+      a.rows = C.rows();
+      a.x_rows = X.rows();
+      a.s_rows = S.rows();
+      a.x_row_stride = int64_t(1) << X.dense.size();
+      a.s_row_stride = int64_t(1) << S.dense.size();
+      a.n_m = int(MX.size());
+      a.nk = nk;
+      a.nn = int(NS.size());
+      a.c_row_stride = int64_t(1) << (a.n_m + a.nn);
+      std::vector<int> kins;
+      for (int j = 0; j < nk; ++j) {
+        a.x_kpos[j] = int8_t(pos_of(X.dense, K[j]));
+        a.s_kpos[j] = int8_t(pos_of(S.dense, K[j]));
+        kins.push_back(a.x_kpos[j]);
+      }
+      std::sort(kins.begin(), kins.end());
+      for (int j = 0; j < nk; ++j) a.x_kins[j] = int8_t(kins[j]);
+      for (int j = 0; j < a.nn; ++j) a.s_npos[j] = int8_t(pos_of(S.dense, NS[NS.size() - 1 - j]));
+      C.dense = MX;
+      C.dense.insert(C.dense.end(), NS.begin(), NS.end());
+      C.buf = new_buf(uint64_t(C.elems()) * 8);
+      L.b_in0 = X.buf;
+      L.b_in1 = S.buf;
+      L.b_out = C.buf;
+      L.g0 = gather(X, C);
+      L.g1 = gather(S, C);
+      L.bufs = {X.buf, S.buf, C.buf};
+      L.info = tnc_step_info{K_STREAM, inv, C.rows(), int64_t(1) << a.n_m, int64_t(1) << a.nn,
+                             int64_t(1) << nk, 8.0 * macs,
+                             8.0 * double(X.elems() + S.elems() + C.elems())};
+      account(L);
+      list(inv).push_back(L);
+      return C;
+    }
+
+    // GEMM: P supplies the M side, Q the N side
+    const bool p_is_a = (double(A.rows()) * std::ldexp(1.0, int(MA.size()))) >=
+                        (double(B.rows()) * std::ldexp(1.0, int(NB.size())));
+    TState& P = p_is_a ? A : B;
+    TState& Q = p_is_a ? B : A;
+    const std::vector<int32_t>& MP = p_is_a ? MA : NB;
+    const std::vector<int32_t>& NQ = p_is_a ? NB : MA;
+    std::vector<int32_t> KP, KQ;   // K in P's / Q's order
+    for (auto x : P.dense)
+      if (std::find(K.begin(), K.end(), x) != K.end()) KP.push_back(x);
+    for (auto x : Q.dense)
+      if (std::find(K.begin(), K.end(), x) != K.end()) KQ.push_back(x);
+    auto cat = [](const std::vector<int32_t>& x, const std::vector<int32_t>& y) {
+      std::vector<int32_t> r = x;
+      r.insert(r.end(), y.begin(), y.end());
+      return r;
+    };
+    int p_form = -1, q_form = -1;  // 0 = [free][K], 1 = [K][free] (P), Q: 0 = [K][N], 1 = [N][K]
+    if (P.dense == cat(MP, KP)) p_form = 0;
+    else if (P.dense == cat(KP, MP)) p_form = 1;
+    if (Q.dense == cat(KQ, NQ)) q_form = 0;
+    else if (Q.dense == cat(NQ, KQ)) q_form = 1;
+    std::vector<int32_t> Kord;
+    int pbuf = P.buf, qbuf = Q.buf;
+    std::vector<int> temps;
+    if (p_form >= 0 && q_form >= 0 && KP == KQ) {
+      Kord = KP;
+    } else if (p_form >= 0 && (q_form < 0 || P.elems() >= Q.elems())) {
+      Kord = KP;
+      q_form = 0;
+      qbuf = emit_permute(Q, cat(Kord, NQ), inv, -1);
+      temps.push_back(qbuf);
+    } else if (q_form >= 0) {
+      Kord = KQ;
+      p_form = 0;
+      pbuf = emit_permute(P, cat(MP, Kord), inv, -1);
+      temps.push_back(pbuf);
+    } else {
+      Kord = KP;
+      p_form = 0;
+      q_form = 0;
+      pbuf = emit_permute(P, cat(MP, Kord), inv, -1);
+      qbuf = emit_permute(Q, cat(Kord, NQ), inv, -1);
+      temps.push_back(pbuf);
+      temps.push_back(qbuf);
+    }
+    Launch L;
+    L.kind = K_GEMM;
+    L.inv = inv;
+    GemmArgs& g = L.gm;
+    int64_t M = int64_t(1) << MP.size(), N = int64_t(1) << NQ.size(), Kd = int64_t(1) << nk;
+    int64_t rows = C.rows();
+    L.g0 = gather(P, C);
+    L.g1 = gather(Q, C);
+    g.a_rows = P.rows();
+    g.b_rows = Q.rows();
+    g.a_row_stride = int64_t(1) << P.dense.size();
+    g.b_row_stride = int64_t(1) << Q.dense.size();
+    g.trans_a = p_form;
+    g.trans_b = q_form;
+    // rows folded into M when Q is shared by every row and P is row-aligned [r][M][K]
+    if (rows > 1 && Q.rows() == 1 && P.q == C.q && p_form == 0) {
+      M *= rows;
+      rows = 1;
+      g.a_rows = 1;
+      g.a_row_stride = 0;
+    }
+    g.M = M;
+    g.N = N;
+    g.K = Kd;
+    g.rows = rows;
+    g.c_row_stride = M * N;
+    g.config = (N <= 16) ? 1 : ((M <= 64 || N <= 32) ? 2 : 0);
+    const int64_t BM = g.config == 2 ? 64 : 128, BN = g.config == 0 ? 64 : (g.config == 1 ? 16 : 32);
+    const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN) * rows;
+    g.k_splits = 1;
+    g.k_chunk = Kd;
+    if (tiles < 512 && Kd >= 512) {
+      int64_t s = 1;
+      while (tiles * s * 2 <= 2048 && Kd / (s * 2) >= 256) s *= 2;
+      g.k_splits = int(s);
+      g.k_chunk = Kd / s;
+    }
+    C.dense = cat(MP, NQ);
+    C.buf = new_buf(uint64_t(C.elems()) * 8);
+    L.b_in0 = pbuf;
+    L.b_in1 = qbuf;
+    L.b_out = C.buf;
+    L.bufs = {pbuf, qbuf, C.buf};
+    int part = -1;
+    if (g.k_splits > 1) {
+      part = new_buf(uint64_t(g.k_splits) * uint64_t(rows) * uint64_t(M) * uint64_t(N) * 8);
+      L.b_tmp = part;
+      L.bufs.push_back(part);
+    }
+    L.info = tnc_step_info{K_GEMM, inv, rows, M, N, Kd, 8.0 * macs,
+                           8.0 * double(P.elems() + Q.elems() + C.elems())};
+    for (int tb : temps) L.bufs.push_back(tb);
+    account(L);
+    list(inv).push_back(L);
+    if (part >= 0) {
+      Launch R;
+      R.kind = K_REDUCE;
+      R.inv = inv;
+      R.rd.elems = rows * M * N;
+      R.rd.splits = g.k_splits;
+      R.b_in0 = part;
+      R.b_out = C.buf;
+      R.bufs = {part, C.buf};
+      R.info = tnc_step_info{K_REDUCE, inv, rows, M, N, 0, 0.0,
+                             8.0 * double(g.k_splits + 1) * double(rows * M * N)};
+      account(R);
+      list(inv).push_back(R);
+    }
+    return C;
+  }
+
+  void run() {
+    leaves();
+    for (auto& pr : net.path) {
+      TState& A = T[pr.first];
+      TState& B = T[pr.second];
+      TState C = step(A, B);
+      B.alive = false;
+      A = std::move(C);
+      plan.n_steps++;
+    }
+    int fin = -1;
+    for (size_t t = 0; t < T.size(); ++t)
+      if (T[t].alive) fin = int(t);
+    TState& F = T[fin];
+    // final tensor: rows = groups, dense = open legs
+    std::set<int32_t> want;
+    for (auto q : net.open) want.insert(net.out_label[q]);
+    std::set<int32_t> have(F.dense.begin(), F.dense.end());
+    if (want != have) fail(TNC_E_INVALID, "the contracted network does not end on the open legs");
+    std::vector<int32_t> row_of(net.closed.size());
+    for (size_t g = 0; g < net.closed.size(); ++g) {
+      const uint64_t k = net.closed[g] & F.q;
+      auto it = std::lower_bound(F.keys.begin(), F.keys.end(), k);
+      row_of[g] = int32_t(it - F.keys.begin());
+    }
+    plan.row_of_off = add_const(row_of.data(), row_of.size() * 4);
+    SliceSumArgs& s = plan.ss;
+    s.L = int64_t(net.closed.size());
+    s.n_open = int(net.open.size());
+    s.f_row_stride = int64_t(1) << F.dense.size();
+    for (int t = 0; t < s.n_open; ++t)
+      s.open_stride[t] = int64_t(1) << pos_of(F.dense, net.out_label[net.open[t]]);
+    plan.final_buf = F.buf;
+    Launch L;
+    L.kind = K_SUM;
+    L.inv = false;
+    L.b_in0 = F.buf;
+    L.bufs = {F.buf};
+    L.info = tnc_step_info{K_SUM, 0, s.L, int64_t(1) << s.n_open, 0, 0, 0.0,
+                           double(s.L << s.n_open) * (8.0 + 32.0)};
+    plan.dep.push_back(L);
+    // constants for slices, sampling
+    plan.slice_ids_off = add_const(net.slice_ids.data(), net.slice_ids.size() * 8);
+    plan.closed_off = add_const(net.closed.data(), net.closed.size() * 8);
+    std::vector<int32_t> open_pad = net.open;
+    open_pad.push_back(0);
+    plan.open_off = add_const(open_pad.data(), open_pad.size() * 4);
+    if (!plan.sl_table.empty()) {
+      plan.sl_prefix_off = add_const(plan.sl_prefix.data(), plan.sl_prefix.size() * 8);
+      // table is written after packing (destination offsets); reserve it now
+      plan.sl_table_off = add_const(plan.sl_table.data(), plan.sl_table.size() * sizeof(SliceLeafEntry));
+    }
+    plan.b_norm = new_buf(uint64_t(plan.norm_parts + 1) * 8);
+    const int64_t l = int64_t(1) << net.open.size();
+    plan.b_cum = new_buf(uint64_t(l) * 8);
+    plan.sample_chunk = std::max<int64_t>(plan.L, 65536);
+    plan.b_samples = new_buf(uint64_t(plan.sample_chunk) * 8);
+  }
+};
+
+void pack(tnc_plan_s& plan) {
+  // lifetimes: phase-1 launches occupy [0, P), phase-2 launches [P, P + D)
+  const int P = int(plan.inv.size()), D = int(plan.dep.size());
+  const int END = P + D;
+  auto touch = [&](int b, int t) {
+    Buf& x = plan.bufs[b];
+    x.t0 = std::min(x.t0, t);
+    x.t1 = std::max(x.t1, t);
+  };
+  for (int i = 0; i < P; ++i)
+    for (int b : plan.inv[i].bufs) touch(b, i);
+  for (int i = 0; i < D; ++i)
+    for (int b : plan.dep[i].bufs) touch(b, P + i);
+  for (auto& b : plan.bufs) {
+    if (b.is_const) continue;
+    if (b.t1 < 0) { b.t0 = 0; b.t1 = END; }          // scratch kept for the whole call
+    if (b.t0 < P && b.t1 >= P) b.to_end = true;       // invariant result read by slices
+    if (b.to_end) b.t1 = END;
+  }
+  plan.consts_bytes = align_up(plan.consts.size());
+  std::vector<int> order;
+  for (size_t i = 0; i < plan.bufs.size(); ++i)
+    if (!plan.bufs[i].is_const) order.push_back(int(i));
+  std::sort(order.begin(), order.end(), [&](int a, int b) {
+    return plan.bufs[a].bytes != plan.bufs[b].bytes ? plan.bufs[a].bytes > plan.bufs[b].bytes : a < b;
+  });
+  std::vector<int> placed;
+  uint64_t top = 0;
+  for (int id : order) {
+    Buf& b = plan.bufs[id];
+    std::vector<std::pair<uint64_t, uint64_t>> busy;
+    for (int o : placed) {
+      const Buf& c = plan.bufs[o];
+      if (c.t1 < b.t0 || b.t1 < c.t0) continue;
+      busy.push_back({c.off, c.off + c.bytes});
+    }
+    std::sort(busy.begin(), busy.end());
+    uint64_t at = 0;
+    for (auto& iv : busy) {
+      if (at + b.bytes <= iv.first) break;
+      at = std::max(at, iv.second);
+    }
+    b.off = at;
+    top = std::max(top, at + b.bytes);
+    placed.push_back(id);
+  }
+  for (int id : order) plan.bufs[id].off += plan.consts_bytes;
+  plan.ws_bytes = plan.consts_bytes + align_up(top);
+  // the slice-leaf table holds workspace destinations
+  for (auto& e : plan.sl_table) e.dst_off = int64_t(plan.bufs[e.dst_off].off / 8);
+  if (!plan.sl_table.empty())
+    std::memcpy(plan.consts.data() + plan.sl_table_off, plan.sl_table.data(),
+                plan.sl_table.size() * sizeof(SliceLeafEntry));
+}
+
+// ------------------------------------------------------------------------------------
+// execution
+struct Exec {
+  tnc_plan_s& p;
+  uint8_t* ws;
+  hipStream_t s;
+  float2* ptr(int b) const { return reinterpret_cast<float2*>(ws + p.bufs[b].off); }
+  const int32_t* gat(int64_t off) const {
+    return off < 0 ? nullptr : reinterpret_cast<const int32_t*>(ws + off);
+  }
+
+  hipEvent_t ev() {
+    if (p.ev_used == p.ev_pool.size()) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      p.ev_pool.push_back(e);
+    }
+    return p.ev_pool[p.ev_used++];
+  }
+
+  void launch(const Launch& L, int64_t slice_index, double* amps, bool timed) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+      e0 = ev();
+      e1 = ev();
+      HIPCHK(hipEventRecord(e0, s));
+    }
+    hipError_t err = hipSuccess;
+    switch (L.kind) {
+      case K_PERMUTE: {
+        PermuteArgs a = L.perm;
+        a.in = ptr(L.b_in0);
+        a.out = ptr(L.b_out);
+        err = launch_permute(a, s);
+        break;
+      }
+      case K_STREAM: {
+        StreamArgs a = L.st;
+        a.X = ptr(L.b_in0);
+        a.S = ptr(L.b_in1);
+        a.C = ptr(L.b_out);
+        a.gx = gat(L.g0);
+        a.gs = gat(L.g1);
+        err = launch_stream(a, s);
+        break;
+      }
+      case K_GEMM: {
+        GemmArgs a = L.gm;
+        a.A = ptr(L.b_in0);
+        a.B = ptr(L.b_in1);
+        a.C = ptr(L.b_out);
+        a.ga = gat(L.g0);
+        a.gb = gat(L.g1);
+        a.partial = L.b_tmp >= 0 ? ptr(L.b_tmp) : nullptr;
+        err = launch_gemm(a, s);
+        break;
+      }
+      case K_REDUCE: {
+        ReduceArgs a = L.rd;
+        a.partial = ptr(L.b_in0);
+        a.C = ptr(L.b_out);
+        err = launch_reduce(a, s);
+        break;
+      }
+      case K_LEAVES: {
+        SliceLeafArgs a{};
+        a.table = reinterpret_cast<const SliceLeafEntry*>(ws + p.sl_table_off);
+        a.prefix = reinterpret_cast<const int64_t*>(ws + p.sl_prefix_off);
+        a.n_entries = int(p.sl_table.size());
+        a.consts = reinterpret_cast<const float2*>(ws);
+        a.ws = reinterpret_cast<float2*>(ws);
+        a.slice_ids = reinterpret_cast<const uint64_t*>(ws + p.slice_ids_off);
+        a.slice_index = slice_index;
+        err = launch_slice_leaves(a, p.sl_total, s);
+        break;
+      }
+      case K_SUM: {
+        SliceSumArgs a = p.ss;
+        a.F = ptr(L.b_in0);
+        a.amps = amps;
+        a.row_of = reinterpret_cast<const int32_t*>(ws + p.row_of_off);
+        a.overwrite = 0;
+        err = launch_slice_sum(a, s);
+        break;
+      }
+    }
+    if (err != hipSuccess) fail(TNC_E_HIP, std::string("kernel launch: ") + hipGetErrorString(err));
+    if (timed) {
+      HIPCHK(hipEventRecord(e1, s));
+      p.pending.push_back(TimingRec{L.kind, L.info.bytes, L.info.flops, e0, e1});
+    }
+  }
+
+  void upload() {
+    if (p.uploaded_ws == ws) return;
+    HIPCHK(hipMemcpyAsync(ws, p.consts.data(), p.consts.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    p.uploaded_ws = ws;
+  }
+
+  void contract(double* amps, int64_t first, int64_t count, bool accumulate) {
+    upload();
+    const int64_t n_amp = p.L << p.n_open;
+    if (!accumulate) {
+      hipError_t e = launch_fill_zero(amps, 2 * n_amp, s);
+      if (e != hipSuccess) fail(TNC_E_HIP, hipGetErrorString(e));
+    }
+    if (count <= 0) return;
+    // with timing on, a bounded sample of slices is bracketed by events
+    int64_t stride = 1;
+    if (p.timing) {
+      const int64_t per = std::max<int64_t>(1, int64_t(p.dep.size()));
+      const int64_t n_timed = std::max<int64_t>(1, 4096 / per);
+      stride = std::max<int64_t>(1, count / n_timed);
+    }
+    for (auto& L : p.inv) launch(L, 0, amps, p.timing);
+    for (int64_t i = 0; i < count; ++i) {
+      const bool timed = p.timing && (i % stride == 0);
+      for (auto& L : p.dep) launch(L, first + i, amps, timed);
+    }
+  }
+};
+
+void harvest(tnc_plan_s& p) {
+  for (auto& r : p.pending) {
+    HIPCHK(hipEventSynchronize(r.e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, r.e0, r.e1));
+    p.t_ms[r.kind] += ms;
+    p.t_bytes[r.kind] += r.bytes;
+    p.t_flops[r.kind] += r.flops;
+    p.t_n[r.kind] += 1;
+  }
+  p.pending.clear();
+  p.ev_used = 0;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    HIPCHK(hipGetDevice(&prev));
+    if (prev != dev) HIPCHK(hipSetDevice(dev));
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------
+// C ABI
+extern "C" {
+
+const char* tnc_last_error(void) { return g_err.c_str(); }
+
+tnc_status tnc_net_create(int device, const tnc_network_desc* d, tnc_net* out) {
+  return guard([&] {
+    if (!d || !out) fail(TNC_E_INVALID, "null argument");
+    *out = nullptr;
+    if (d->n_qubits < 0 || d->n_qubits > 64) fail(TNC_E_INVALID, "n_qubits must be in [0, 64]");
+    if (d->n_tensors < 1) fail(TNC_E_INVALID, "a network needs at least one tensor");
+    if (!d->ranks || !d->labels || !d->data || (d->n_qubits > 0 && !d->out_label))
+      fail(TNC_E_INVALID, "null array in the network description");
+    auto* n = new tnc_net_s();
+    try {
+      n->device = device;
+      n->n_qubits = d->n_qubits;
+      int64_t lp = 0, dp = 0;
+      for (int t = 0; t < d->n_tensors; ++t) {
+        const int r = d->ranks[t];
+        if (r < 0 || r > kMaxRank) fail(TNC_E_INVALID, "tensor rank out of range [0, 40]");
+        std::vector<int32_t> lab(d->labels + lp, d->labels + lp + r);
+        for (auto x : lab) {
+          if (x < 0) fail(TNC_E_INVALID, "negative label");
+          n->holders[x].push_back(t);
+        }
+        std::set<int32_t> uniq(lab.begin(), lab.end());
+        if (int(uniq.size()) != r) fail(TNC_E_INVALID, "a tensor repeats a label");
+        const int64_t sz = int64_t(1) << r;
+        n->labels.push_back(lab);
+        n->data.emplace_back(d->data + dp, d->data + dp + 2 * sz);
+        lp += r;
+        dp += 2 * sz;
+      }
+      for (auto& kv : n->holders)
+        if (kv.second.size() > 2)
+          fail(TNC_E_INVALID, "label " + std::to_string(kv.first) + " is held by more than two tensors");
+      n->out_label.assign(d->out_label, d->out_label + d->n_qubits);
+      std::set<int32_t> outs;
+      for (auto x : n->out_label) {
+        auto it = n->holders.find(x);
+        if (it == n->holders.end() || it->second.size() != 1)
+          fail(TNC_E_INVALID, "output label " + std::to_string(x) + " must be held by exactly one tensor");
+        if (!outs.insert(x).second) fail(TNC_E_INVALID, "two qubits share an output label");
+      }
+      for (auto& kv : n->holders)
+        if (kv.second.size() == 1 && !outs.count(kv.first))
+          fail(TNC_E_INVALID, "label " + std::to_string(kv.first) + " is dangling (one holder, not an output)");
+      n->slice_ids = {0};
+      n->closed = {0};
+    } catch (...) {
+      delete n;
+      throw;
+    }
+    *out = n;
+  });
+}
+
+tnc_status tnc_net_set_path(tnc_net net, const int32_t* pairs, int32_t n, const int32_t* out_orders) {
+  return guard([&] {
+    if (!net) fail(TNC_E_NOT_FOUND, "null network");
+    if (out_orders) fail(TNC_E_UNSUPPORTED, "explicit result orders are not supported; pass NULL");
+    if (n < 0 || (n > 0 && !pairs)) fail(TNC_E_INVALID, "bad path array");
+    const int nt = int(net->labels.size());
+    std::vector<bool> alive(nt, true);
+    std::vector<std::pair<int, int>> path;
+    for (int s = 0; s < n; ++s) {
+      const int i = pairs[2 * s], j = pairs[2 * s + 1];
+      if (i < 0 || j < 0 || i >= nt || j >= nt || i == j)
+        fail(TNC_E_INVALID, "path step " + std::to_string(s) + " has an invalid pair");
+      if (!alive[i] || !alive[j])
+        fail(TNC_E_INVALID, "path step " + std::to_string(s) + " uses a retired tensor");
+      alive[j] = false;
+      path.push_back({i, j});
+    }
+    int left = 0;
+    for (bool a : alive) left += a;
+    if (left != 1) fail(TNC_E_INVALID, "the path leaves " + std::to_string(left) + " tensors (need 1)");
+    net->path = path;
+    net->has_path = true;
+  });
+}
+
+tnc_status tnc_net_set_slices(tnc_net net, const int32_t* sliced, int32_t k, const uint64_t* ids,
+                              int64_t n_ids) {
+  return guard([&] {
+    if (!net) fail(TNC_E_NOT_FOUND, "null network");
+    if (k < 0 || k > 63) fail(TNC_E_INVALID, "k must be in [0, 63]");
+    if (n_ids < 1 || !ids || (k > 0 && !sliced)) fail(TNC_E_INVALID, "bad slice arrays");
+    std::set<int32_t> outs(net->out_label.begin(), net->out_label.end()), seen;
+    for (int b = 0; b < k; ++b) {
+      auto it = net->holders.find(sliced[b]);
+      if (it == net->holders.end() || it->second.size() != 2 || outs.count(sliced[b]))
+        fail(TNC_E_INVALID, "sliced label " + std::to_string(sliced[b]) + " is not a bond");
+      if (!seen.insert(sliced[b]).second) fail(TNC_E_INVALID, "a label is sliced twice");
+    }
+    for (int64_t i = 0; i < n_ids; ++i)
+      if (k < 64 && (ids[i] >> k) != 0) fail(TNC_E_INVALID, "slice id out of range");
+    net->sliced.assign(sliced, sliced + k);
+    net->slice_ids.assign(ids, ids + n_ids);
+    net->has_slices = true;
+  });
+}
+
+tnc_status tnc_net_set_targets(tnc_net net, const int32_t* open, int32_t n_open,
+                               const uint64_t* closed, int64_t L) {
+  return guard([&] {
+    if (!net) fail(TNC_E_NOT_FOUND, "null network");
+    const int n = net->n_qubits;
+    if (n_open < 0 || n_open > n || (n_open > 0 && !open)) fail(TNC_E_INVALID, "bad open-qubit list");
+    if (n_open > 30) fail(TNC_E_UNSUPPORTED, "more than 30 open qubits");
+    if (L < 1 || !closed) fail(TNC_E_INVALID, "need at least one group");
+    std::set<int32_t> os;
+    uint64_t omask = 0;
+    for (int t = 0; t < n_open; ++t) {
+      if (open[t] < 0 || open[t] >= n) fail(TNC_E_INVALID, "open qubit out of range");
+      if (!os.insert(open[t]).second) fail(TNC_E_INVALID, "open qubit listed twice");
+      omask |= uint64_t(1) << (n - 1 - open[t]);
+    }
+    const uint64_t nmask = n == 64 ? ~uint64_t(0) : ((uint64_t(1) << n) - 1);
+    std::vector<uint64_t> c(closed, closed + L);
+    for (auto& x : c) x &= nmask & ~omask;
+    std::vector<uint64_t> s = c;
+    std::sort(s.begin(), s.end());
+    if (std::adjacent_find(s.begin(), s.end()) != s.end())
+      fail(TNC_E_INVALID, "two groups have the same closed bits");
+    net->open.assign(open, open + n_open);
+    net->closed = c;
+    net->has_targets = true;
+  });
+}
+
+tnc_status tnc_plan_create(tnc_net net, tnc_precision precision, int32_t max_batch, tnc_plan* out) {
+  return guard([&] {
+    if (!net || !out) fail(TNC_E_INVALID, "null argument");
+    *out = nullptr;
+    if (!net->has_path && net->labels.size() > 1) fail(TNC_E_INVALID, "no path set");
+    if (!net->has_targets) fail(TNC_E_INVALID, "no targets set");
+    if (precision != TNC_C64) fail(TNC_E_UNSUPPORTED, "only TNC_C64 is implemented");
+    if (max_batch < 1) fail(TNC_E_INVALID, "max_batch_slices must be >= 1");
+    auto* p = new tnc_plan_s();
+    try {
+      p->device = net->device;
+      p->n_qubits = net->n_qubits;
+      p->precision = precision;
+      p->L = int64_t(net->closed.size());
+      p->n_open = int(net->open.size());
+      p->open = net->open;
+      p->closed = net->closed;
+      p->slice_ids = net->slice_ids;
+      Compiler c(*net, *p);
+      c.run();
+      pack(*p);
+    } catch (...) {
+      delete p;
+      throw;
+    }
+    *out = p;
+  });
+}
+
+tnc_status tnc_plan_workspace_bytes(tnc_plan p, uint64_t* bytes) {
+  return guard([&] {
+    if (!p || !bytes) fail(TNC_E_INVALID, "null argument");
+    *bytes = p->ws_bytes;
+  });
+}
+
+tnc_status tnc_plan_stats(tnc_plan p, double* flops, double* bytes, int32_t* n_steps) {
+  return guard([&] {
+    if (!p) fail(TNC_E_INVALID, "null plan");
+    if (flops) *flops = p->flops_slice;
+    if (bytes) *bytes = p->bytes_slice;
+    if (n_steps) *n_steps = p->n_steps;
+  });
+}
+
+static void check_ws(tnc_plan p, void* ws, uint64_t bytes) {
+  if (!ws) fail(TNC_E_INVALID, "null workspace");
+  if (bytes < p->ws_bytes)
+    fail(TNC_E_OOM, "workspace of " + std::to_string(bytes) + " bytes < required " + std::to_string(p->ws_bytes));
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) fail(TNC_E_INVALID, "workspace must be 256-byte aligned");
+}
+
+tnc_status tnc_contract_range(tnc_plan p, void* ws, uint64_t ws_bytes, void* stream, double* amps,
+                              int64_t first, int64_t count, int32_t accumulate) {
+  return guard([&] {
+    if (!p || !amps) fail(TNC_E_INVALID, "null argument");
+    check_ws(p, ws, ws_bytes);
+    if (first < 0 || count < 0 || first + count > int64_t(p->slice_ids.size()))
+      fail(TNC_E_INVALID, "slice range outside the slice list");
+    DeviceGuard dg(p->device);
+    Exec e{*p, static_cast<uint8_t*>(ws), static_cast<hipStream_t>(stream)};
+    e.contract(amps, first, count, accumulate != 0);
+  });
+}
+
+tnc_status tnc_contract(tnc_plan p, void* ws, uint64_t ws_bytes, void* stream, double* amps,
+                        double* h_norm) {
+  return guard([&] {
+    if (!p || !amps) fail(TNC_E_INVALID, "null argument");
+    check_ws(p, ws, ws_bytes);
+    DeviceGuard dg(p->device);
+    Exec e{*p, static_cast<uint8_t*>(ws), static_cast<hipStream_t>(stream)};
+    e.contract(amps, 0, int64_t(p->slice_ids.size()), false);
+    if (h_norm) {
+      double* parts = reinterpret_cast<double*>(e.ws + p->bufs[p->b_norm].off);
+      hipError_t err = launch_norm(amps, p->L << p->n_open, parts, p->norm_parts,
+                                   parts + p->norm_parts, e.s);
+      if (err != hipSuccess) fail(TNC_E_HIP, hipGetErrorString(err));
+      HIPCHK(hipMemcpyAsync(h_norm, parts + p->norm_parts, 8, hipMemcpyDeviceToHost, e.s));
+      HIPCHK(hipStreamSynchronize(e.s));
+    }
+  });
+}
+
+tnc_status tnc_sample(tnc_plan p, void* ws, uint64_t ws_bytes, const double* amps, uint64_t seed,
+                      int64_t n_samples, uint64_t* h_bits, void* stream) {
+  return guard([&] {
+    if (!p || !amps || (n_samples > 0 && !h_bits)) fail(TNC_E_INVALID, "null argument");
+    check_ws(p, ws, ws_bytes);
+    if (n_samples < 0) fail(TNC_E_INVALID, "negative sample count");
+    if (p->L > 1 && n_samples != p->L)
+      fail(TNC_E_INVALID, "with several groups, n_samples must equal the number of groups");
+    DeviceGuard dg(p->device);
+    Exec e{*p, static_cast<uint8_t*>(ws), static_cast<hipStream_t>(stream)};
+    e.upload();
+    double* cum = reinterpret_cast<double*>(e.ws + p->bufs[p->b_cum].off);
+    uint64_t* dout = reinterpret_cast<uint64_t*>(e.ws + p->bufs[p->b_samples].off);
+    const uint64_t* closed = reinterpret_cast<const uint64_t*>(e.ws + p->closed_off);
+    const int32_t* openq = reinterpret_cast<const int32_t*>(e.ws + p->open_off);
+    if (p->L > 1) {
+      hipError_t err = launch_sample(amps, p->L, p->n_open, closed, openq, p->n_qubits, seed, p->L,
+                                     cum, dout, e.s);
+      if (err != hipSuccess) fail(TNC_E_HIP, hipGetErrorString(err));
+      HIPCHK(hipMemcpyAsync(h_bits, dout, uint64_t(p->L) * 8, hipMemcpyDeviceToHost, e.s));
+      HIPCHK(hipStreamSynchronize(e.s));
+      return;
+    }
+    // one group: draws j = 0..n-1 in chunks (the draw index keeps counting across chunks)
+    for (int64_t done = 0; done < n_samples; done += p->sample_chunk) {
+      const int64_t c = std::min(p->sample_chunk, n_samples - done);
+      // shift the counter: uniform j uses state seed + (j + 1) gamma
+      const uint64_t seed_c = seed + uint64_t(done) * 0x9E3779B97F4A7C15ull;
+      hipError_t err = launch_sample(amps, 1, p->n_open, closed, openq, p->n_qubits, seed_c, c, cum,
+                                     dout, e.s);
+      if (err != hipSuccess) fail(TNC_E_HIP, hipGetErrorString(err));
+      HIPCHK(hipMemcpyAsync(h_bits + done, dout, uint64_t(c) * 8, hipMemcpyDeviceToHost, e.s));
+      HIPCHK(hipStreamSynchronize(e.s));
+    }
+  });
+}
+
+tnc_status tnc_plan_destroy(tnc_plan p) {
+  return guard([&] { delete p; });
+}
+
+tnc_status tnc_net_destroy(tnc_net n) {
+  return guard([&] { delete n; });
+}
+
+tnc_status tnc_plan_n_launches(tnc_plan p, int32_t* n) {
+  return guard([&] {
+    if (!p || !n) fail(TNC_E_INVALID, "null argument");
+    *n = int32_t(p->inv.size() + p->dep.size());
+  });
+}
+
+tnc_status tnc_plan_launch_info(tnc_plan p, int32_t i, tnc_step_info* info) {
+  return guard([&] {
+    if (!p || !info) fail(TNC_E_INVALID, "null argument");
+    const int P = int(p->inv.size());
+    if (i < 0 || i >= P + int(p->dep.size())) fail(TNC_E_INVALID, "launch index out of range");
+    const Launch& L = i < P ? p->inv[i] : p->dep[i - P];
+    *info = L.info;
+    info->kind = L.kind;
+    info->invariant = L.inv ? 1 : 0;
+  });
+}
+
+tnc_status tnc_plan_set_timing(tnc_plan p, int32_t enable) {
+  return guard([&] {
+    if (!p) fail(TNC_E_INVALID, "null plan");
+    p->timing = enable != 0;
+  });
+}
+
+tnc_status tnc_plan_timing(tnc_plan p, double* ms, double* bytes, double* flops, int64_t* launches,
+                           int32_t reset) {
+  return guard([&] {
+    if (!p) fail(TNC_E_INVALID, "null plan");
+    DeviceGuard dg(p->device);
+    harvest(*p);
+    for (int k = 0; k < kKinds; ++k) {
+      if (ms) ms[k] = p->t_ms[k];
+      if (bytes) bytes[k] = p->t_bytes[k];
+      if (flops) flops[k] = p->t_flops[k];
+      if (launches) launches[k] = p->t_n[k];
+    }
+    if (reset) {
+      for (int k = 0; k < kKinds; ++k) p->t_ms[k] = p->t_bytes[k] = p->t_flops[k] = 0, p->t_n[k] = 0;
+    }
+  });
+}
+
+}  // extern "C"

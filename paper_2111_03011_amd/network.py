@@ -1,0 +1,175 @@
+"""Circuit -> simplified tensor network (host side of the library).
+
+Paper, "Method": single-qubit gates are matrices, fSim gates (Eq. (1)) four-way
+tensors, the initial product state is a set of vectors and the final state a boundary.
+Results paragraph: the network is simplified by contracting order-one and order-two
+tensors into their neighbours before planning.
+
+The construction here never materialises a separate tensor for a single-qubit gate:
+  * gates acting on a qubit before its first fSim are folded into that qubit's initial
+    vector, which is then folded into the first fSim's input leg;
+  * gates between two fSims on a qubit are folded forward into the later fSim's input;
+  * gates after a qubit's last fSim are folded backward into that fSim's output leg,
+    which becomes the qubit's output leg.
+Afterwards any tensor of rank <= 2 (for example a first-cycle fSim whose two inputs were
+both initial vectors) is contracted into a neighbour, repeatedly.
+
+Labels are non-negative ints.  The output of the j-th two-qubit gate on qubit q that
+feeds a later two-qubit gate on q is the bond named (q, j); `bond_label[(q, j)]` is its
+label while it survives simplification.  `out_label[q]` is qubit q's output leg.
+Tensor data are complex128, row-major in label order (first label slowest).
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_S2 = 1.0 / math.sqrt(2.0)
+# exp(-i pi/4 P) for P = X, Y, W = (X+Y)/sqrt2, written out entry by entry.
+_ONEQ = {
+    "sqrt_x": np.array([[_S2, -1j * _S2], [-1j * _S2, _S2]], dtype=np.complex128),
+    "sqrt_y": np.array([[_S2, -_S2], [_S2, _S2]], dtype=np.complex128),
+    "sqrt_w": np.array([[_S2, -_S2 * complex(_S2, _S2)],
+                        [_S2 * complex(_S2, -_S2), _S2]], dtype=np.complex128),
+}
+
+
+def _fsim4(theta: float, phi: float) -> np.ndarray:
+    """fSim as t[out_a, out_b, in_a, in_b]; the 4x4 of Eq. (1) is symmetric."""
+    t = np.zeros((2, 2, 2, 2), dtype=np.complex128)
+    t[0, 0, 0, 0] = 1.0
+    t[0, 1, 0, 1] = math.cos(theta)
+    t[1, 0, 1, 0] = math.cos(theta)
+    t[0, 1, 1, 0] = -1j * math.sin(theta)
+    t[1, 0, 0, 1] = -1j * math.sin(theta)
+    t[1, 1, 1, 1] = complex(math.cos(phi), -math.sin(phi))
+    return t
+
+
+@dataclass
+class TensorNetwork:
+    n_qubits: int
+    tensors: list = field(default_factory=list)      # complex128 arrays
+    labels: list = field(default_factory=list)       # list[list[int]]
+    out_label: list = field(default_factory=list)    # [n_qubits]
+    bond_label: dict = field(default_factory=dict)   # (q, j) -> label
+
+    def ranks(self):
+        return [len(l) for l in self.labels]
+
+    def flat_labels(self):
+        return [x for l in self.labels for x in l]
+
+    def flat_data(self):
+        parts = [np.ascontiguousarray(t, dtype=np.complex128).reshape(-1) for t in self.tensors]
+        return np.concatenate(parts) if parts else np.zeros(0, np.complex128)
+
+
+def _apply_matrix(t: np.ndarray, labels: list, lab: int, m: np.ndarray, side: str) -> np.ndarray:
+    """side 'in': t[..., a, ...] <- sum_b t[..., b, ...] m[b, a]   (m acts before t)
+       side 'out': t[..., a, ...] <- sum_b m[a, b] t[..., b, ...]  (m acts after t)"""
+    ax = labels.index(lab)
+    mm = m if side == "in" else m.T
+    out = np.tensordot(t, mm, axes=([ax], [0]))
+    return np.moveaxis(out, -1, ax)
+
+
+def circuit_network(circuit: dict, simplify: bool = True) -> TensorNetwork:
+    n = circuit["n_qubits"]
+    g = _fsim4(circuit["fsim"]["theta"], circuit["fsim"]["phi"])
+    next_label = [0]
+
+    def new_label():
+        next_label[0] += 1
+        return next_label[0] - 1
+
+    tensors, labels = [], []
+    head = [np.array([1.0, 0.0], dtype=np.complex128) for _ in range(n)]  # state before 1st fSim
+    pending = [np.eye(2, dtype=np.complex128) for _ in range(n)]          # 1q gates since last fSim
+    last = [None] * n          # (tensor index, output label) of the last fSim on q
+    n2q = [0] * n
+    bond_of = {}               # label -> (q, j)
+    for layer in circuit["layers"]:
+        for q, name in enumerate(layer["oneq"]):
+            u = _ONEQ[name]
+            if last[q] is None:
+                head[q] = u @ head[q]
+            else:
+                pending[q] = u @ pending[q]
+        for qa, qb in layer["couplers"]:
+            t = g.copy()
+            oa, ob = new_label(), new_label()
+            labs = [oa, ob, -1, -2]
+            # fold the inputs: initial vectors or the pending gates of each wire
+            for q, slot in ((qa, -1), (qb, -2)):
+                if last[q] is None:
+                    ax = labs.index(slot)
+                    t = np.tensordot(t, head[q], axes=([ax], [0]))
+                    labs.remove(slot)
+                else:
+                    prev_out = last[q][1]
+                    t = _apply_matrix(t, labs, slot, pending[q], "in")
+                    labs[labs.index(slot)] = prev_out
+                    pending[q] = np.eye(2, dtype=np.complex128)
+            tensors.append(t)
+            labels.append(labs)
+            idx = len(tensors) - 1
+            for q, o in ((qa, oa), (qb, ob)):
+                bond_of[o] = (q, n2q[q])
+                n2q[q] += 1
+                last[q] = (idx, o)
+    out_label = [None] * n
+    for q in range(n):
+        if last[q] is None:
+            o = new_label()
+            tensors.append(head[q].copy())
+            labels.append([o])
+            out_label[q] = o
+        else:
+            idx, o = last[q]
+            tensors[idx] = _apply_matrix(tensors[idx], labels[idx], o, pending[q], "out")
+            out_label[q] = o
+            bond_of.pop(o, None)          # last output of a qubit is its leg, not a bond
+    net = TensorNetwork(n_qubits=n, tensors=tensors, labels=labels, out_label=out_label,
+                        bond_label={v: k for k, v in bond_of.items()})
+    if simplify:
+        simplify_low_rank(net)
+    return net
+
+
+def simplify_low_rank(net: TensorNetwork) -> None:
+    """Contract every tensor of rank <= 2 into a neighbour (one sharing a label),
+    repeatedly; the neighbour's rank never grows."""
+    changed = True
+    while changed:
+        changed = False
+        holders = {}
+        for i, l in enumerate(net.labels):
+            for x in l or ():
+                holders.setdefault(x, []).append(i)
+        for i, l in enumerate(net.labels):
+            if l is None or len(l) > 2:
+                continue
+            nbrs = sorted({j for x in l for j in holders[x] if j != i and net.labels[j] is not None})
+            if not nbrs:
+                continue
+            j = min(nbrs, key=lambda k: (len(net.labels[k]), k))
+            shared = [x for x in l if x in net.labels[j]]
+            ai = [l.index(x) for x in shared]
+            aj = [net.labels[j].index(x) for x in shared]
+            res = np.tensordot(net.tensors[j], net.tensors[i], axes=(aj, ai))
+            new = [x for x in net.labels[j] if x not in shared] + [x for x in l if x not in shared]
+            net.tensors[j], net.labels[j] = res, new
+            net.tensors[i], net.labels[i] = None, None
+            for x in shared:
+                for q_j, lab in list(net.bond_label.items()):
+                    if lab == x:
+                        del net.bond_label[q_j]
+            changed = True
+            break
+    keep = [i for i, l in enumerate(net.labels) if l is not None]
+    net.tensors = [net.tensors[i] for i in keep]
+    net.labels = [list(net.labels[i]) for i in keep]

@@ -1,0 +1,347 @@
+"""Contraction planning: path, sliced bonds and cost (host side of the library).
+
+Paper, "Method" and Appendix B.2: the network is contracted pairwise along an order
+found by a complexity-greedy search; slicing fixes chosen bonds so that the largest
+intermediate fits the device, and every fixed assignment (a slice) is an independent
+contraction whose results are summed.  Appendix A: tensors that carry final-state
+qubits only keep the configurations that some requested bitstring needs.
+
+Cost model.  A tensor carries dense labels (bond dimension 2 each) and a set Q of closed
+final qubits.  Its row count is the number of distinct restrictions of the requested
+closed parts to Q (1 when Q is empty), so its size in elements is rows(Q) * 2^|dense|.
+Contracting A and B costs rows(Q_A | Q_B) * 2^|dense_A | dense_B| complex multiply-adds,
+the paper's time complexity T_c (Table I); flops are 8 T_c.
+
+Search.  Greedy: repeatedly contract the pair of tensors sharing a label that minimises
+size(C) - size(A) - size(B); the randomised variant adds Gumbel noise scaled by a
+temperature.  Slicing: bonds are added one at a time, each time the one that lowers the
+largest intermediate while raising the total cost least, until the size bound (and,
+when asked, an exact count) is met; the path is then searched again on the sliced
+network.  Steps that touch no sliced leaf are the same in every slice; the objective
+counts them once.
+
+Path format (Appendix E): pairs (i, j); the result is stored at position i.
+"""
+
+from __future__ import annotations
+
+import heapq
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+def _popcount(x: int) -> int:
+    return bin(x).count("1")
+
+
+class RowCounter:
+    """rows(Q): number of distinct closed-bit restrictions to the qubit mask Q."""
+
+    def __init__(self, n_qubits: int, closed_bits):
+        self.n = n_qubits
+        self.bits = np.asarray(closed_bits, dtype=np.uint64)
+        self.cache = {0: 1}
+
+    def qmask(self, qubits) -> int:
+        m = 0
+        for q in qubits:
+            m |= 1 << (self.n - 1 - q)
+        return m
+
+    def __call__(self, mask: int) -> int:
+        r = self.cache.get(mask)
+        if r is None:
+            if self.bits.size <= 1:
+                r = 1
+            else:
+                r = int(np.unique(self.bits & np.uint64(mask)).size)
+            self.cache[mask] = r
+        return r
+
+
+@dataclass
+class Problem:
+    """Labels as bitsets; closed output legs turned into row masks; sliced labels dropped."""
+    dense: list            # per leaf: int bitset of dense label ids
+    qmask: list            # per leaf: int bit mask (bitstring positions) of closed qubits
+    rows: RowCounter
+    label_ids: list        # bit position -> original label
+
+    def size(self, dense: int, q: int) -> int:
+        return self.rows(q) << _popcount(dense)
+
+
+def make_problem(labels, out_label, n_qubits, open_qubits, closed_bits, sliced=()) -> Problem:
+    all_labels = sorted({x for l in labels for x in l})
+    pos = {x: i for i, x in enumerate(all_labels)}
+    open_set = set(int(q) for q in open_qubits)
+    closed_leg = {out_label[q]: q for q in range(n_qubits) if q not in open_set}
+    rows = RowCounter(n_qubits, closed_bits)
+    sl = set(sliced)
+    dense, qm = [], []
+    for l in labels:
+        d, m = 0, 0
+        for x in l:
+            if x in closed_leg:
+                m |= 1 << (n_qubits - 1 - closed_leg[x])
+            elif x not in sl:
+                d |= 1 << pos[x]
+        dense.append(d)
+        qm.append(m)
+    return Problem(dense=dense, qmask=qm, rows=rows, label_ids=all_labels)
+
+
+@dataclass
+class PathCost:
+    flops_per_slice: float = 0.0     # 8 T_c of slice-dependent steps
+    flops_invariant: float = 0.0     # 8 T_c of steps shared by all slices
+    peak_log2: float = 0.0
+    steps: list = field(default_factory=list)   # (i, j, rows, log2 dense A, B, C, macs, dep)
+
+    def total(self, n_slices: int) -> float:
+        return self.flops_invariant + n_slices * self.flops_per_slice
+
+
+def greedy_path(prob: Problem, temperature: float = 0.0, seed: int = 0):
+    """Pairs (i, j) contracting every connected component; leftovers joined at the end."""
+    rng = np.random.default_rng(seed)
+    n = len(prob.dense)
+    dense = list(prob.dense)
+    qm = list(prob.qmask)
+    alive = [True] * n
+    holders = {}
+    for i, d in enumerate(dense):
+        x = d
+        while x:
+            b = x & -x
+            holders.setdefault(b, set()).add(i)
+            x ^= b
+    # closed-qubit rows also link tensors (they must end in the same result)
+    heap = []
+    version = [0] * n
+
+    def score(i, j):
+        c = prob.size(dense[i] ^ dense[j], qm[i] | qm[j])
+        s = c - prob.size(dense[i], qm[i]) - prob.size(dense[j], qm[j])
+        if temperature > 0:
+            g = -math.log(-math.log(rng.random() + 1e-300) + 1e-300)
+            s = s - temperature * abs(s + 1) * g
+        return s
+
+    def push(i, j):
+        if i > j:
+            i, j = j, i
+        heapq.heappush(heap, (score(i, j), i, j, version[i], version[j]))
+
+    for b, hs in holders.items():
+        hs = sorted(hs)
+        if len(hs) == 2:
+            push(hs[0], hs[1])
+    path = []
+    while heap:
+        s, i, j, vi, vj = heapq.heappop(heap)
+        if not (alive[i] and alive[j]) or vi != version[i] or vj != version[j]:
+            continue
+        shared = dense[i] & dense[j]
+        new = dense[i] ^ dense[j]
+        # move j's non-shared labels to i
+        x = dense[j]
+        while x:
+            b = x & -x
+            holders[b].discard(j)
+            if not (b & shared):
+                holders[b].add(i)
+            x ^= b
+        x = shared
+        while x:
+            b = x & -x
+            holders[b].discard(i)
+            x ^= b
+        dense[i], qm[i] = new, qm[i] | qm[j]
+        alive[j] = False
+        version[i] += 1
+        path.append((i, j))
+        nbrs = set()
+        x = new
+        while x:
+            b = x & -x
+            nbrs |= holders[b]
+            x ^= b
+        nbrs.discard(i)
+        for k in nbrs:
+            if alive[k]:
+                push(i, k)
+    rest = [k for k in range(n) if alive[k]]
+    # join what is left (disconnected pieces, row-only tensors): smallest first
+    rest.sort(key=lambda k: prob.size(dense[k], qm[k]))
+    while len(rest) > 1:
+        i, j = rest[0], rest[1]
+        dense[i] ^= dense[j]
+        qm[i] |= qm[j]
+        path.append((i, j))
+        rest = [i] + rest[2:]
+        rest.sort(key=lambda k: prob.size(dense[k], qm[k]))
+    return path
+
+
+def path_cost(prob: Problem, path, sliced_leaves=None) -> PathCost:
+    """Cost of a path; `sliced_leaves` = leaf indices holding a sliced label (the steps
+    above them differ between slices)."""
+    dense = list(prob.dense)
+    qm = list(prob.qmask)
+    dep = [bool(sliced_leaves and k in sliced_leaves) for k in range(len(dense))]
+    out = PathCost()
+    peak = max((prob.size(d, q) for d, q in zip(dense, qm)), default=1)
+    for i, j in path:
+        union = dense[i] | dense[j]
+        qc = qm[i] | qm[j]
+        rows = prob.rows(qc)
+        macs = float(rows) * float(1 << _popcount(union))
+        d = dep[i] or dep[j]
+        if d:
+            out.flops_per_slice += 8.0 * macs
+        else:
+            out.flops_invariant += 8.0 * macs
+        out.steps.append((i, j, rows, _popcount(dense[i]), _popcount(dense[j]),
+                          _popcount(dense[i] ^ dense[j]), macs, d))
+        dense[i] ^= dense[j]
+        qm[i] = qc
+        dep[i] = d
+        peak = max(peak, prob.size(dense[i], qc))
+    out.peak_log2 = math.log2(peak)
+    return out
+
+
+def _intermediates(prob: Problem, path):
+    """(dense bitset, qmask) of every intermediate, leaves included."""
+    dense = list(prob.dense)
+    qm = list(prob.qmask)
+    items = list(zip(dense, qm))
+    for i, j in path:
+        dense[i] ^= dense[j]
+        qm[i] |= qm[j]
+        items.append((dense[i], qm[i]))
+    return items
+
+
+def _step_operands(prob: Problem, path):
+    """Per step: (dense A | dense B, q mask of C) -- what decides its cost."""
+    dense = list(prob.dense)
+    qm = list(prob.qmask)
+    out = []
+    for i, j in path:
+        out.append((dense[i] | dense[j], qm[i] | qm[j], dense[i] ^ dense[j]))
+        dense[i] ^= dense[j]
+        qm[i] |= qm[j]
+    return out
+
+
+def choose_slices(prob: Problem, path, max_log2: float, exact: int | None = None,
+                  forbidden: int = 0):
+    """Bond bits to slice along a fixed path (greedy): returns a bitset of label bits."""
+    ops = _step_operands(prob, path)
+    leaves = list(zip(prob.dense, prob.qmask))
+    chosen = 0
+    # candidates: labels shared by two leaves (bonds); closed legs are never dense
+    counts = {}
+    for d in prob.dense:
+        x = d
+        while x:
+            b = x & -x
+            counts[b] = counts.get(b, 0) + 1
+            x ^= b
+    cands = [b for b, c in counts.items() if c == 2 and not (b & forbidden)]
+
+    def peak_and_cost(mask):
+        peak = 0.0
+        for d, q in leaves:
+            peak = max(peak, math.log2(prob.rows(q)) + _popcount(d & ~mask))
+        cost = 0.0
+        for union, q, out in ops:
+            peak = max(peak, math.log2(prob.rows(q)) + _popcount(out & ~mask))
+            cost += prob.rows(q) * float(1 << _popcount(union & ~mask))
+        return peak, cost * (1 << _popcount(mask))
+
+    cur_peak, _ = peak_and_cost(0)
+    while True:
+        k = _popcount(chosen)
+        need_more = cur_peak > max_log2 + 1e-9 or (exact is not None and k < exact)
+        if not need_more or (exact is not None and k >= exact):
+            break
+        best = None
+        for b in cands:
+            if b & chosen:
+                continue
+            pk, cost = peak_and_cost(chosen | b)
+            key = (max(pk, max_log2) if cur_peak > max_log2 else 0.0, cost, pk)
+            if best is None or key < best[0]:
+                best = (key, b, pk)
+        if best is None:
+            break
+        chosen |= best[1]
+        cur_peak = best[2]
+    return chosen, cur_peak
+
+
+@dataclass
+class Plan:
+    path: list
+    sliced_labels: list
+    cost: PathCost
+    n_slices: int
+
+    @property
+    def total_flops(self) -> float:
+        return self.cost.total(self.n_slices)
+
+
+def find_plan(net, open_qubits, closed_bits, max_log2: float = 26.0,
+              n_sliced: int | None = None, trials: int = 16, seed: int = 0,
+              temperature: float = 0.3, rounds: int = 2) -> Plan:
+    """Random-greedy search of (path, sliced bonds) under the size bound.
+
+    n_sliced=None slices as few bonds as the bound needs; an int asks for exactly that
+    many.  Returns the plan with the lowest total flop count over the slices (steps
+    shared by all slices counted once)."""
+    n = net.n_qubits
+    base = make_problem(net.labels, net.out_label, n, open_qubits, closed_bits)
+    bond_bits = 0
+    pos = {x: i for i, x in enumerate(base.label_ids)}
+    bond_labels = set(net.bond_label.values())
+    for x in base.label_ids:
+        if x in bond_labels:
+            bond_bits |= 1 << pos[x]
+    forbidden = ((1 << len(base.label_ids)) - 1) & ~bond_bits
+    best = None
+    for t in range(trials):
+        temp = 0.0 if t == 0 else temperature
+        path = greedy_path(base, temperature=temp, seed=seed + 7919 * t)
+        sl = 0
+        for _ in range(rounds):
+            need_exact = n_sliced
+            sl, pk = choose_slices(base, path, max_log2, exact=need_exact, forbidden=forbidden)
+            sliced_prob = make_problem(net.labels, net.out_label, n, open_qubits, closed_bits,
+                                       sliced=[base.label_ids[i] for i in range(len(base.label_ids))
+                                               if (sl >> i) & 1])
+            path2 = greedy_path(sliced_prob, temperature=temp, seed=seed + 104729 * t + 1)
+            c1 = path_cost(sliced_prob, path)
+            c2 = path_cost(sliced_prob, path2)
+            if c2.peak_log2 <= max_log2 + 1e-9 and (c1.peak_log2 > max_log2 + 1e-9 or
+                                                   c2.flops_per_slice < c1.flops_per_slice):
+                path = path2
+        sliced = [base.label_ids[i] for i in range(len(base.label_ids)) if (sl >> i) & 1]
+        if n_sliced is not None and len(sliced) != n_sliced:
+            continue
+        sp = make_problem(net.labels, net.out_label, n, open_qubits, closed_bits, sliced=sliced)
+        sliced_leaves = {k for k, l in enumerate(net.labels) if any(x in sliced for x in l)}
+        cost = path_cost(sp, path, sliced_leaves)
+        if cost.peak_log2 > max_log2 + 1e-9:
+            continue
+        cand = Plan(path=path, sliced_labels=sliced, cost=cost, n_slices=1 << len(sliced))
+        if best is None or cand.total_flops < best.total_flops:
+            best = cand
+    if best is None:
+        raise RuntimeError("no plan met the size bound; raise trials or the bound")
+    return best

@@ -1,0 +1,74 @@
+"""Seeded workloads: circuit -> network -> plan -> targets, for each configuration."""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+import synth
+
+from .network import TensorNetwork, circuit_network
+from .planner import Plan, find_plan
+
+
+@dataclass
+class Workload:
+    name: str
+    circuit: dict
+    net: TensorNetwork
+    open_qubits: list
+    closed_bits: np.ndarray
+    plan: Plan
+    slice_ids: np.ndarray
+
+    @property
+    def sliced_bonds(self):
+        """Sliced labels as bond names (q, j), in slice-bit order."""
+        inv = {lab: key for key, lab in self.net.bond_label.items()}
+        return [inv[x] for x in self.plan.sliced_labels]
+
+    @property
+    def n_amplitudes(self) -> int:
+        return len(self.closed_bits) << len(self.open_qubits)
+
+
+def make_workload(circuit: dict, open_qubits, closed_bits, max_log2: float = 26,
+                  n_sliced=None, slice_ids=None, trials: int = 4, seed: int = 0,
+                  name: str = "custom") -> Workload:
+    net = circuit_network(circuit)
+    plan = find_plan(net, open_qubits, closed_bits, max_log2=max_log2, n_sliced=n_sliced,
+                     trials=trials, seed=seed)
+    if slice_ids is None:
+        slice_ids = np.arange(plan.n_slices, dtype=np.uint64)
+    return Workload(name, circuit, net, list(open_qubits), np.asarray(closed_bits, np.uint64),
+                    plan, np.asarray(slice_ids, dtype=np.uint64))
+
+
+def config_workload(name: str, mode: str = "default", trials: int = 4) -> Workload:
+    """name: small | sliced | large.  For small, mode 'amplitudes' (64 bitstrings, no open
+    qubit) or 'samples' (all 12 qubits open, one group)."""
+    cfg = synth.config(name)
+    circuit = synth.circuit_from_config(cfg)
+    n = circuit["n_qubits"]
+    if name == "small":
+        if mode == "samples":
+            open_q, closed = list(range(n)), np.zeros(1, np.uint64)
+        else:
+            a = cfg["amplitudes"]
+            open_q, closed = [], synth.distinct_bitstrings(n, a["count"], a["seed"])
+        return make_workload(circuit, open_q, closed, max_log2=cfg["max_log2_size"],
+                             n_sliced=None, trials=trials, seed=cfg["path_seed"], name=name)
+    open_q = cfg["open_qubits"]
+    g = cfg["groups"]
+    closed = synth.group_targets(n, open_q, g["L"], g["seed"])
+    ids = None
+    w = make_workload(circuit, open_q, closed, max_log2=cfg["max_log2_size"],
+                      n_sliced=cfg.get("sliced_labels"), trials=trials, seed=cfg["path_seed"],
+                      name=name)
+    if "slice_subset" in cfg:
+        sub = cfg["slice_subset"]
+        k = len(w.plan.sliced_labels)
+        ids = synth.slice_subset(k, sub["count"], sub["seed"])
+        w.slice_ids = ids
+    return w

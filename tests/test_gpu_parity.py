@@ -1,0 +1,157 @@
+"""GPU parity: libtnc (through its C ABI) against the CPU oracle on the same seeded
+inputs.  Tolerance: normwise relative error <= 1e-5 for complex64 contraction with FP32
+accumulation (the bound the target states); samples are compared exactly on identical
+amplitudes and uniforms."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import contract as ocontract
+from oracle import metrics, sampling, statevector
+from tests.gpu_util import log, random_pair_network, require_gpu
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _contraction(net, path, **kw):
+    from paper_2111_03011_amd.contractor import Contraction
+    return Contraction(net, path, **kw)
+
+
+def _pair_case(rank_a, rank_b, shared, seed, order_a=None, order_b=None):
+    net = random_pair_network(rank_a, rank_b, shared, seed, order_a, order_b)
+    c = _contraction(net, [(0, 1)], open_qubits=list(range(net.n_qubits)), closed_bits=[0])
+    c.contract()
+    got = c.amps.cpu().numpy()[0]
+    ref = ocontract.contract_path(net.tensors, net.labels, [(0, 1)], net.out_label).reshape(-1)
+    kinds = sorted({l.kind for l in c.launches()})
+    c.close()
+    return metrics.rel_error(got, ref), kinds
+
+
+@pytest.mark.parametrize("ra,rb,k,oa,ob,want", [
+    # fused small-operand stream: gate-like operand, K labels spread through the big one
+    (14, 4, 2, [5, 0, 6, 7, 8, 9, 10, 11, 1, 12, 13, 2, 3, 4], None, 2),
+    (12, 7, 4, None, None, 2),
+    # GEMM, operands already grouped ([M][K] x [K][N])
+    (16, 14, 6, None, None, 1),
+    # GEMM, transposed operands ([K][M] x [N][K])
+    (15, 13, 5, list(range(5)) + list(range(5, 15)), list(range(15, 23)) + list(range(5)), 1),
+    # GEMM after permutes (labels interleaved)
+    (14, 12, 5, [5, 0, 6, 1, 7, 2, 8, 3, 9, 4, 10, 11, 12, 13], None, 1),
+    # narrow N (<= 16), small M (<= 64), long K with split-K
+    (20, 16, 12, None, None, 1),
+    (10, 17, 5, None, None, 1),
+])
+def test_pair_contractions(ra, rb, k, oa, ob, want):
+    log(f"pair case ra={ra} rb={rb} k={k}")
+    err, kinds = _pair_case(ra, rb, k, seed=ra * 100 + rb, order_a=oa, order_b=ob)
+    log(f"  rel err {err:.3e} kinds {kinds}")
+    assert want in kinds
+    assert err <= TOL
+
+
+def test_small_amplitudes_match_state_vector():
+    from paper_2111_03011_amd.workload import config_workload
+    log("small config, 64 amplitudes")
+    w = config_workload("small", mode="amplitudes")
+    c = _contraction(w.net, w.plan.path, sliced_labels=w.plan.sliced_labels,
+                     slice_ids=w.slice_ids, open_qubits=w.open_qubits, closed_bits=w.closed_bits)
+    c.contract()
+    got = c.amps.cpu().numpy()[:, 0]
+    psi = statevector.simulate(w.circuit)
+    ref = psi[w.closed_bits.astype(np.int64)]
+    err = metrics.rel_error(got, ref)
+    log(f"  rel err {err:.3e}")
+    assert err <= TOL
+    c.close()
+
+
+def test_small_samples_exact_on_same_amplitudes():
+    from paper_2111_03011_amd.workload import config_workload
+    cfg = synth.config("small")
+    log("small config, all qubits open, 1000 samples")
+    w = config_workload("small", mode="samples")
+    c = _contraction(w.net, w.plan.path, sliced_labels=w.plan.sliced_labels,
+                     slice_ids=w.slice_ids, open_qubits=w.open_qubits, closed_bits=w.closed_bits)
+    norm = c.contract(norm=True)
+    amps = c.amps.cpu().numpy()
+    psi = statevector.simulate(w.circuit)
+    assert metrics.rel_error(amps[0], psi) <= TOL
+    assert abs(norm - np.sum(np.abs(amps) ** 2)) <= 1e-12 * max(norm, 1.0)
+    seed, k = cfg["samples"]["seed"], cfg["samples"]["count"]
+    bits = c.sample(seed, k)
+    draws = sampling.sample(amps, seed, k)
+    want = sampling.bitstrings(draws, w.closed_bits, w.open_qubits, w.net.n_qubits)
+    assert np.array_equal(bits, want)
+    # and the draws follow |psi|^2: chi-square over the 16 most likely outcomes + rest
+    p = np.abs(psi) ** 2
+    top = np.argsort(p)[::-1][:16]
+    obs = np.array([np.sum(bits == t) for t in top] + [0])
+    obs[-1] = k - obs[:-1].sum()
+    exp = np.concatenate([p[top], [1 - p[top].sum()]]) * k
+    chi2 = np.sum((obs - exp) ** 2 / exp)
+    assert chi2 < 45      # 16 dof, p ~ 2e-4
+    c.close()
+
+
+def _sliced_workload(rows, cols, cycles, seed, open_q, L, max_log2, n_sliced=None):
+    from paper_2111_03011_amd.workload import make_workload
+    circ = synth.make_circuit(rows, cols, cycles, seed)
+    n = circ["n_qubits"]
+    closed = synth.group_targets(n, open_q, L, seed + 1)
+    return make_workload(circ, open_q, closed, max_log2=max_log2, n_sliced=n_sliced,
+                         trials=2, seed=seed)
+
+
+@pytest.mark.parametrize("shape", [
+    (3, 4, 8, 11, [0, 5, 11], 1, 7, 4),     # one group, forced slicing
+    (4, 4, 10, 12, [2, 9, 13], 24, 9, None),  # sparse rows (24 groups) and slicing
+    (3, 4, 8, 13, [], 40, 8, None),          # amplitude mode (no open qubit), sliced
+])
+def test_sliced_per_slice_and_sum(shape):
+    r, cc, m, seed, open_q, L, max_log2, k = shape
+    log(f"sliced case {shape}")
+    w = _sliced_workload(r, cc, m, seed, open_q, L, max_log2, k)
+    bonds = w.sliced_bonds
+    log(f"  {len(bonds)} sliced bonds, {len(w.plan.path)} steps")
+    c = _contraction(w.net, w.plan.path, sliced_labels=w.plan.sliced_labels,
+                     slice_ids=w.slice_ids, open_qubits=w.open_qubits, closed_bits=w.closed_bits)
+    per = ocontract.sparse_amplitudes(w.circuit, w.open_qubits, w.closed_bits,
+                                      sliced_bonds=bonds, slice_ids=w.slice_ids, per_slice=True)
+    for idx in sorted({0, len(w.slice_ids) // 2, len(w.slice_ids) - 1}):
+        c.contract_range(idx, 1)
+        got = c.amps.cpu().numpy()
+        err = metrics.rel_error(got, per[idx])
+        log(f"  slice {idx}: rel err {err:.3e}")
+        assert err <= TOL
+    c.contract()
+    got = c.amps.cpu().numpy()
+    psi = statevector.simulate(w.circuit)
+    ref = statevector.sparse_from_state(psi, w.circuit["n_qubits"], w.open_qubits, w.closed_bits)
+    err = metrics.rel_error(got, ref)
+    log(f"  full sum rel err {err:.3e}")
+    assert err <= TOL
+    assert np.allclose(per.sum(axis=0), ref, atol=1e-12)
+    c.close()
+
+
+def test_group_sampling_one_per_group_exact():
+    log("one draw per group")
+    w = _sliced_workload(4, 4, 10, 21, [1, 6, 11, 12], 50, 11)
+    c = _contraction(w.net, w.plan.path, sliced_labels=w.plan.sliced_labels,
+                     slice_ids=w.slice_ids, open_qubits=w.open_qubits, closed_bits=w.closed_bits)
+    c.contract()
+    amps = c.amps.cpu().numpy()
+    bits = c.sample(99, len(w.closed_bits))
+    want = sampling.bitstrings(sampling.sample(amps, 99, len(w.closed_bits)), w.closed_bits,
+                               w.open_qubits, w.circuit["n_qubits"])
+    assert np.array_equal(bits, want)
+    c.close()
