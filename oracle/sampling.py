@@ -10,7 +10,8 @@ generators", OOPSLA 2014) used as a counter-based generator: draw j uses the sta
 seed + (j+1)*gamma, i.e. the (j+1)-th output of the sequential generator started at
 `seed`, and u_j = (output >> 11) * 2^-53.
 
-Inverse CDF: with c_mu = sum_{nu <= mu} |a_nu|^2 (summed in mu order, float64) and
+Inverse CDF: with w_mu = re^2 + im^2 (each product and the sum rounded to float64),
+c_mu = sum_{nu <= mu} w_nu (summed in mu order, float64) and
 T = c_{l-1}, the draw is the smallest mu with c_mu > u * T.  A group whose amplitudes are
 all zero draws mu = floor(u * l).
 """
@@ -61,7 +62,8 @@ def sample(amps: np.ndarray, seed: int, n_samples: int) -> np.ndarray:
     Returns (group index, mu) pairs as an int64 array of shape [n_samples, 2]."""
     amps = np.asarray(amps)
     L = amps.shape[0]
-    w = np.abs(amps.astype(np.complex128)) ** 2
+    a = amps.astype(np.complex128)
+    w = a.real * a.real + a.imag * a.imag
     out = np.zeros((n_samples, 2), dtype=np.int64)
     if L == 1:
         for j in range(n_samples):
