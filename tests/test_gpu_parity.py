@@ -155,3 +155,33 @@ def test_group_sampling_one_per_group_exact():
                                w.open_qubits, w.circuit["n_qubits"])
     assert np.array_equal(bits, want)
     c.close()
+
+
+def test_sliced_config_sampled_slices_full_size():
+    """The 5x6 / 14-cycle workload at full size, in the configuration bench.py times: two of
+    the oracle's eight seeded slices compared element by element, and the full 1024-slice
+    sum checked through a property that holds at any size (the sparse norm of 4096
+    Porter-Thomas amplitudes of a 2^30 state is 4096 / 2^30 within a few percent)."""
+    from paper_2111_03011_amd.workload import config_workload
+    cfg = synth.config("sliced")
+    log("sliced config at full size")
+    w = config_workload("sliced", trials=2)
+    assert len(w.slice_ids) == 1024 and w.plan.cost.peak_log2 <= 26
+    c = _contraction(w.net, w.plan.path, sliced_labels=w.plan.sliced_labels,
+                     slice_ids=w.slice_ids, open_qubits=w.open_qubits, closed_bits=w.closed_bits)
+    picks = synth.slice_subset(len(w.plan.sliced_labels), cfg["oracle_slices"]["count"],
+                               cfg["oracle_slices"]["seed"])[:2]
+    for sid in picks:
+        pos = int(np.nonzero(w.slice_ids == sid)[0][0])
+        c.contract_range(pos, 1)
+        got = c.amps.cpu().numpy()
+        ref = ocontract.sparse_amplitudes(w.circuit, w.open_qubits, w.closed_bits,
+                                          sliced_bonds=w.sliced_bonds, slice_ids=[int(sid)])
+        err = metrics.rel_error(got, ref)
+        log(f"  slice {int(sid)}: rel err {err:.3e}")
+        assert err <= TOL
+    norm = c.contract(norm=True)
+    ratio = norm * 2.0 ** 30 / 4096
+    log(f"  full sum: norm x 2^30 / 4096 = {ratio:.4f}")
+    assert 0.85 < ratio < 1.15
+    c.close()
