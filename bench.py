@@ -64,6 +64,7 @@ def main():
     ap.add_argument("--workload", default="sliced", choices=["sliced", "small", "large"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--samples", type=int, default=1000)
+    ap.add_argument("--batch", type=int, default=8, help="slices per launch (hipGraph per batch)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); slices would shard "
@@ -86,7 +87,8 @@ def main():
           f"{len(w.plan.sliced_labels)} sliced bonds, {len(w.slice_ids)} slices, "
           f"peak 2^{w.plan.cost.peak_log2:.0f}, {t_plan:.1f} s", file=sys.stderr, flush=True)
     c = Contraction(w.net, w.plan.path, sliced_labels=w.plan.sliced_labels,
-                    slice_ids=w.slice_ids, open_qubits=w.open_qubits, closed_bits=w.closed_bits)
+                    slice_ids=w.slice_ids, open_qubits=w.open_qubits, closed_bits=w.closed_bits,
+                    max_batch_slices=args.batch)
     flops_slice, bytes_slice, n_steps = c.stats()
     flops_inv = sum(l.flops for l in c.launches() if l.invariant)
     flops_step = flops_slice * len(w.slice_ids) + flops_inv

@@ -135,8 +135,9 @@ tnc_status tnc_sample(tnc_plan plan, void* d_workspace, uint64_t ws_bytes, const
 tnc_status tnc_plan_destroy(tnc_plan plan);
 tnc_status tnc_net_destroy(tnc_net net);
 
-/* Per-step description for reporting: kind 0 = permute, 1 = GEMM, 2 = small-operand
- * stream, 3 = slice leaves, 4 = slice sum, 5 = split-K reduction; rows, m, n, k in
+/* Per-step description for reporting: kind 1 = GEMM, 2 = small-operand stream, 3 = slice
+ * leaves, 4 = slice sum, 5 = split-K reduction (0 is reserved: operands are never
+ * permuted, the GEMM reads them in their stored layouts); rows, m, n, k in
  * elements; flops and bytes algorithmic; invariant = 1 if run once per call. */
 typedef struct {
   int32_t kind;

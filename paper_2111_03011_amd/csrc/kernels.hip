@@ -1,12 +1,13 @@
 // HIP kernels of the contraction path, written for CDNA4 (gfx950, wave64).
 //
-//   k_permute      binary-axis transpose staged through LDS (8 KiB tiles, XOR swizzle)
 //   k_stream       big tensor x small tensor, reading the big one in its own layout
 //                  (the small operand's labels may sit at any bit positions)
 //   k_gemm         complex64 GEMM on the FP32 matrix cores: the interleaved complex A is
 //                  used as a real M x 2K matrix and B is expanded on the fly into the
 //                  2K x 2N real embedding [[Br, Bi], [-Bi, Br]], so one
-//                  v_mfma_f32_32x32x2f32 consumes exactly one complex k
+//                  v_mfma_f32_32x32x2f32 consumes exactly one complex k; both operands
+//                  are read in their stored label order (per-slot scattered offsets), so
+//                  the path needs no transposes
 //   k_reduce       split-K partial sums, fixed order
 //   k_slice_leaves per-slice instantiation of the leaves that hold sliced bonds
 //   k_slice_sum    FP64 accumulation of a slice's result into psi_hat
@@ -20,59 +21,6 @@ namespace {
 
 constexpr int kThreads = 256;
 
-__device__ __forceinline__ int swz(int e) { return e ^ ((e >> 5) & 31); }
-
-// ---------------------------------------------------------------------------------
-// permute
-__global__ __launch_bounds__(kThreads) void k_permute(PermuteArgs a) {
-  __shared__ float2 tile[1 << kMaxTileBits];
-  constexpr int EPT = (1 << kMaxTileBits) / kThreads;
-  const int T = 1 << a.n_tile;
-  int64_t in_off[EPT], out_off[EPT];
-  int lds_r[EPT];
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = threadIdx.x + i * kThreads;
-    int64_t o = 0, oo = 0;
-    int ee = 0;
-    for (int j = 0; j < a.n_tile; ++j) {
-      if ((e >> j) & 1) {
-        o += int64_t(1) << a.e_in[j];
-        oo += int64_t(1) << a.f_out[j];
-        ee |= 1 << a.f_to_e[j];
-      }
-    }
-    in_off[i] = o;
-    out_off[i] = oo;
-    lds_r[i] = swz(ee);
-  }
-  const int64_t ntiles = a.rows << a.n_rest;
-  const int64_t rest_mask = (int64_t(1) << a.n_rest) - 1;
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int64_t r = t >> a.n_rest;
-    const int64_t tau = t & rest_mask;
-    int64_t ib = r * a.row_elems, ob = r * a.row_elems;
-    for (int j = 0; j < a.n_rest; ++j) {
-      if ((tau >> j) & 1) {
-        ib += int64_t(1) << a.r_in[j];
-        ob += int64_t(1) << a.r_out[j];
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int e = threadIdx.x + i * kThreads;
-      if (e < T) tile[swz(e)] = a.in[ib + in_off[i]];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int f = threadIdx.x + i * kThreads;
-      if (f < T) a.out[ob + out_off[i]] = tile[lds_r[i]];
-    }
-    __syncthreads();
-  }
-}
-
 // ---------------------------------------------------------------------------------
 // big x small stream
 template <int NK, int NN>
@@ -81,7 +29,7 @@ __global__ __launch_bounds__(kThreads) void k_stream(StreamArgs a) {
   __shared__ float2 s_lds[KS * NS];
   __shared__ int64_t koff[KS];
   __shared__ int32_t soff[KS * NS];
-  const bool s_shared = (a.s_rows == 1 && a.gs == nullptr);
+  const bool s_shared = (a.s_rows == 1 && a.gs == nullptr && a.s_slice_stride == 0);
   for (int k = threadIdx.x; k < KS; k += kThreads) {
     int64_t ko = 0;
     for (int j = 0; j < NK; ++j)
@@ -99,13 +47,15 @@ __global__ __launch_bounds__(kThreads) void k_stream(StreamArgs a) {
     if (s_shared) s_lds[q] = a.S[so];
   }
   __syncthreads();
-  const int64_t total = a.rows << a.n_m;
+  const int64_t per_slice = a.rows << a.n_m;
+  const int64_t total = per_slice * a.nb;
   const int64_t mmask = (int64_t(1) << a.n_m) - 1;
   for (int64_t g = int64_t(blockIdx.x) * kThreads + threadIdx.x; g < total;
        g += int64_t(gridDim.x) * kThreads) {
-    const int64_t r = g >> a.n_m, m = g & mmask;
+    const int64_t sl = g / per_slice, gs = g - sl * per_slice;
+    const int64_t r = gs >> a.n_m, m = gs & mmask;
     const int64_t xr = a.gx ? a.gx[r] : (a.x_rows == 1 ? 0 : r);
-    const float2* X = a.X + xr * a.x_row_stride;
+    const float2* X = a.X + sl * a.x_slice_stride + xr * a.x_row_stride;
     int64_t xo = m;
 #pragma unroll
     for (int j = 0; j < NK; ++j) {
@@ -130,7 +80,7 @@ __global__ __launch_bounds__(kThreads) void k_stream(StreamArgs a) {
       }
     } else {
       const int64_t sr = a.gs ? a.gs[r] : (a.s_rows == 1 ? 0 : r);
-      const float2* S = a.S + sr * a.s_row_stride;
+      const float2* S = a.S + sl * a.s_slice_stride + sr * a.s_row_stride;
 #pragma unroll
       for (int k = 0; k < KS; ++k) {
 #pragma unroll
@@ -141,7 +91,7 @@ __global__ __launch_bounds__(kThreads) void k_stream(StreamArgs a) {
         }
       }
     }
-    float2* C = a.C + r * a.c_row_stride + (m << NN);
+    float2* C = a.C + sl * a.c_slice_stride + r * a.c_row_stride + (m << NN);
 #pragma unroll
     for (int n = 0; n < NS; ++n) C[n] = acc[n];
   }
@@ -159,11 +109,22 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb) {
   return x * q + (x < rem ? x : rem) + bid / 8;
 }
 
-template <int WAVES_M, int WAVES_N, int UM, int UN, int BK, bool TA, bool TB>
+// Scatter the low `nbits` bits of x to the bit positions pos[0..nbits) (a software pdep).
+__device__ __forceinline__ int64_t scatter_bits(int64_t x, const int8_t* pos, int nbits) {
+  int64_t o = 0;
+  for (int j = 0; j < nbits; ++j)
+    if ((x >> j) & 1) o += int64_t(1) << pos[j];
+  return o;
+}
+
+template <int WAVES_M, int WAVES_N, int UM, int UN, int BK, bool A_MFAST, bool B_NFAST>
 __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs a) {
   static_assert(WAVES_M * WAVES_N == 4, "four waves per workgroup");
   constexpr int BM = WAVES_M * UM * 32;
   constexpr int BN = WAVES_N * UN * 16;
+  constexpr int LBM = (BM == 128) ? 7 : (BM == 64 ? 6 : 5);
+  constexpr int LBN = (BN == 64) ? 6 : (BN == 32 ? 5 : 4);
+  constexpr int LBK = (BK == 16) ? 4 : (BK == 32 ? 5 : 3);
   constexpr int AS = 2 * BK + 2;       // floats per LDS row of A (m-major)
   constexpr int BS = 2 * BN + 2;       // floats per LDS row of B (k-major)
   constexpr int A_LD = BM * BK / kThreads;
@@ -178,20 +139,49 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs a) {
   if (tile >= tiles_m * tiles_n) return;
   const int64_t tm = tile % tiles_m, tn = tile / tiles_m;
   const int64_t z = int64_t(blockIdx.y) + int64_t(blockIdx.z) * gridDim.y;
-  const int64_t r = z / a.k_splits;
+  const int64_t zr = z / a.k_splits;      // slice * rows + row
   const int ks = int(z % a.k_splits);
-  if (r >= a.rows) return;
+  if (zr >= a.rows * a.nb) return;
+  const int64_t sl = zr / a.rows, r = zr - sl * a.rows;
   const int64_t ar = a.ga ? a.ga[r] : (a.a_rows == 1 ? 0 : r);
   const int64_t br = a.gb ? a.gb[r] : (a.b_rows == 1 ? 0 : r);
-  const float2* __restrict__ A = a.A + ar * a.a_row_stride;
-  const float2* __restrict__ B = a.B + br * a.b_row_stride;
   const int64_t m0 = tm * BM, n0 = tn * BN;
+  // block bases: the tile corner's scattered offset (tile sizes divide the group sizes
+  // whenever the group is larger than the tile, so corner and in-tile bits are disjoint)
+  const int64_t mloc_mask = (int64_t(1) << a.nm) - 1;
+  const float2* __restrict__ A = a.A + sl * a.a_slice_stride + ar * a.a_row_stride +
+                                (a.fold ? (m0 >> a.nm) * a.fold_stride : 0) +
+                                scatter_bits(m0 & mloc_mask, a.a_mpos, a.nm);
+  const float2* __restrict__ B =
+      a.B + sl * a.b_slice_stride + br * a.b_row_stride + scatter_bits(n0, a.b_npos, a.nn);
   const int64_t k_begin = int64_t(ks) * a.k_chunk;
   const int64_t k_end = (k_begin + a.k_chunk < K) ? k_begin + a.k_chunk : K;
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int wm = wave % WAVES_M, wn = wave / WAVES_M;
+
+  // per-thread load slots: fixed (row, col) inside the tile, fixed scattered offsets
+  int64_t a_off[A_LD], b_off[B_LD];
+  bool a_in[A_LD], b_in[B_LD];
+  const int nbm = a.nm < LBM ? a.nm : LBM, nbk = a.nk < LBK ? a.nk : LBK;
+  const int nbn = a.nn < LBN ? a.nn : LBN;
+#pragma unroll
+  for (int i = 0; i < A_LD; ++i) {
+    const int q = threadIdx.x + i * kThreads;
+    int row, col;
+    if (A_MFAST) { row = q % BM; col = q / BM; } else { row = q / BK; col = q % BK; }
+    a_off[i] = scatter_bits(row, a.a_mpos, nbm) + scatter_bits(col, a.a_kpos, nbk);
+    a_in[i] = (m0 + row < M);
+  }
+#pragma unroll
+  for (int i = 0; i < B_LD; ++i) {
+    const int q = threadIdx.x + i * kThreads;
+    int kr, n;
+    if (B_NFAST) { kr = q / BN; n = q % BN; } else { n = q / BK; kr = q % BK; }
+    b_off[i] = scatter_bits(kr, a.b_kpos, nbk) + scatter_bits(n, a.b_npos, nbn);
+    b_in[i] = (q < BK * BN) && (n0 + n < N);
+  }
 
   f32x16 acc[UM][UN];
 #pragma unroll
@@ -203,24 +193,22 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs a) {
 
   float2 ra[A_LD], rb[B_LD];
   auto load = [&](int64_t k0) {
+    const int64_t ka = scatter_bits(k0, a.a_kpos, a.nk);
+    const int64_t kb = scatter_bits(k0, a.b_kpos, a.nk);
 #pragma unroll
     for (int i = 0; i < A_LD; ++i) {
       const int q = threadIdx.x + i * kThreads;
-      int row, col;
-      if (!TA) { row = q / BK; col = q % BK; } else { col = q / BM; row = q % BM; }
-      const int64_t m = m0 + row, k = k0 + col;
+      const int col = A_MFAST ? q / BM : q % BK;
       float2 v = make_float2(0.f, 0.f);
-      if (m < M && k < k_end) v = TA ? A[k * M + m] : A[m * K + k];
+      if (a_in[i] && k0 + col < k_end) v = A[ka + a_off[i]];
       ra[i] = v;
     }
 #pragma unroll
     for (int i = 0; i < B_LD; ++i) {
       const int q = threadIdx.x + i * kThreads;
-      int kr, n;
-      if (!TB) { kr = q / BN; n = q % BN; } else { n = q / BK; kr = q % BK; }
-      const int64_t k = k0 + kr, nn = n0 + n;
+      const int kr = B_NFAST ? q / BN : q % BK;
       float2 v = make_float2(0.f, 0.f);
-      if (q < BK * BN && k < k_end && nn < N) v = TB ? B[nn * K + k] : B[k * N + nn];
+      if (b_in[i] && k0 + kr < k_end) v = B[kb + b_off[i]];
       rb[i] = v;
     }
   };
@@ -229,7 +217,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs a) {
     for (int i = 0; i < A_LD; ++i) {
       const int q = threadIdx.x + i * kThreads;
       int row, col;
-      if (!TA) { row = q / BK; col = q % BK; } else { col = q / BM; row = q % BM; }
+      if (A_MFAST) { row = q % BM; col = q / BM; } else { row = q / BK; col = q % BK; }
       *reinterpret_cast<float2*>(&As[row * AS + 2 * col]) = ra[i];
     }
 #pragma unroll
@@ -237,7 +225,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs a) {
       const int q = threadIdx.x + i * kThreads;
       if (q >= BK * BN) continue;
       int kr, n;
-      if (!TB) { kr = q / BN; n = q % BN; } else { n = q / BK; kr = q % BK; }
+      if (B_NFAST) { kr = q / BN; n = q % BN; } else { n = q / BK; kr = q % BK; }
       *reinterpret_cast<float2*>(&Bs[kr * BS + 2 * n]) = rb[i];
     }
   };
@@ -273,8 +261,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs a) {
   }
 
   float* out = (a.k_splits > 1)
-                   ? reinterpret_cast<float*>(a.partial + (int64_t(ks) * a.rows + r) * M * N)
-                   : reinterpret_cast<float*>(a.C + r * a.c_row_stride);
+                   ? reinterpret_cast<float*>(a.partial + (int64_t(ks) * a.rows * a.nb + zr) * M * N)
+                   : reinterpret_cast<float*>(a.C + sl * a.c_slice_stride + r * a.c_row_stride);
 #pragma unroll
   for (int i = 0; i < UM; ++i)
 #pragma unroll
@@ -304,14 +292,17 @@ __global__ __launch_bounds__(kThreads) void k_reduce(ReduceArgs a) {
 
 // ---------------------------------------------------------------------------------
 // slices
-__global__ __launch_bounds__(kThreads) void k_slice_leaves(SliceLeafArgs a, int64_t total) {
-  const uint64_t sigma = a.slice_ids[a.slice_index];
+__global__ __launch_bounds__(kThreads) void k_slice_leaves(SliceLeafArgs a, int64_t per_slice) {
+  const int64_t base = *a.base;
+  const int64_t total = per_slice * a.nb;
   for (int64_t g = int64_t(blockIdx.x) * kThreads + threadIdx.x; g < total;
        g += int64_t(gridDim.x) * kThreads) {
+    const int64_t sl = g / per_slice, gg = g - sl * per_slice;
+    const uint64_t sigma = a.slice_ids[base + sl];
     int e = 0;
-    while (e + 1 < a.n_entries && a.prefix[e + 1] <= g) ++e;
+    while (e + 1 < a.n_entries && a.prefix[e + 1] <= gg) ++e;
     const SliceLeafEntry& t = a.table[e];
-    const int64_t o = g - a.prefix[e];
+    const int64_t o = gg - a.prefix[e];
     const int64_t row = o >> t.dense_out;
     int64_t d = o & ((int64_t(1) << t.dense_out) - 1);
     for (int j = 0; j < t.n_sl; ++j) {
@@ -320,7 +311,7 @@ __global__ __launch_bounds__(kThreads) void k_slice_leaves(SliceLeafArgs a, int6
       d = ((d >> p) << (p + 1)) | (v << p) | (d & ((int64_t(1) << p) - 1));
     }
     const int64_t src = t.src_off + (row << (t.dense_out + t.n_sl)) + d;
-    a.ws[t.dst_off + o] = a.consts[src];
+    a.ws[t.dst_off + sl * t.elems_out + o] = a.consts[src];
   }
 }
 
@@ -333,17 +324,23 @@ __global__ __launch_bounds__(kThreads) void k_slice_sum(SliceSumArgs a) {
     int64_t off = int64_t(a.row_of[grp]) * a.f_row_stride;
     for (int t = 0; t < a.n_open; ++t)
       if ((mu >> (a.n_open - 1 - t)) & 1) off += a.open_stride[t];
-    const float2 v = a.F[off];
     double2* out = reinterpret_cast<double2*>(a.amps) + g;
-    if (a.overwrite) {
-      *out = make_double2(double(v.x), double(v.y));
-    } else {
-      double2 o = *out;
+    double2 o = a.overwrite ? make_double2(0.0, 0.0) : *out;
+    for (int64_t sl = 0; sl < a.nb; ++sl) {     // slice order, one rounding per slice
+      const float2 v = a.F[sl * a.f_slice_stride + off];
       o.x += double(v.x);
       o.y += double(v.y);
-      *out = o;
     }
+    *out = o;
   }
+}
+
+__global__ void k_set_i64(int64_t* p, int64_t v) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *p = v;
+}
+
+__global__ void k_add_i64(int64_t* p, int64_t v) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *p += v;
 }
 
 __global__ __launch_bounds__(kThreads) void k_fill_zero(double* p, int64_t n) {
@@ -477,7 +474,7 @@ int grid_for(int64_t work, int64_t per_block, int64_t cap = 8192) {
 
 template <int NK, int NN>
 hipError_t launch_stream_t(const StreamArgs& a, hipStream_t s) {
-  const int64_t total = a.rows << a.n_m;
+  const int64_t total = (a.rows << a.n_m) * a.nb;
   hipLaunchKernelGGL((k_stream<NK, NN>), dim3(grid_for(total, kThreads, 65536)), dim3(kThreads), 0,
                      s, a);
   return hipGetLastError();
@@ -499,15 +496,15 @@ template <int WM, int WN, int UM, int UN, int BK>
 hipError_t launch_gemm_cfg(const GemmArgs& a, hipStream_t s) {
   constexpr int BM = WM * UM * 32, BN = WN * UN * 16;
   const int64_t tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
-  const int64_t zs = a.rows * a.k_splits;
+  const int64_t zs = a.rows * a.nb * a.k_splits;
   const int64_t gy = zs < 65535 ? zs : 65535;
   const int64_t gz = (zs + gy - 1) / gy;
   const dim3 grid{unsigned(tiles), unsigned(gy), unsigned(gz)};
-  if (!a.trans_a && !a.trans_b)
+  if (!a.a_mfast && !a.b_nfast)
     hipLaunchKernelGGL((k_gemm<WM, WN, UM, UN, BK, false, false>), grid, dim3(kThreads), 0, s, a);
-  else if (a.trans_a && !a.trans_b)
+  else if (a.a_mfast && !a.b_nfast)
     hipLaunchKernelGGL((k_gemm<WM, WN, UM, UN, BK, true, false>), grid, dim3(kThreads), 0, s, a);
-  else if (!a.trans_a && a.trans_b)
+  else if (!a.a_mfast && a.b_nfast)
     hipLaunchKernelGGL((k_gemm<WM, WN, UM, UN, BK, false, true>), grid, dim3(kThreads), 0, s, a);
   else
     hipLaunchKernelGGL((k_gemm<WM, WN, UM, UN, BK, true, true>), grid, dim3(kThreads), 0, s, a);
@@ -515,12 +512,6 @@ hipError_t launch_gemm_cfg(const GemmArgs& a, hipStream_t s) {
 }
 
 }  // namespace
-
-hipError_t launch_permute(const PermuteArgs& a, hipStream_t s) {
-  const int64_t tiles = a.rows << a.n_rest;
-  hipLaunchKernelGGL(k_permute, dim3(grid_for(tiles, 1, 16384)), dim3(kThreads), 0, s, a);
-  return hipGetLastError();
-}
 
 hipError_t launch_stream(const StreamArgs& a, hipStream_t s) {
   switch (a.nk) {
@@ -551,15 +542,25 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_slice_leaves(const SliceLeafArgs& a, int64_t total, hipStream_t s) {
-  hipLaunchKernelGGL(k_slice_leaves, dim3(grid_for(total, kThreads)), dim3(kThreads), 0, s, a,
-                     total);
+hipError_t launch_slice_leaves(const SliceLeafArgs& a, int64_t per_slice, hipStream_t s) {
+  hipLaunchKernelGGL(k_slice_leaves, dim3(grid_for(per_slice * a.nb, kThreads)), dim3(kThreads), 0,
+                     s, a, per_slice);
   return hipGetLastError();
 }
 
 hipError_t launch_slice_sum(const SliceSumArgs& a, hipStream_t s) {
   const int64_t total = a.L << a.n_open;
   hipLaunchKernelGGL(k_slice_sum, dim3(grid_for(total, kThreads)), dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, s, p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_i64(int64_t* p, int64_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_i64, dim3(1), dim3(64), 0, s, p, v);
   return hipGetLastError();
 }
 

@@ -2,9 +2,9 @@
 //
 // The contraction of one slice is compiled once into a list of kernel launches:
 //   * leaves carrying sliced bonds are instantiated per slice (paper, Appendix B.2);
-//   * every path pair (Appendix E format) becomes either a fused small-operand stream, or
-//     permutes (only when an operand's labels are interleaved) followed by a complex GEMM,
-//     optionally split along K with a fixed-order reduction;
+//   * every path pair (Appendix E format) becomes either a fused small-operand stream or a
+//     complex GEMM that reads both operands in their stored layouts (no permute is ever
+//     issued), optionally split along K with a fixed-order reduction;
 //   * tensors that carry closed final qubits keep one row per distinct restriction of the
 //     requested bitstrings (Appendix A: only the configurations some target needs), and
 //     a contraction of two such tensors gathers the matching operand rows;
@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <set>
@@ -93,7 +94,9 @@ enum Kind { K_PERMUTE = 0, K_GEMM = 1, K_STREAM = 2, K_LEAVES = 3, K_SUM = 4, K_
 constexpr int kKinds = 6;
 
 struct Buf {
-  uint64_t bytes = 0;
+  uint64_t bytes = 0;         // all copies
+  uint64_t elems = 0;         // complex64 elements of one copy
+  bool per_slice = false;     // one copy per slice of a batch
   bool is_const = false;
   uint64_t off = 0;       // absolute byte offset in the workspace
   int t0 = INT_MAX, t1 = -1;
@@ -106,7 +109,6 @@ struct Launch {
   std::vector<int> bufs;  // buffers touched (for lifetimes)
   int b_in0 = -1, b_in1 = -1, b_out = -1, b_tmp = -1;
   int64_t g0 = -1, g1 = -1;   // byte offsets of row gathers in the constants block
-  PermuteArgs perm{};
   StreamArgs st{};
   GemmArgs gm{};
   ReduceArgs rd{};
@@ -160,7 +162,13 @@ struct tnc_plan_s {
   // sampling and norm scratch
   int64_t closed_off = 0, open_off = 0;
   int norm_parts = 1024;
-  int b_norm = -1, b_cum = -1, b_samples = -1;
+  int b_norm = -1, b_cum = -1, b_samples = -1, b_counter = -1;
+  int batch = 1;
+  // captured program of one full batch (per workspace and amplitude buffer)
+  hipGraphExec_t graph = nullptr;
+  hipStream_t capture_stream = nullptr;
+  const void* graph_ws = nullptr;
+  const void* graph_amps = nullptr;
   int64_t sample_chunk = 0;
 
   double flops_slice = 0, bytes_slice = 0, flops_inv = 0, bytes_inv = 0;
@@ -176,6 +184,8 @@ struct tnc_plan_s {
   int64_t t_n[kKinds] = {};
   ~tnc_plan_s() {
     for (auto e : ev_pool) (void)hipEventDestroy(e);
+    if (graph) (void)hipGraphExecDestroy(graph);
+    if (capture_stream) (void)hipStreamDestroy(capture_stream);
   }
 };
 
@@ -208,12 +218,19 @@ struct Compiler {
 
   Compiler(tnc_net_s& n, tnc_plan_s& p) : net(n), plan(p) {}
 
-  int new_buf(uint64_t bytes, bool is_const = false) {
+  int new_buf(uint64_t bytes, bool is_const = false, bool per_slice = false) {
     Buf b;
-    b.bytes = align_up(std::max<uint64_t>(bytes, 8));
+    b.elems = bytes / 8;
+    b.per_slice = per_slice;
+    const uint64_t copies = per_slice ? uint64_t(plan.batch) : 1;
+    b.bytes = align_up(std::max<uint64_t>(bytes * copies, 8));
     b.is_const = is_const;
     plan.bufs.push_back(b);
     return int(plan.bufs.size() - 1);
+  }
+
+  int64_t sstride(int b) const {
+    return plan.bufs[b].per_slice ? int64_t(plan.bufs[b].elems) : 0;
   }
 
   int64_t add_const(const void* p, uint64_t bytes) {
@@ -316,7 +333,7 @@ struct Compiler {
           e.bit[j] = int8_t(sl[j].second);
         }
         s.dep = true;
-        s.buf = new_buf(uint64_t(e.elems_out) * 8);
+        s.buf = new_buf(uint64_t(e.elems_out) * 8, false, true);
         e.dst_off = s.buf;    // resolved after packing
         plan.sl_table.push_back(e);
       }
@@ -350,68 +367,24 @@ struct Compiler {
     }
   }
 
-  // permute operand s (rows kept) into label order `to`; returns the new buffer
-  int emit_permute(const TState& s, const std::vector<int32_t>& to, bool inv, int step_out_buf) {
-    (void)step_out_buf;
-    const int d = int(s.dense.size());
-    std::vector<int> pi(d);   // input position -> output position
-    for (int p = 0; p < d; ++p) pi[p] = pos_of(to, s.dense[d - 1 - p]);
-    Launch L;
-    L.kind = K_PERMUTE;
-    L.inv = inv;
-    PermuteArgs& a = L.perm;
-    a.rows = s.rows();
-    a.row_elems = int64_t(1) << d;
-    // tile bits: the lowest input bits and the input bits that land lowest in the output
-    int ia = std::min(d, 5), ib = std::min(d, 5);
-    auto tile_set = [&](int na, int nb) {
-      std::vector<int> u;
-      for (int p = 0; p < na; ++p) u.push_back(p);
-      for (int p = 0; p < d; ++p)
-        if (pi[p] < nb && p >= na) u.push_back(p);
-      return u;
-    };
-    std::vector<int> U = tile_set(ia, ib);
-    while (true) {
-      bool grew = false;
-      if (ia < d) {
-        auto u2 = tile_set(ia + 1, ib);
-        if (int(u2.size()) <= kMaxTileBits) { ia++; U = u2; grew = true; }
-      }
-      if (ib < d) {
-        auto u2 = tile_set(ia, ib + 1);
-        if (int(u2.size()) <= kMaxTileBits) { ib++; U = u2; grew = true; }
-      }
-      if (!grew) break;
+  // Tile configuration and split-K.  Debug overrides: TNC_GEMM_CONFIG forces a tile
+  // configuration, TNC_SPLITK_BLOCKS sets the workgroup count split-K aims for.
+  static void choose_tiles(GemmArgs& g, int64_t M, int64_t N, int64_t Kd, int64_t rows) {
+    const char* force = std::getenv("TNC_GEMM_CONFIG");
+    const char* blocks_env = std::getenv("TNC_SPLITK_BLOCKS");
+    const int64_t target = blocks_env ? std::atoll(blocks_env) : 2048;
+    g.config = (N <= 16) ? 1 : ((M <= 64 || N <= 32) ? 2 : 0);
+    if (force) g.config = std::atoi(force);
+    const int64_t BM = g.config == 2 ? 64 : 128, BN = g.config == 0 ? 64 : (g.config == 1 ? 16 : 32);
+    const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN) * rows;
+    g.k_splits = 1;
+    g.k_chunk = Kd;
+    if (tiles * 4 <= target && Kd >= 512) {
+      int64_t s = 1;
+      while (tiles * s * 2 <= target && Kd / (s * 2) >= 256) s *= 2;
+      g.k_splits = int(s);
+      g.k_chunk = Kd / s;
     }
-    a.n_tile = int(U.size());
-    for (int j = 0; j < a.n_tile; ++j) a.e_in[j] = int8_t(U[j]);
-    std::vector<int> byout = U;
-    std::sort(byout.begin(), byout.end(), [&](int x, int y) { return pi[x] < pi[y]; });
-    for (int j = 0; j < a.n_tile; ++j) {
-      a.f_out[j] = int8_t(pi[byout[j]]);
-      a.f_to_e[j] = int8_t(std::find(U.begin(), U.end(), byout[j]) - U.begin());
-    }
-    int nr = 0;
-    for (int p = 0; p < d; ++p) {
-      if (std::find(U.begin(), U.end(), p) != U.end()) continue;
-      a.r_in[nr] = int8_t(p);
-      a.r_out[nr] = int8_t(pi[p]);
-      nr++;
-    }
-    a.n_rest = nr;
-    const int out = new_buf(uint64_t(s.elems()) * 8);
-    L.b_in0 = s.buf;
-    L.b_out = out;
-    L.bufs = {s.buf, out};
-    L.info.kind = K_PERMUTE;
-    L.info.invariant = inv;
-    L.info.rows = s.rows();
-    L.info.m = int64_t(1) << d;
-    L.info.bytes = 16.0 * double(s.elems());
-    account(L);
-    list(inv).push_back(L);
-    return out;
   }
 
   TState step(TState& A, TState& B) {
@@ -465,7 +438,10 @@ struct Compiler {
       for (int j = 0; j < a.nn; ++j) a.s_npos[j] = int8_t(pos_of(S.dense, NS[NS.size() - 1 - j]));
       C.dense = MX;
       C.dense.insert(C.dense.end(), NS.begin(), NS.end());
-      C.buf = new_buf(uint64_t(C.elems()) * 8);
+      C.buf = new_buf(uint64_t(C.elems()) * 8, false, C.dep);
+      a.x_slice_stride = sstride(X.buf);
+      a.s_slice_stride = sstride(S.buf);
+      a.c_slice_stride = sstride(C.buf);
       L.b_in0 = X.buf;
       L.b_in1 = S.buf;
       L.b_out = C.buf;
@@ -497,51 +473,38 @@ struct Compiler {
       r.insert(r.end(), y.begin(), y.end());
       return r;
     };
-    int p_form = -1, q_form = -1;  // 0 = [free][K], 1 = [K][free] (P), Q: 0 = [K][N], 1 = [N][K]
-    if (P.dense == cat(MP, KP)) p_form = 0;
-    else if (P.dense == cat(KP, MP)) p_form = 1;
-    if (Q.dense == cat(KQ, NQ)) q_form = 0;
-    else if (Q.dense == cat(NQ, KQ)) q_form = 1;
-    std::vector<int32_t> Kord;
-    int pbuf = P.buf, qbuf = Q.buf;
-    std::vector<int> temps;
-    if (p_form >= 0 && q_form >= 0 && KP == KQ) {
-      Kord = KP;
-    } else if (p_form >= 0 && (q_form < 0 || P.elems() >= Q.elems())) {
-      Kord = KP;
-      q_form = 0;
-      qbuf = emit_permute(Q, cat(Kord, NQ), inv, -1);
-      temps.push_back(qbuf);
-    } else if (q_form >= 0) {
-      Kord = KQ;
-      p_form = 0;
-      pbuf = emit_permute(P, cat(MP, Kord), inv, -1);
-      temps.push_back(pbuf);
-    } else {
-      Kord = KP;
-      p_form = 0;
-      q_form = 0;
-      pbuf = emit_permute(P, cat(MP, Kord), inv, -1);
-      qbuf = emit_permute(Q, cat(Kord, NQ), inv, -1);
-      temps.push_back(pbuf);
-      temps.push_back(qbuf);
-    }
+    // the logical k order follows the larger operand, so its loads stay contiguous
+    const std::vector<int32_t>& Kord = (P.elems() >= Q.elems()) ? KP : KQ;
     Launch L;
     L.kind = K_GEMM;
     L.inv = inv;
     GemmArgs& g = L.gm;
-    int64_t M = int64_t(1) << MP.size(), N = int64_t(1) << NQ.size(), Kd = int64_t(1) << nk;
+    const int nm = int(MP.size()), nn = int(NQ.size());
+    int64_t M = int64_t(1) << nm, N = int64_t(1) << nn, Kd = int64_t(1) << nk;
     int64_t rows = C.rows();
+    g.nm = nm;
+    g.nk = nk;
+    g.nn = nn;
+    for (int j = 0; j < nm; ++j) g.a_mpos[j] = int8_t(pos_of(P.dense, MP[nm - 1 - j]));
+    for (int j = 0; j < nk; ++j) {
+      g.a_kpos[j] = int8_t(pos_of(P.dense, Kord[nk - 1 - j]));
+      g.b_kpos[j] = int8_t(pos_of(Q.dense, Kord[nk - 1 - j]));
+    }
+    for (int j = 0; j < nn; ++j) g.b_npos[j] = int8_t(pos_of(Q.dense, NQ[nn - 1 - j]));
+    g.a_mfast = (!P.dense.empty() && std::find(MP.begin(), MP.end(), P.dense.back()) != MP.end());
+    g.b_nfast = (!Q.dense.empty() && std::find(NQ.begin(), NQ.end(), Q.dense.back()) != NQ.end());
+    const int pbuf = P.buf, qbuf = Q.buf;
     L.g0 = gather(P, C);
     L.g1 = gather(Q, C);
     g.a_rows = P.rows();
     g.b_rows = Q.rows();
     g.a_row_stride = int64_t(1) << P.dense.size();
     g.b_row_stride = int64_t(1) << Q.dense.size();
-    g.trans_a = p_form;
-    g.trans_b = q_form;
-    // rows folded into M when Q is shared by every row and P is row-aligned [r][M][K]
-    if (rows > 1 && Q.rows() == 1 && P.q == C.q && p_form == 0) {
+    // rows folded into M when Q is shared by every row and P's rows line up with C's
+    // (a tile never straddles two rows: the per-row M is at least the largest tile)
+    if (rows > 1 && Q.rows() == 1 && P.q == C.q && M >= 128) {
+      g.fold = 1;
+      g.fold_stride = g.a_row_stride;
       M *= rows;
       rows = 1;
       g.a_rows = 1;
@@ -552,32 +515,25 @@ struct Compiler {
     g.K = Kd;
     g.rows = rows;
     g.c_row_stride = M * N;
-    g.config = (N <= 16) ? 1 : ((M <= 64 || N <= 32) ? 2 : 0);
-    const int64_t BM = g.config == 2 ? 64 : 128, BN = g.config == 0 ? 64 : (g.config == 1 ? 16 : 32);
-    const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN) * rows;
-    g.k_splits = 1;
-    g.k_chunk = Kd;
-    if (tiles < 512 && Kd >= 512) {
-      int64_t s = 1;
-      while (tiles * s * 2 <= 2048 && Kd / (s * 2) >= 256) s *= 2;
-      g.k_splits = int(s);
-      g.k_chunk = Kd / s;
-    }
+    choose_tiles(g, M, N, Kd, rows);
     C.dense = cat(MP, NQ);
-    C.buf = new_buf(uint64_t(C.elems()) * 8);
+    C.buf = new_buf(uint64_t(C.elems()) * 8, false, C.dep);
+    g.a_slice_stride = sstride(pbuf);
+    g.b_slice_stride = sstride(qbuf);
+    g.c_slice_stride = sstride(C.buf);
     L.b_in0 = pbuf;
     L.b_in1 = qbuf;
     L.b_out = C.buf;
     L.bufs = {pbuf, qbuf, C.buf};
     int part = -1;
     if (g.k_splits > 1) {
-      part = new_buf(uint64_t(g.k_splits) * uint64_t(rows) * uint64_t(M) * uint64_t(N) * 8);
+      part = new_buf(uint64_t(g.k_splits) * uint64_t(rows) * uint64_t(M) * uint64_t(N) * 8, false,
+                     C.dep);
       L.b_tmp = part;
       L.bufs.push_back(part);
     }
     L.info = tnc_step_info{K_GEMM, inv, rows, M, N, Kd, 8.0 * macs,
                            8.0 * double(P.elems() + Q.elems() + C.elems())};
-    for (int tb : temps) L.bufs.push_back(tb);
     account(L);
     list(inv).push_back(L);
     if (part >= 0) {
@@ -627,6 +583,7 @@ struct Compiler {
     s.L = int64_t(net.closed.size());
     s.n_open = int(net.open.size());
     s.f_row_stride = int64_t(1) << F.dense.size();
+    s.f_slice_stride = sstride(F.buf);
     for (int t = 0; t < s.n_open; ++t)
       s.open_stride[t] = int64_t(1) << pos_of(F.dense, net.out_label[net.open[t]]);
     plan.final_buf = F.buf;
@@ -654,6 +611,7 @@ struct Compiler {
     plan.b_cum = new_buf(uint64_t(l) * 8);
     plan.sample_chunk = std::max<int64_t>(plan.L, 65536);
     plan.b_samples = new_buf(uint64_t(plan.sample_chunk) * 8);
+    plan.b_counter = new_buf(8);
   }
 };
 
@@ -732,22 +690,22 @@ struct Exec {
     return p.ev_pool[p.ev_used++];
   }
 
-  void launch(const Launch& L, int64_t slice_index, double* amps, bool timed) {
+  int64_t* counter() const { return reinterpret_cast<int64_t*>(ws + p.bufs[p.b_counter].off); }
+
+  void check(hipError_t err) {
+    if (err != hipSuccess) fail(TNC_E_HIP, std::string("kernel launch: ") + hipGetErrorString(err));
+  }
+
+  // one launch of the program for nb slices (nb = 1 for the invariant phase)
+  void launch(const Launch& L, int64_t nb, double* amps, hipStream_t st, bool timed) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
       e0 = ev();
       e1 = ev();
-      HIPCHK(hipEventRecord(e0, s));
+      HIPCHK(hipEventRecord(e0, st));
     }
     hipError_t err = hipSuccess;
     switch (L.kind) {
-      case K_PERMUTE: {
-        PermuteArgs a = L.perm;
-        a.in = ptr(L.b_in0);
-        a.out = ptr(L.b_out);
-        err = launch_permute(a, s);
-        break;
-      }
       case K_STREAM: {
         StreamArgs a = L.st;
         a.X = ptr(L.b_in0);
@@ -755,7 +713,8 @@ struct Exec {
         a.C = ptr(L.b_out);
         a.gx = gat(L.g0);
         a.gs = gat(L.g1);
-        err = launch_stream(a, s);
+        a.nb = nb;
+        err = launch_stream(a, st);
         break;
       }
       case K_GEMM: {
@@ -766,14 +725,16 @@ struct Exec {
         a.ga = gat(L.g0);
         a.gb = gat(L.g1);
         a.partial = L.b_tmp >= 0 ? ptr(L.b_tmp) : nullptr;
-        err = launch_gemm(a, s);
+        a.nb = nb;
+        err = launch_gemm(a, st);
         break;
       }
       case K_REDUCE: {
         ReduceArgs a = L.rd;
         a.partial = ptr(L.b_in0);
         a.C = ptr(L.b_out);
-        err = launch_reduce(a, s);
+        a.elems = L.rd.elems * nb;
+        err = launch_reduce(a, st);
         break;
       }
       case K_LEAVES: {
@@ -784,8 +745,9 @@ struct Exec {
         a.consts = reinterpret_cast<const float2*>(ws);
         a.ws = reinterpret_cast<float2*>(ws);
         a.slice_ids = reinterpret_cast<const uint64_t*>(ws + p.slice_ids_off);
-        a.slice_index = slice_index;
-        err = launch_slice_leaves(a, p.sl_total, s);
+        a.base = counter();
+        a.nb = nb;
+        err = launch_slice_leaves(a, p.sl_total, st);
         break;
       }
       case K_SUM: {
@@ -794,15 +756,46 @@ struct Exec {
         a.amps = amps;
         a.row_of = reinterpret_cast<const int32_t*>(ws + p.row_of_off);
         a.overwrite = 0;
-        err = launch_slice_sum(a, s);
+        a.nb = nb;
+        err = launch_slice_sum(a, st);
         break;
       }
     }
-    if (err != hipSuccess) fail(TNC_E_HIP, std::string("kernel launch: ") + hipGetErrorString(err));
+    check(err);
     if (timed) {
-      HIPCHK(hipEventRecord(e1, s));
-      p.pending.push_back(TimingRec{L.kind, L.info.bytes, L.info.flops, e0, e1});
+      HIPCHK(hipEventRecord(e1, st));
+      p.pending.push_back(TimingRec{L.kind, L.info.bytes * double(nb), L.info.flops * double(nb), e0, e1});
     }
+  }
+
+  // the per-batch program: every slice-dependent launch, then the slice counter advance
+  void batch(int64_t nb, double* amps, hipStream_t st, bool timed) {
+    for (auto& L : p.dep) launch(L, nb, amps, st, timed);
+    check(launch_add_i64(counter(), nb, st));
+  }
+
+  void capture(double* amps) {
+    if (p.graph && p.graph_ws == ws && p.graph_amps == amps) return;
+    if (p.graph) {
+      HIPCHK(hipGraphExecDestroy(p.graph));
+      p.graph = nullptr;
+    }
+    if (!p.capture_stream) HIPCHK(hipStreamCreateWithFlags(&p.capture_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(p.capture_stream, hipStreamCaptureModeThreadLocal));
+    try {
+      batch(p.batch, amps, p.capture_stream, false);
+    } catch (...) {
+      (void)hipStreamEndCapture(p.capture_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    HIPCHK(hipStreamEndCapture(p.capture_stream, &g));
+    hipError_t e = hipGraphInstantiate(&p.graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) fail(TNC_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    p.graph_ws = ws;
+    p.graph_amps = amps;
   }
 
   void upload() {
@@ -815,22 +808,30 @@ struct Exec {
   void contract(double* amps, int64_t first, int64_t count, bool accumulate) {
     upload();
     const int64_t n_amp = p.L << p.n_open;
-    if (!accumulate) {
-      hipError_t e = launch_fill_zero(amps, 2 * n_amp, s);
-      if (e != hipSuccess) fail(TNC_E_HIP, hipGetErrorString(e));
-    }
+    if (!accumulate) check(launch_fill_zero(amps, 2 * n_amp, s));
     if (count <= 0) return;
-    // with timing on, a bounded sample of slices is bracketed by events
-    int64_t stride = 1;
+    for (auto& L : p.inv) launch(L, 1, amps, s, p.timing);
+    check(launch_set_i64(counter(), first, s));
+    const int64_t S = p.batch;
+    const int64_t full = count / S, rest = count % S;
+    static const bool no_graph = std::getenv("TNC_NO_GRAPH") != nullptr;
+    // Full batches replay the captured graph.  With timing on, a bounded sample of batches
+    // (about 4096 launches per call) is launched eagerly with an event pair per launch.
+    const int64_t nbat = full + (rest ? 1 : 0);
+    int64_t stride = nbat + 1;
     if (p.timing) {
       const int64_t per = std::max<int64_t>(1, int64_t(p.dep.size()));
       const int64_t n_timed = std::max<int64_t>(1, 4096 / per);
-      stride = std::max<int64_t>(1, count / n_timed);
+      stride = std::max<int64_t>(1, nbat / n_timed);
     }
-    for (auto& L : p.inv) launch(L, 0, amps, p.timing);
-    for (int64_t i = 0; i < count; ++i) {
-      const bool timed = p.timing && (i % stride == 0);
-      for (auto& L : p.dep) launch(L, first + i, amps, timed);
+    if (full > 0 && !no_graph) capture(amps);
+    for (int64_t b = 0; b < nbat; ++b) {
+      const int64_t nb = b < full ? S : rest;
+      const bool timed = p.timing && (b % stride == 0);
+      if (timed || no_graph || nb < S)
+        batch(nb, amps, s, timed);
+      else
+        HIPCHK(hipGraphLaunch(p.graph, s));
     }
   }
 };
@@ -1014,6 +1015,7 @@ tnc_status tnc_plan_create(tnc_net net, tnc_precision precision, int32_t max_bat
       p->open = net->open;
       p->closed = net->closed;
       p->slice_ids = net->slice_ids;
+      p->batch = std::max<int32_t>(1, std::min<int32_t>(max_batch, int32_t(net->slice_ids.size())));
       Compiler c(*net, *p);
       c.run();
       pack(*p);

@@ -10,23 +10,7 @@
 
 namespace tnc {
 
-constexpr int kMaxTileBits = 10;   // permute tile: 2^10 complex64 = 8 KiB of LDS
 constexpr int kMaxRank = 40;
-
-// out[r][y] = in[r][x], bit p of x moves to bit out_pos[p] of y.
-struct PermuteArgs {
-  const float2* in;
-  float2* out;
-  int64_t rows;
-  int64_t row_elems;          // 2^rank (both sides)
-  int n_tile;                 // bits staged through LDS
-  int n_rest;                 // remaining bits (tile index)
-  int8_t e_in[kMaxTileBits];  // e-bit j -> input bit position (bits 0.. are input-fastest)
-  int8_t f_out[kMaxTileBits]; // f-bit j -> output bit position (bits 0.. are output-fastest)
-  int8_t f_to_e[kMaxTileBits];// f-bit j -> e-bit holding the same label
-  int8_t r_in[kMaxRank];      // tile-index bit j -> input position
-  int8_t r_out[kMaxRank];     // tile-index bit j -> output position
-};
 
 // C[r][m][n] = sum_k X[gx(r)][m (+) k] * S[gs(r)][k, n] for a small S (<= 2^6 x 2^4).
 // m enumerates X's free labels in X order; K positions in X are spread anywhere.
@@ -39,6 +23,8 @@ struct StreamArgs {
   int64_t rows;               // output rows
   int64_t x_rows, s_rows;     // operand row counts (for null gathers)
   int64_t x_row_stride, s_row_stride, c_row_stride;
+  int64_t nb;                 // slices in this launch
+  int64_t x_slice_stride, s_slice_stride, c_slice_stride;   // 0 = shared by every slice
   int n_m;                    // log2 M
   int nk, nn;                 // log2 K, log2 N (template values)
   int8_t x_kpos[6];           // k bit j -> X bit position
@@ -47,8 +33,11 @@ struct StreamArgs {
   int8_t s_npos[4];           // n bit j -> S bit position
 };
 
-// C[r][m][n] = sum_k A[ga(r)][m,k] B[gb(r)][k,n]; A is [M][K] (or [K][M] when trans_a),
-// B is [K][N] (or [N][K] when trans_b), C is [M][N].  With k_splits > 1 every split
+// C[r][m][n] = sum_k A[ga(r)][m,k] B[gb(r)][k,n] with C stored [M][N] row-major.
+// A and B are read in their own layouts: bit j of the logical index m (k, n) selects bit
+// position a_mpos[j] (a_kpos[j] / b_kpos[j], b_npos[j]) of the operand's dense index, so no
+// operand is ever permuted.  With fold = 1 the output rows are folded into M:
+// m = row * 2^nm + m_local and A's row stride is fold_stride.  With k_splits > 1 every split
 // writes its partial product to `partial` [split][row][M][N].
 struct GemmArgs {
   const float2* A;
@@ -58,15 +47,21 @@ struct GemmArgs {
   const int32_t* gb;
   int64_t rows, a_rows, b_rows;
   int64_t a_row_stride, b_row_stride, c_row_stride;
+  int64_t nb;                 // slices in this launch (partial layout [split][slice][row][M][N])
+  int64_t a_slice_stride, b_slice_stride, c_slice_stride;
   int64_t M, N, K;
-  int trans_a, trans_b;
+  int nm, nk, nn;             // log2 of the label groups (M = 2^nm unless folded)
+  int fold;
+  int64_t fold_stride;
+  int a_mfast, b_nfast;       // operand's lowest bit is an m (n) bit: load along m (n)
+  int8_t a_mpos[kMaxRank], a_kpos[kMaxRank], b_kpos[kMaxRank], b_npos[kMaxRank];
   int k_splits;
   int64_t k_chunk;
   float2* partial;
   int config;                 // tile configuration id
 };
 
-struct ReduceArgs {           // C[i] = sum_s partial[s][i]
+struct ReduceArgs {           // C[i] = sum_s partial[s][i]  (i over every slice of the launch)
   const float2* partial;
   float2* C;
   int64_t elems;
@@ -84,6 +79,8 @@ struct SliceLeafEntry {
   int8_t bit[8];              // which bit of the slice id gives each value
 };
 
+// Slice s of a launch uses slice id slice_ids[*base + s] and writes its leaves at
+// dst_off + s * elems_out.
 struct SliceLeafArgs {
   const SliceLeafEntry* table;
   const int64_t* prefix;      // [n_entries + 1] element prefix sums
@@ -91,29 +88,34 @@ struct SliceLeafArgs {
   const float2* consts;
   float2* ws;
   const uint64_t* slice_ids;  // device
-  int64_t slice_index;
+  const int64_t* base;        // device: index of the launch's first slice in slice_ids
+  int64_t nb;
 };
 
 // amps[g][mu] (+)= sum over the final tensor's entry for (row_of[g], mu).
+// amps is accumulated slice by slice in slice order, whatever the launch's batch size.
 struct SliceSumArgs {
   const float2* F;
   double* amps;               // [L][2^n_open] complex128
   const int32_t* row_of;      // [L]
   int64_t L;
   int64_t f_row_stride;
+  int64_t nb, f_slice_stride;
   int n_open;
   int64_t open_stride[64];    // element stride of open qubit t (t = 0 is mu's top bit)
   int overwrite;
 };
 
 // Launchers (return hipError_t of the launch).
-hipError_t launch_permute(const PermuteArgs& a, hipStream_t s);
 hipError_t launch_stream(const StreamArgs& a, hipStream_t s);
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_slice_leaves(const SliceLeafArgs& a, int64_t total_elems, hipStream_t s);
 hipError_t launch_slice_sum(const SliceSumArgs& a, hipStream_t s);
 hipError_t launch_fill_zero(double* p, int64_t n_doubles, hipStream_t s);
+// *p = v; *p += v (single-thread kernels: safe inside captured graphs)
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s);
+hipError_t launch_add_i64(int64_t* p, int64_t v, hipStream_t s);
 // Sum of |amp|^2 over n complex128 values into *out (device double), deterministic.
 hipError_t launch_norm(const double* amps, int64_t n, double* partials, int n_partials,
                        double* out, hipStream_t s);
