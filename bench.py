@@ -65,6 +65,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--samples", type=int, default=1000)
     ap.add_argument("--batch", type=int, default=8, help="slices per launch (hipGraph per batch)")
+    ap.add_argument("--precision", default="c64", choices=["c64", "bf16x3"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); slices would shard "
@@ -80,15 +81,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     t_plan = time.perf_counter()
-    w = config_workload(args.workload, mode="samples" if args.workload == "small" else "default",
-                        trials=2)
+    w = config_workload(args.workload, mode="samples" if args.workload == "small" else "default")
     t_plan = time.perf_counter() - t_plan
     print(f"[bench] planned {args.workload}: {len(w.plan.path)} steps, "
           f"{len(w.plan.sliced_labels)} sliced bonds, {len(w.slice_ids)} slices, "
           f"peak 2^{w.plan.cost.peak_log2:.0f}, {t_plan:.1f} s", file=sys.stderr, flush=True)
     c = Contraction(w.net, w.plan.path, sliced_labels=w.plan.sliced_labels,
                     slice_ids=w.slice_ids, open_qubits=w.open_qubits, closed_bits=w.closed_bits,
-                    max_batch_slices=args.batch)
+                    max_batch_slices=args.batch,
+                    precision={"c64": 0, "bf16x3": 2}[args.precision])
     flops_slice, bytes_slice, n_steps = c.stats()
     flops_inv = sum(l.flops for l in c.launches() if l.invariant)
     flops_step = flops_slice * len(w.slice_ids) + flops_inv
@@ -148,7 +149,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64",
+        "dtype": args.precision,
         "data": "synthetic (seeded Sycamore-like circuit; random gates, no dataset)",
         "config": {
             "workload": {

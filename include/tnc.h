@@ -44,7 +44,13 @@ enum {
 const char* tnc_last_error(void);
 
 /* Arithmetic of the contraction steps.  The slice sum and the sampler are FP64 in every
- * case.  TNC_C64: complex64 operands, FP32 accumulation on the FP32 matrix cores. */
+ * case, and tensors are stored as complex64 in every case.
+ *   TNC_C64     GEMM steps on the FP32 matrix cores, FP32 accumulation.
+ *   TNC_BF16X3  GEMM steps split every operand value x into hi = bf16(x) and
+ *               lo = bf16(x - hi) and accumulate hi*hi + hi*lo + lo*hi in FP32 on the BF16
+ *               matrix cores (about 16 significant bits per operand; BF16 keeps FP32's
+ *               exponent range, so no scaling is needed).
+ *   the FP16 and 3M forms are declared for ABI stability and return TNC_E_UNSUPPORTED. */
 typedef enum {
   TNC_C64 = 0,
   TNC_FP16X3 = 1,
@@ -157,6 +163,44 @@ tnc_status tnc_plan_launch_info(tnc_plan plan, int32_t i, tnc_step_info* info);
 tnc_status tnc_plan_set_timing(tnc_plan plan, int32_t enable);
 tnc_status tnc_plan_timing(tnc_plan plan, double* ms, double* bytes, double* flops,
                            int64_t* launches, int32_t reset);
+
+/* Serving: a request loop on one device with continuous batching.  The caller hands over
+ * one device arena; every submitted request (a network with path, slices and targets set)
+ * is compiled at submission, queued, and admitted first come first served as soon as one of
+ * max_slots slots and a contiguous block of the arena large enough for its footprint
+ * (workspace + amplitude buffer) are free.  Admitted requests each own a HIP stream; the
+ * server enqueues their slices chunk by chunk (chunk_batches slice batches at a time,
+ * alternating between requests), so requests that arrive while others are on the GPU start
+ * as soon as room frees up and their kernels overlap on the device.  The amplitudes of a
+ * request are the same whether it runs alone or among others (same program, same order of
+ * the FP64 sum).  For a given server, calls may come from any host thread.  A request that
+ * fails (a HIP error, an invalid argument found late) fails alone.  tnc_server_destroy
+ * waits for device work already enqueued, then drops queued requests. */
+typedef struct tnc_server_s* tnc_server;
+
+typedef struct {
+  double t_submit, t_admit, t_done;   /* seconds since tnc_server_create (t_done 0 = running) */
+  int64_t n_amplitudes, n_samples, slices;
+  double norm;                         /* sum |amp|^2 of the request's sparse state */
+  double footprint_bytes;
+} tnc_request_info;
+
+/* d_arena: caller-owned device memory (256-byte aligned) the server sub-allocates. */
+tnc_status tnc_server_create(int device, void* d_arena, uint64_t arena_bytes, int32_t max_slots,
+                             int32_t chunk_batches, tnc_server* out);
+/* n_samples: 0 = amplitudes only; one group: any count; several groups: their number.
+ * The network can be destroyed after the call.  TNC_E_OOM if the footprint exceeds the
+ * whole arena (the request could never be admitted). */
+tnc_status tnc_server_submit(tnc_server server, tnc_net net, tnc_precision precision,
+                             int32_t max_batch_slices, int64_t n_samples, uint64_t seed,
+                             uint64_t* request_id);
+/* TNC_E_BUSY while queued or running (info is filled either way).  When finished the
+ * request is retired: h_amps (host, [L][2^n_open] complex128, nullable) and h_bits (host,
+ * [n_samples], nullable) receive the results, and its own status is returned. */
+tnc_status tnc_server_poll(tnc_server server, uint64_t request_id, double* h_amps,
+                           uint64_t* h_bits, tnc_request_info* info);
+tnc_status tnc_server_pending(tnc_server server, int32_t* queued, int32_t* running);
+tnc_status tnc_server_destroy(tnc_server server);
 
 #ifdef __cplusplus
 }

@@ -117,71 +117,141 @@ __device__ __forceinline__ int64_t scatter_bits(int64_t x, const int8_t* pos, in
   return o;
 }
 
+// Tile bookkeeping shared by the GEMM kernels: which output tile, slice, row and K range
+// this workgroup owns, the operand bases of the tile corner, and for every load slot of
+// this thread its fixed (row, col) inside the tile and its scattered element offset.
+// Tile sizes divide a label group whenever the group is larger than the tile, so the
+// corner bits and the in-tile bits never overlap.
+template <int BM, int BN, int BK, bool A_MFAST, bool B_NFAST>
+struct GemmTile {
+  static constexpr int LBM = (BM == 128) ? 7 : (BM == 64 ? 6 : 5);
+  static constexpr int LBN = (BN == 128) ? 7 : (BN == 64 ? 6 : (BN == 32 ? 5 : 4));
+  static constexpr int LBK = (BK == 16) ? 4 : (BK == 32 ? 5 : 3);
+  static constexpr int A_LD = BM * BK / kThreads;
+  static constexpr int B_LD = (BK * BN + kThreads - 1) / kThreads;
+
+  const float2* A;
+  const float2* B;
+  int64_t M, N, m0, n0, k_begin, k_end, zr, sl, r;
+  int ks;
+  int32_t a_off[A_LD], b_off[B_LD];
+  int16_t a_row[A_LD], a_col[A_LD], b_kr[B_LD], b_n[B_LD];
+  bool a_in[A_LD], b_in[B_LD];
+
+  __device__ __forceinline__ bool init(const GemmArgs& a) {
+    M = a.M;
+    N = a.N;
+    const int64_t tiles_m = (M + BM - 1) / BM;
+    const int64_t tiles_n = (N + BN - 1) / BN;
+    const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
+    if (tile >= tiles_m * tiles_n) return false;
+    const int64_t tm = tile % tiles_m, tn = tile / tiles_m;
+    const int64_t z = int64_t(blockIdx.y) + int64_t(blockIdx.z) * gridDim.y;
+    zr = z / a.k_splits;      // slice * rows + row
+    ks = int(z % a.k_splits);
+    if (zr >= a.rows * a.nb) return false;
+    sl = zr / a.rows;
+    r = zr - sl * a.rows;
+    const int64_t ar = a.ga ? a.ga[r] : (a.a_rows == 1 ? 0 : r);
+    const int64_t br = a.gb ? a.gb[r] : (a.b_rows == 1 ? 0 : r);
+    m0 = tm * BM;
+    n0 = tn * BN;
+    const int64_t mloc_mask = (int64_t(1) << a.nm) - 1;
+    A = a.A + sl * a.a_slice_stride + ar * a.a_row_stride +
+        (a.fold ? (m0 >> a.nm) * a.fold_stride : 0) + scatter_bits(m0 & mloc_mask, a.a_mpos, a.nm);
+    B = a.B + sl * a.b_slice_stride + br * a.b_row_stride + scatter_bits(n0, a.b_npos, a.nn);
+    k_begin = int64_t(ks) * a.k_chunk;
+    k_end = (k_begin + a.k_chunk < a.K) ? k_begin + a.k_chunk : a.K;
+    const int nbm = a.nm < LBM ? a.nm : LBM, nbk = a.nk < LBK ? a.nk : LBK;
+    const int nbn = a.nn < LBN ? a.nn : LBN;
+#pragma unroll
+    for (int i = 0; i < A_LD; ++i) {
+      const int q = threadIdx.x + i * kThreads;
+      int row, col;
+      if (A_MFAST) { row = q % BM; col = q / BM; } else { row = q / BK; col = q % BK; }
+      a_off[i] = int32_t(scatter_bits(row, a.a_mpos, nbm) + scatter_bits(col, a.a_kpos, nbk));
+      a_row[i] = int16_t(row);
+      a_col[i] = int16_t(col);
+      a_in[i] = (m0 + row < M);
+    }
+#pragma unroll
+    for (int i = 0; i < B_LD; ++i) {
+      const int q = threadIdx.x + i * kThreads;
+      int kr, n;
+      if (B_NFAST) { kr = q / BN; n = q % BN; } else { n = q / BK; kr = q % BK; }
+      b_off[i] = int32_t(scatter_bits(kr, a.b_kpos, nbk) + scatter_bits(n, a.b_npos, nbn));
+      b_kr[i] = int16_t(kr);
+      b_n[i] = int16_t(n);
+      b_in[i] = (q < BK * BN) && (n0 + n < N);
+    }
+    return true;
+  }
+
+  // global -> registers; out-of-range slots read the tile corner (always valid) and are zeroed
+  __device__ __forceinline__ void load(const GemmArgs& a, int64_t k0, float2* ra, float2* rb) const {
+    const float2* __restrict__ Ak = A + scatter_bits(k0, a.a_kpos, a.nk);
+    const float2* __restrict__ Bk = B + scatter_bits(k0, a.b_kpos, a.nk);
+    const int64_t kl = k_end - k0;
+#pragma unroll
+    for (int i = 0; i < A_LD; ++i) {
+      const bool ok = a_in[i] && a_col[i] < kl;
+      const float2 v = Ak[ok ? a_off[i] : 0];
+      ra[i] = ok ? v : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < B_LD; ++i) {
+      const bool ok = b_in[i] && b_kr[i] < kl;
+      const float2 v = Bk[ok ? b_off[i] : 0];
+      rb[i] = ok ? v : make_float2(0.f, 0.f);
+    }
+  }
+
+  __device__ __forceinline__ float* out(const GemmArgs& a) const {
+    return (a.k_splits > 1)
+               ? reinterpret_cast<float*>(a.partial + (int64_t(ks) * a.rows * a.nb + zr) * M * N)
+               : reinterpret_cast<float*>(a.C + sl * a.c_slice_stride + r * a.c_row_stride);
+  }
+
+  // 32x32 accumulator layout: column = lane % 32, row = 8 (v/4) + 4 (lane/32) + v%4; the
+  // real column j is complex column j/2, real part for even j
+  template <int UM, int UN>
+  __device__ __forceinline__ void store_acc(const GemmArgs& a, const f32x16 (&acc)[UM][UN],
+                                            int wm_base, int wn_base) const {
+    float* o = out(a);
+    const int lane = threadIdx.x & 63, half = lane >> 5, j32 = lane & 31;
+#pragma unroll
+    for (int i = 0; i < UM; ++i)
+#pragma unroll
+      for (int j = 0; j < UN; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int row = wm_base + i * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+          const int64_t m = m0 + row;
+          const int64_t np = n0 + wn_base + j * 16 + (j32 >> 1);
+          if (m < M && np < N) o[(m * N + np) * 2 + (j32 & 1)] = acc[i][j][v];
+        }
+  }
+};
+
 template <int WAVES_M, int WAVES_N, int UM, int UN, int BK, bool A_MFAST, bool B_NFAST>
 __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs a) {
   static_assert(WAVES_M * WAVES_N == 4, "four waves per workgroup");
   constexpr int BM = WAVES_M * UM * 32;
   constexpr int BN = WAVES_N * UN * 16;
-  constexpr int LBM = (BM == 128) ? 7 : (BM == 64 ? 6 : 5);
-  constexpr int LBN = (BN == 64) ? 6 : (BN == 32 ? 5 : 4);
-  constexpr int LBK = (BK == 16) ? 4 : (BK == 32 ? 5 : 3);
+  using Tile = GemmTile<BM, BN, BK, A_MFAST, B_NFAST>;
+  constexpr int A_LD = Tile::A_LD, B_LD = Tile::B_LD;
   constexpr int AS = 2 * BK + 2;       // floats per LDS row of A (m-major)
   constexpr int BS = 2 * BN + 2;       // floats per LDS row of B (k-major)
-  constexpr int A_LD = BM * BK / kThreads;
-  constexpr int B_LD = (BK * BN + kThreads - 1) / kThreads;
-  __shared__ float As[BM * AS];
-  __shared__ float Bs[BK * BS];
+  constexpr int A_STAGE = BM * AS, B_STAGE = BK * BS;
+  // two LDS stages: stage t is read while the tile of stage t+1 is written
+  __shared__ float As[2 * A_STAGE];
+  __shared__ float Bs[2 * B_STAGE];
 
-  const int64_t M = a.M, N = a.N, K = a.K;
-  const int64_t tiles_m = (M + BM - 1) / BM;
-  const int64_t tiles_n = (N + BN - 1) / BN;
-  const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
-  if (tile >= tiles_m * tiles_n) return;
-  const int64_t tm = tile % tiles_m, tn = tile / tiles_m;
-  const int64_t z = int64_t(blockIdx.y) + int64_t(blockIdx.z) * gridDim.y;
-  const int64_t zr = z / a.k_splits;      // slice * rows + row
-  const int ks = int(z % a.k_splits);
-  if (zr >= a.rows * a.nb) return;
-  const int64_t sl = zr / a.rows, r = zr - sl * a.rows;
-  const int64_t ar = a.ga ? a.ga[r] : (a.a_rows == 1 ? 0 : r);
-  const int64_t br = a.gb ? a.gb[r] : (a.b_rows == 1 ? 0 : r);
-  const int64_t m0 = tm * BM, n0 = tn * BN;
-  // block bases: the tile corner's scattered offset (tile sizes divide the group sizes
-  // whenever the group is larger than the tile, so corner and in-tile bits are disjoint)
-  const int64_t mloc_mask = (int64_t(1) << a.nm) - 1;
-  const float2* __restrict__ A = a.A + sl * a.a_slice_stride + ar * a.a_row_stride +
-                                (a.fold ? (m0 >> a.nm) * a.fold_stride : 0) +
-                                scatter_bits(m0 & mloc_mask, a.a_mpos, a.nm);
-  const float2* __restrict__ B =
-      a.B + sl * a.b_slice_stride + br * a.b_row_stride + scatter_bits(n0, a.b_npos, a.nn);
-  const int64_t k_begin = int64_t(ks) * a.k_chunk;
-  const int64_t k_end = (k_begin + a.k_chunk < K) ? k_begin + a.k_chunk : K;
-
+  Tile t;
+  if (!t.init(a)) return;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int wm = wave % WAVES_M, wn = wave / WAVES_M;
-
-  // per-thread load slots: fixed (row, col) inside the tile, fixed scattered offsets
-  int64_t a_off[A_LD], b_off[B_LD];
-  bool a_in[A_LD], b_in[B_LD];
-  const int nbm = a.nm < LBM ? a.nm : LBM, nbk = a.nk < LBK ? a.nk : LBK;
-  const int nbn = a.nn < LBN ? a.nn : LBN;
-#pragma unroll
-  for (int i = 0; i < A_LD; ++i) {
-    const int q = threadIdx.x + i * kThreads;
-    int row, col;
-    if (A_MFAST) { row = q % BM; col = q / BM; } else { row = q / BK; col = q % BK; }
-    a_off[i] = scatter_bits(row, a.a_mpos, nbm) + scatter_bits(col, a.a_kpos, nbk);
-    a_in[i] = (m0 + row < M);
-  }
-#pragma unroll
-  for (int i = 0; i < B_LD; ++i) {
-    const int q = threadIdx.x + i * kThreads;
-    int kr, n;
-    if (B_NFAST) { kr = q / BN; n = q % BN; } else { n = q / BK; kr = q % BK; }
-    b_off[i] = scatter_bits(kr, a.b_kpos, nbk) + scatter_bits(n, a.b_npos, nbn);
-    b_in[i] = (q < BK * BN) && (n0 + n < N);
-  }
 
   f32x16 acc[UM][UN];
 #pragma unroll
@@ -192,89 +262,203 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs a) {
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
 
   float2 ra[A_LD], rb[B_LD];
-  auto load = [&](int64_t k0) {
-    const int64_t ka = scatter_bits(k0, a.a_kpos, a.nk);
-    const int64_t kb = scatter_bits(k0, a.b_kpos, a.nk);
+  auto store = [&](int stage) {
+    float* as = As + stage * A_STAGE;
+    float* bs = Bs + stage * B_STAGE;
 #pragma unroll
-    for (int i = 0; i < A_LD; ++i) {
-      const int q = threadIdx.x + i * kThreads;
-      const int col = A_MFAST ? q / BM : q % BK;
-      float2 v = make_float2(0.f, 0.f);
-      if (a_in[i] && k0 + col < k_end) v = A[ka + a_off[i]];
-      ra[i] = v;
-    }
+    for (int i = 0; i < A_LD; ++i)
+      *reinterpret_cast<float2*>(&as[t.a_row[i] * AS + 2 * t.a_col[i]]) = ra[i];
 #pragma unroll
-    for (int i = 0; i < B_LD; ++i) {
-      const int q = threadIdx.x + i * kThreads;
-      const int kr = B_NFAST ? q / BN : q % BK;
-      float2 v = make_float2(0.f, 0.f);
-      if (b_in[i] && k0 + kr < k_end) v = B[kb + b_off[i]];
-      rb[i] = v;
-    }
-  };
-  auto store = [&]() {
-#pragma unroll
-    for (int i = 0; i < A_LD; ++i) {
-      const int q = threadIdx.x + i * kThreads;
-      int row, col;
-      if (A_MFAST) { row = q % BM; col = q / BM; } else { row = q / BK; col = q % BK; }
-      *reinterpret_cast<float2*>(&As[row * AS + 2 * col]) = ra[i];
-    }
-#pragma unroll
-    for (int i = 0; i < B_LD; ++i) {
-      const int q = threadIdx.x + i * kThreads;
-      if (q >= BK * BN) continue;
-      int kr, n;
-      if (B_NFAST) { kr = q / BN; n = q % BN; } else { n = q / BK; kr = q % BK; }
-      *reinterpret_cast<float2*>(&Bs[kr * BS + 2 * n]) = rb[i];
-    }
+    for (int i = 0; i < B_LD; ++i)
+      if (BK * BN % kThreads == 0 || threadIdx.x + i * kThreads < BK * BN)
+        *reinterpret_cast<float2*>(&bs[t.b_kr[i] * BS + 2 * t.b_n[i]]) = rb[i];
   };
 
   const int half = lane >> 5;          // 0: lanes carry Re(A); 1: lanes carry Im(A)
   const int j32 = lane & 31;
   const int bc = j32 & 1;              // output column parity: 0 = real part, 1 = imaginary
-  if (k_begin < k_end) load(k_begin);
-  for (int64_t k0 = k_begin; k0 < k_end; k0 += BK) {
-    __syncthreads();
-    store();
-    __syncthreads();
-    if (k0 + BK < k_end) load(k0 + BK);
-#pragma unroll 4
+  // real embedding of B: rows (Re k, Im k) x columns (Re n, Im n) -> this lane takes the
+  // imaginary part when its (row, column) parities differ, negated for (Im k, Re n)
+  const bool b_take_im = (half != bc);
+  const float b_sign = (half == 1 && bc == 0) ? -1.f : 1.f;
+  int a_rd[UM], b_rd[UN];
+#pragma unroll
+  for (int i = 0; i < UM; ++i) a_rd[i] = (wm * UM * 32 + i * 32 + j32) * AS + half;
+#pragma unroll
+  for (int j = 0; j < UN; ++j) b_rd[j] = 2 * (wn * UN * 16 + j * 16 + (j32 >> 1));
+
+  int stage = 0;
+  if (t.k_begin < t.k_end) {
+    t.load(a, t.k_begin, ra, rb);
+    store(0);
+  }
+  __syncthreads();
+  for (int64_t k0 = t.k_begin; k0 < t.k_end; k0 += BK) {
+    const bool more = k0 + BK < t.k_end;
+    if (more) t.load(a, k0 + BK, ra, rb);
+    const float* as = As + stage * A_STAGE;
+    const float* bs = Bs + stage * B_STAGE;
+    // fragments double-buffered in registers: step kk+1 is read from LDS before the
+    // matrix-core instructions of step kk are issued
+    float af[2][UM];
+    float2 bv[2][UN];
+#pragma unroll
+    for (int i = 0; i < UM; ++i) af[0][i] = as[a_rd[i]];
+#pragma unroll
+    for (int j = 0; j < UN; ++j) bv[0][j] = *reinterpret_cast<const float2*>(&bs[b_rd[j]]);
+#pragma unroll
     for (int kk = 0; kk < BK; ++kk) {
-      float af[UM], bf[UN];
+      const int cur = kk & 1, nxt = cur ^ 1;
+      if (kk + 1 < BK) {
 #pragma unroll
-      for (int i = 0; i < UM; ++i)
-        af[i] = As[(wm * UM * 32 + i * 32 + j32) * AS + 2 * kk + half];
+        for (int i = 0; i < UM; ++i) af[nxt][i] = as[a_rd[i] + 2 * (kk + 1)];
 #pragma unroll
-      for (int j = 0; j < UN; ++j) {
-        const int np = wn * UN * 16 + j * 16 + (j32 >> 1);
-        const float2 b = *reinterpret_cast<const float2*>(&Bs[kk * BS + 2 * np]);
-        // real embedding of B: rows (Re k, Im k) x columns (Re n, Im n)
-        bf[j] = half == 0 ? (bc == 0 ? b.x : b.y) : (bc == 0 ? -b.y : b.x);
+        for (int j = 0; j < UN; ++j)
+          bv[nxt][j] = *reinterpret_cast<const float2*>(&bs[(kk + 1) * BS + b_rd[j]]);
       }
+      float bf[UN];
+#pragma unroll
+      for (int j = 0; j < UN; ++j) bf[j] = (b_take_im ? bv[cur][j].y : bv[cur][j].x) * b_sign;
+      // keep the reads of step kk+1 ahead of this step's matrix instructions
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int i = 0; i < UM; ++i)
 #pragma unroll
         for (int j = 0; j < UN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[cur][i], bf[j], acc[i][j], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
     }
+    if (more) store(stage ^ 1);
+    __syncthreads();
+    stage ^= 1;
   }
+  t.template store_acc<UM, UN>(a, acc, wm * UM * 32, wn * UN * 16);
+}
 
-  float* out = (a.k_splits > 1)
-                   ? reinterpret_cast<float*>(a.partial + (int64_t(ks) * a.rows * a.nb + zr) * M * N)
-                   : reinterpret_cast<float*>(a.C + sl * a.c_slice_stride + r * a.c_row_stride);
+// ---------------------------------------------------------------------------------
+// split-precision complex GEMM: every FP32 operand value x is split while it is staged
+// into LDS as hi = bf16(x), lo = bf16(x - hi); the product is hi*hi + hi*lo + lo*hi with
+// FP32 accumulation (the lo*lo term, ~2^-16 relative, is dropped).  A is kept as the real
+// M x 2K matrix of its interleaved parts; B is written in LDS directly in its real
+// embedding, transposed so that one lane's eight consecutive K values are contiguous:
+//   column 2n   (real part of C):      (Re B, -Im B) for every complex k
+//   column 2n+1 (imaginary part of C): (Im B,  Re B)
+// One v_mfma_f32_32x32x16_bf16 then consumes 8 complex k for 32 rows x 16 complex columns.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = __bf16(x);
+  lo = __bf16(x - float(hi));
+}
+
+template <int WAVES_M, int WAVES_N, int UM, int UN, bool A_MFAST, bool B_NFAST>
+__global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
+  static_assert(WAVES_M * WAVES_N == 4, "four waves per workgroup");
+  constexpr int BK = 16;                       // complex k per LDS stage (two MFMA steps)
+  constexpr int BM = WAVES_M * UM * 32;
+  constexpr int BN = WAVES_N * UN * 16;
+  using Tile = GemmTile<BM, BN, BK, A_MFAST, B_NFAST>;
+  constexpr int A_LD = Tile::A_LD, B_LD = Tile::B_LD;
+  constexpr int RS = 2 * BK + 8;               // bf16 per LDS row (32 real k + 16 B pad)
+  constexpr int A_PLANE = BM * RS, B_PLANE = 2 * BN * RS;
+  constexpr int STAGE = 2 * A_PLANE + 2 * B_PLANE;   // hi and lo planes of A and B
+  __shared__ __attribute__((aligned(16))) __bf16 lds[2 * STAGE];
+
+  Tile t;
+  if (!t.init(a)) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wm = wave % WAVES_M, wn = wave / WAVES_M;
+
+  f32x16 acc[UM][UN];
 #pragma unroll
   for (int i = 0; i < UM; ++i)
 #pragma unroll
     for (int j = 0; j < UN; ++j)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        // 32x32 accumulator layout: column = lane % 32, row = 8 (v/4) + 4 (lane/32) + v%4
-        const int row = wm * UM * 32 + i * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
-        const int64_t m = m0 + row;
-        const int64_t np = n0 + wn * UN * 16 + j * 16 + (j32 >> 1);
-        if (m < M && np < N) out[(m * N + np) * 2 + bc] = acc[i][j][v];
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
+
+  float2 ra[A_LD], rb[B_LD];
+  auto store = [&](int stage) {
+    __bf16* ah = lds + stage * STAGE;
+    __bf16* al = ah + A_PLANE;
+    __bf16* bh = al + A_PLANE;
+    __bf16* bl = bh + B_PLANE;
+#pragma unroll
+    for (int i = 0; i < A_LD; ++i) {
+      __bf16 h0, l0, h1, l1;
+      split_bf16(ra[i].x, h0, l0);
+      split_bf16(ra[i].y, h1, l1);
+      bf16x2 h, l;
+      h[0] = h0; h[1] = h1; l[0] = l0; l[1] = l1;
+      const int o = t.a_row[i] * RS + 2 * t.a_col[i];
+      *reinterpret_cast<bf16x2*>(&ah[o]) = h;
+      *reinterpret_cast<bf16x2*>(&al[o]) = l;
+    }
+#pragma unroll
+    for (int i = 0; i < B_LD; ++i) {
+      if (!(BK * BN % kThreads == 0 || threadIdx.x + i * kThreads < BK * BN)) continue;
+      __bf16 rh, rl, ih, il;
+      split_bf16(rb[i].x, rh, rl);
+      split_bf16(rb[i].y, ih, il);
+      const int o0 = (2 * t.b_n[i]) * RS + 2 * t.b_kr[i];     // column 2n
+      const int o1 = o0 + RS;                                 // column 2n+1
+      bf16x2 v;
+      v[0] = rh; v[1] = -ih; *reinterpret_cast<bf16x2*>(&bh[o0]) = v;
+      v[0] = ih; v[1] = rh;  *reinterpret_cast<bf16x2*>(&bh[o1]) = v;
+      v[0] = rl; v[1] = -il; *reinterpret_cast<bf16x2*>(&bl[o0]) = v;
+      v[0] = il; v[1] = rl;  *reinterpret_cast<bf16x2*>(&bl[o1]) = v;
+    }
+  };
+
+  const int half = lane >> 5, j32 = lane & 31;
+  int a_rd[UM], b_rd[UN];
+#pragma unroll
+  for (int i = 0; i < UM; ++i) a_rd[i] = (wm * UM * 32 + i * 32 + j32) * RS + 8 * half;
+#pragma unroll
+  for (int j = 0; j < UN; ++j) b_rd[j] = (2 * (wn * UN * 16 + j * 16) + j32) * RS + 8 * half;
+
+  int stage = 0;
+  if (t.k_begin < t.k_end) {
+    t.load(a, t.k_begin, ra, rb);
+    store(0);
+  }
+  __syncthreads();
+  for (int64_t k0 = t.k_begin; k0 < t.k_end; k0 += BK) {
+    const bool more = k0 + BK < t.k_end;
+    if (more) t.load(a, k0 + BK, ra, rb);
+    const __bf16* ah = lds + stage * STAGE;
+    const __bf16* al = ah + A_PLANE;
+    const __bf16* bh = al + A_PLANE;
+    const __bf16* bl = bh + B_PLANE;
+#pragma unroll
+    for (int kstep = 0; kstep < 2; ++kstep) {
+      bf16x8 xah[UM], xal[UM], xbh[UN], xbl[UN];
+#pragma unroll
+      for (int i = 0; i < UM; ++i) {
+        xah[i] = *reinterpret_cast<const bf16x8*>(&ah[a_rd[i] + 16 * kstep]);
+        xal[i] = *reinterpret_cast<const bf16x8*>(&al[a_rd[i] + 16 * kstep]);
       }
+#pragma unroll
+      for (int j = 0; j < UN; ++j) {
+        xbh[j] = *reinterpret_cast<const bf16x8*>(&bh[b_rd[j] + 16 * kstep]);
+        xbl[j] = *reinterpret_cast<const bf16x8*>(&bl[b_rd[j] + 16 * kstep]);
+      }
+#pragma unroll
+      for (int i = 0; i < UM; ++i)
+#pragma unroll
+        for (int j = 0; j < UN; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xal[i], xbh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xah[i], xbl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xah[i], xbh[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    if (more) store(stage ^ 1);
+    __syncthreads();
+    stage ^= 1;
+  }
+  t.template store_acc<UM, UN>(a, acc, wm * UM * 32, wn * UN * 16);
 }
 
 __global__ __launch_bounds__(kThreads) void k_reduce(ReduceArgs a) {
@@ -500,14 +684,22 @@ hipError_t launch_gemm_cfg(const GemmArgs& a, hipStream_t s) {
   const int64_t gy = zs < 65535 ? zs : 65535;
   const int64_t gz = (zs + gy - 1) / gy;
   const dim3 grid{unsigned(tiles), unsigned(gy), unsigned(gz)};
-  if (!a.a_mfast && !a.b_nfast)
-    hipLaunchKernelGGL((k_gemm<WM, WN, UM, UN, BK, false, false>), grid, dim3(kThreads), 0, s, a);
-  else if (a.a_mfast && !a.b_nfast)
-    hipLaunchKernelGGL((k_gemm<WM, WN, UM, UN, BK, true, false>), grid, dim3(kThreads), 0, s, a);
-  else if (!a.a_mfast && a.b_nfast)
-    hipLaunchKernelGGL((k_gemm<WM, WN, UM, UN, BK, false, true>), grid, dim3(kThreads), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_gemm<WM, WN, UM, UN, BK, true, true>), grid, dim3(kThreads), 0, s, a);
+  const int sel = (a.a_mfast ? 1 : 0) | (a.b_nfast ? 2 : 0);
+  if (a.precision == 0) {
+    switch (sel) {
+      case 0: hipLaunchKernelGGL((k_gemm<WM, WN, UM, UN, BK, false, false>), grid, dim3(kThreads), 0, s, a); break;
+      case 1: hipLaunchKernelGGL((k_gemm<WM, WN, UM, UN, BK, true, false>), grid, dim3(kThreads), 0, s, a); break;
+      case 2: hipLaunchKernelGGL((k_gemm<WM, WN, UM, UN, BK, false, true>), grid, dim3(kThreads), 0, s, a); break;
+      default: hipLaunchKernelGGL((k_gemm<WM, WN, UM, UN, BK, true, true>), grid, dim3(kThreads), 0, s, a); break;
+    }
+  } else {
+    switch (sel) {
+      case 0: hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, false, false>), grid, dim3(kThreads), 0, s, a); break;
+      case 1: hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, true, false>), grid, dim3(kThreads), 0, s, a); break;
+      case 2: hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, false, true>), grid, dim3(kThreads), 0, s, a); break;
+      default: hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, true, true>), grid, dim3(kThreads), 0, s, a); break;
+    }
+  }
   return hipGetLastError();
 }
 
@@ -527,12 +719,14 @@ hipError_t launch_stream(const StreamArgs& a, hipStream_t s) {
 }
 
 // Tile configurations (complex elements): 0 = 128 x 64 (2x2 waves, 2x2 MFMA tiles each),
-// 1 = 128 x 16 (4x1 waves, one MFMA tile each), 2 = 64 x 32 (2x2 waves, one tile each).
+// 1 = 128 x 16 (4x1 waves, one MFMA tile each), 2 = 64 x 32 (2x2 waves, one tile each),
+// 3 = 128 x 128 (2x2 waves, 2x4 MFMA tiles each).
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t s) {
   switch (a.config) {
     case 0: return launch_gemm_cfg<2, 2, 2, 2, 16>(a, s);
     case 1: return launch_gemm_cfg<4, 1, 1, 1, 16>(a, s);
     case 2: return launch_gemm_cfg<2, 2, 1, 1, 16>(a, s);
+    case 3: return launch_gemm_cfg<2, 2, 2, 4, 16>(a, s);
   }
   return hipErrorInvalidValue;
 }

@@ -15,14 +15,19 @@
 #include "tnc.h"
 
 #include <algorithm>
+#include <chrono>
 #include <climits>
+#include <condition_variable>
+#include <deque>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <set>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -375,7 +380,8 @@ struct Compiler {
     const int64_t target = blocks_env ? std::atoll(blocks_env) : 2048;
     g.config = (N <= 16) ? 1 : ((M <= 64 || N <= 32) ? 2 : 0);
     if (force) g.config = std::atoi(force);
-    const int64_t BM = g.config == 2 ? 64 : 128, BN = g.config == 0 ? 64 : (g.config == 1 ? 16 : 32);
+    static const int64_t kBM[4] = {128, 128, 64, 128}, kBN[4] = {64, 16, 32, 128};
+    const int64_t BM = kBM[g.config], BN = kBN[g.config];
     const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN) * rows;
     g.k_splits = 1;
     g.k_chunk = Kd;
@@ -516,6 +522,7 @@ struct Compiler {
     g.rows = rows;
     g.c_row_stride = M * N;
     choose_tiles(g, M, N, Kd, rows);
+    g.precision = (plan.precision == TNC_BF16X3) ? 1 : 0;
     C.dense = cat(MP, NQ);
     C.buf = new_buf(uint64_t(C.elems()) * 8, false, C.dep);
     g.a_slice_stride = sstride(pbuf);
@@ -805,12 +812,16 @@ struct Exec {
     p.uploaded_ws = ws;
   }
 
-  void contract(double* amps, int64_t first, int64_t count, bool accumulate) {
+  // skip_invariant: the slice-invariant results already sit in this workspace from an
+  // earlier call with the same workspace (their buffers are never reused by slice steps)
+  void contract(double* amps, int64_t first, int64_t count, bool accumulate,
+                bool skip_invariant = false) {
     upload();
     const int64_t n_amp = p.L << p.n_open;
     if (!accumulate) check(launch_fill_zero(amps, 2 * n_amp, s));
     if (count <= 0) return;
-    for (auto& L : p.inv) launch(L, 1, amps, s, p.timing);
+    if (!skip_invariant)
+      for (auto& L : p.inv) launch(L, 1, amps, s, p.timing);
     check(launch_set_i64(counter(), first, s));
     const int64_t S = p.batch;
     const int64_t full = count / S, rest = count % S;
@@ -850,6 +861,66 @@ void harvest(tnc_plan_s& p) {
   p.ev_used = 0;
 }
 
+// Draws of tnc_sample; synchronous on `st`.
+void sample_into(tnc_plan_s& p, uint8_t* ws, const double* amps, uint64_t seed, int64_t n_samples,
+                 uint64_t* h_bits, hipStream_t st) {
+  if (n_samples < 0) fail(TNC_E_INVALID, "negative sample count");
+  if (p.L > 1 && n_samples != p.L)
+    fail(TNC_E_INVALID, "with several groups, n_samples must equal the number of groups");
+  Exec e{p, ws, st};
+  e.upload();
+  double* cum = reinterpret_cast<double*>(ws + p.bufs[p.b_cum].off);
+  uint64_t* dout = reinterpret_cast<uint64_t*>(ws + p.bufs[p.b_samples].off);
+  const uint64_t* closed = reinterpret_cast<const uint64_t*>(ws + p.closed_off);
+  const int32_t* openq = reinterpret_cast<const int32_t*>(ws + p.open_off);
+  if (p.L > 1) {
+    hipError_t err = launch_sample(amps, p.L, p.n_open, closed, openq, p.n_qubits, seed, p.L, cum,
+                                   dout, st);
+    if (err != hipSuccess) fail(TNC_E_HIP, hipGetErrorString(err));
+    HIPCHK(hipMemcpyAsync(h_bits, dout, uint64_t(p.L) * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return;
+  }
+  // one group: draws j = 0..n-1 in chunks (the draw index keeps counting across chunks)
+  for (int64_t done = 0; done < n_samples; done += p.sample_chunk) {
+    const int64_t c = std::min(p.sample_chunk, n_samples - done);
+    // shift the counter: uniform j uses state seed + (j + 1) gamma
+    const uint64_t seed_c = seed + uint64_t(done) * 0x9E3779B97F4A7C15ull;
+    hipError_t err = launch_sample(amps, 1, p.n_open, closed, openq, p.n_qubits, seed_c, c, cum,
+                                   dout, st);
+    if (err != hipSuccess) fail(TNC_E_HIP, hipGetErrorString(err));
+    HIPCHK(hipMemcpyAsync(h_bits + done, dout, uint64_t(c) * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+}
+
+tnc_plan_s* make_plan(tnc_net_s& net, tnc_precision precision, int32_t max_batch) {
+  if (!net.has_path && net.labels.size() > 1) fail(TNC_E_INVALID, "no path set");
+  if (!net.has_targets) fail(TNC_E_INVALID, "no targets set");
+  if (precision != TNC_C64 && precision != TNC_BF16X3)
+    fail(TNC_E_UNSUPPORTED, "implemented precisions: TNC_C64, TNC_BF16X3");
+  if (max_batch < 1) fail(TNC_E_INVALID, "max_batch_slices must be >= 1");
+  auto* p = new tnc_plan_s();
+  try {
+    p->device = net.device;
+    p->n_qubits = net.n_qubits;
+    p->precision = precision;
+    p->L = int64_t(net.closed.size());
+    p->n_open = int(net.open.size());
+    p->open = net.open;
+    p->closed = net.closed;
+    p->slice_ids = net.slice_ids;
+    p->batch = std::max<int32_t>(1, std::min<int32_t>(max_batch, int32_t(net.slice_ids.size())));
+    Compiler c(net, *p);
+    c.run();
+    pack(*p);
+  } catch (...) {
+    delete p;
+    throw;
+  }
+  return p;
+}
+
 struct DeviceGuard {
   int prev = -1;
   explicit DeviceGuard(int dev) {
@@ -863,6 +934,213 @@ struct DeviceGuard {
 };
 
 }  // namespace
+
+
+// ------------------------------------------------------------------------------------
+// serving: continuous batching of contraction requests on one device
+namespace {
+
+enum ReqState { R_QUEUED, R_RUNNING, R_DONE, R_FAILED };
+
+struct Request {
+  uint64_t id = 0;
+  tnc_plan_s* plan = nullptr;
+  int64_t n_samples = 0;
+  uint64_t seed = 0;
+  uint64_t ws_bytes = 0, amps_bytes = 0, footprint = 0, off = 0;
+  int slot = -1;
+  int64_t next = 0, total = 0;
+  std::deque<hipEvent_t> chunks;        // chunks in flight, oldest first
+  ReqState state = R_QUEUED;
+  std::vector<double> amps;
+  std::vector<uint64_t> bits;
+  double norm = 0, t_submit = 0, t_admit = 0, t_done = 0;
+  tnc_status code = TNC_OK;
+  std::string err;
+  ~Request() { delete plan; }
+};
+
+}  // namespace
+
+struct tnc_server_s {
+  int device = 0;
+  uint8_t* arena = nullptr;
+  uint64_t arena_bytes = 0;
+  int max_slots = 1;
+  int chunk_batches = 4;
+  std::map<uint64_t, uint64_t> free_list;     // arena offset -> bytes
+  std::vector<hipStream_t> streams;
+  std::vector<bool> slot_busy;
+  std::vector<hipEvent_t> ev_free;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Request*> pending;
+  std::vector<Request*> active;
+  std::map<uint64_t, Request*> all;
+  uint64_t next_id = 1;
+  bool stop = false;
+  std::thread worker;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+
+  double now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+
+  bool alloc(uint64_t bytes, uint64_t* off) {
+    for (auto it = free_list.begin(); it != free_list.end(); ++it) {
+      if (it->second < bytes) continue;
+      *off = it->first;
+      const uint64_t rest = it->second - bytes, at = it->first + bytes;
+      free_list.erase(it);
+      if (rest) free_list[at] = rest;
+      return true;
+    }
+    return false;
+  }
+
+  void release(uint64_t off, uint64_t bytes) {
+    auto it = free_list.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_list.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_list.erase(nx);
+    }
+    if (it != free_list.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_list.erase(it);
+      }
+    }
+  }
+
+  hipEvent_t get_event() {
+    if (!ev_free.empty()) {
+      hipEvent_t e = ev_free.back();
+      ev_free.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return e;
+  }
+
+  // enqueue the next chunk of slices, or finish the request once every chunk has completed
+  bool step(Request& r) {
+    bool did = false;
+    while (!r.chunks.empty() && hipEventQuery(r.chunks.front()) == hipSuccess) {
+      ev_free.push_back(r.chunks.front());
+      r.chunks.pop_front();
+      did = true;
+    }
+    uint8_t* ws = arena + r.off;
+    double* amps = reinterpret_cast<double*>(ws + align_up(r.ws_bytes));
+    hipStream_t st = streams[r.slot];
+    if (r.next < r.total && r.chunks.size() < 2) {
+      const int64_t count = std::min<int64_t>(int64_t(chunk_batches) * r.plan->batch, r.total - r.next);
+      Exec e{*r.plan, ws, st};
+      e.contract(amps, r.next, count, r.next > 0, r.next > 0);
+      hipEvent_t ev = get_event();
+      HIPCHK(hipEventRecord(ev, st));
+      r.chunks.push_back(ev);
+      r.next += count;
+      did = true;
+    }
+    if (r.next >= r.total && r.chunks.empty()) {
+      const int64_t n_amp = r.plan->L << r.plan->n_open;
+      r.amps.resize(size_t(2 * n_amp));
+      if (r.n_samples > 0) {
+        r.bits.resize(size_t(r.n_samples));
+        sample_into(*r.plan, ws, amps, r.seed, r.n_samples, r.bits.data(), st);
+      }
+      HIPCHK(hipMemcpyAsync(r.amps.data(), amps, uint64_t(n_amp) * 16, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      double nrm = 0;
+      for (double x : r.amps) nrm += x * x;
+      r.norm = nrm;
+      r.state = R_DONE;
+      did = true;
+    }
+    return did;
+  }
+
+  void retire_from_active(Request* r) {
+    // caller holds mu
+    release(r->off, r->footprint);
+    slot_busy[r->slot] = false;
+    for (auto e : r->chunks) ev_free.push_back(e);
+    r->chunks.clear();
+    r->t_done = now();
+    active.erase(std::find(active.begin(), active.end(), r));
+  }
+
+  void run() {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    while (true) {
+      if (stop) break;
+      // admission: first come first served, while a slot and a large enough block exist
+      while (!pending.empty() && int(active.size()) < max_slots) {
+        Request* r = pending.front();
+        uint64_t off;
+        if (!alloc(r->footprint, &off)) break;
+        pending.pop_front();
+        r->off = off;
+        for (int k = 0; k < max_slots; ++k)
+          if (!slot_busy[k]) { r->slot = k; slot_busy[k] = true; break; }
+        r->state = R_RUNNING;
+        r->t_admit = now();
+        active.push_back(r);
+      }
+      if (active.empty()) {
+        cv.wait(lk, [&] { return stop || !pending.empty(); });
+        continue;
+      }
+      std::vector<Request*> act = active;
+      lk.unlock();
+      bool did = false;
+      std::vector<Request*> finished;
+      for (Request* r : act) {
+        try {
+          did |= step(*r);
+        } catch (const Error& e) {
+          r->state = R_FAILED;
+          r->code = e.code;
+          r->err = e.msg;
+          (void)hipStreamSynchronize(streams[r->slot]);
+        } catch (const std::exception& e) {
+          r->state = R_FAILED;
+          r->code = TNC_E_INTERNAL;
+          r->err = e.what();
+          (void)hipStreamSynchronize(streams[r->slot]);
+        }
+        if (r->state == R_DONE || r->state == R_FAILED) finished.push_back(r);
+      }
+      lk.lock();
+      for (Request* r : finished) retire_from_active(r);
+      if (!finished.empty()) cv.notify_all();
+      if (!did && finished.empty()) {
+        lk.unlock();
+        std::this_thread::sleep_for(std::chrono::microseconds(50));
+        lk.lock();
+      }
+    }
+    // shutting down: let queued device work finish before the arena goes away
+    for (auto st : streams) (void)hipStreamSynchronize(st);
+  }
+
+  ~tnc_server_s() {
+    {
+      std::lock_guard<std::mutex> g(mu);
+      stop = true;
+    }
+    cv.notify_all();
+    if (worker.joinable()) worker.join();
+    for (auto& kv : all) delete kv.second;
+    for (auto e : ev_free) (void)hipEventDestroy(e);
+    for (auto st : streams) (void)hipStreamDestroy(st);
+  }
+};
 
 // ------------------------------------------------------------------------------------
 // C ABI
@@ -1001,29 +1279,7 @@ tnc_status tnc_plan_create(tnc_net net, tnc_precision precision, int32_t max_bat
   return guard([&] {
     if (!net || !out) fail(TNC_E_INVALID, "null argument");
     *out = nullptr;
-    if (!net->has_path && net->labels.size() > 1) fail(TNC_E_INVALID, "no path set");
-    if (!net->has_targets) fail(TNC_E_INVALID, "no targets set");
-    if (precision != TNC_C64) fail(TNC_E_UNSUPPORTED, "only TNC_C64 is implemented");
-    if (max_batch < 1) fail(TNC_E_INVALID, "max_batch_slices must be >= 1");
-    auto* p = new tnc_plan_s();
-    try {
-      p->device = net->device;
-      p->n_qubits = net->n_qubits;
-      p->precision = precision;
-      p->L = int64_t(net->closed.size());
-      p->n_open = int(net->open.size());
-      p->open = net->open;
-      p->closed = net->closed;
-      p->slice_ids = net->slice_ids;
-      p->batch = std::max<int32_t>(1, std::min<int32_t>(max_batch, int32_t(net->slice_ids.size())));
-      Compiler c(*net, *p);
-      c.run();
-      pack(*p);
-    } catch (...) {
-      delete p;
-      throw;
-    }
-    *out = p;
+    *out = make_plan(*net, precision, max_batch);
   });
 }
 
@@ -1087,35 +1343,9 @@ tnc_status tnc_sample(tnc_plan p, void* ws, uint64_t ws_bytes, const double* amp
   return guard([&] {
     if (!p || !amps || (n_samples > 0 && !h_bits)) fail(TNC_E_INVALID, "null argument");
     check_ws(p, ws, ws_bytes);
-    if (n_samples < 0) fail(TNC_E_INVALID, "negative sample count");
-    if (p->L > 1 && n_samples != p->L)
-      fail(TNC_E_INVALID, "with several groups, n_samples must equal the number of groups");
     DeviceGuard dg(p->device);
-    Exec e{*p, static_cast<uint8_t*>(ws), static_cast<hipStream_t>(stream)};
-    e.upload();
-    double* cum = reinterpret_cast<double*>(e.ws + p->bufs[p->b_cum].off);
-    uint64_t* dout = reinterpret_cast<uint64_t*>(e.ws + p->bufs[p->b_samples].off);
-    const uint64_t* closed = reinterpret_cast<const uint64_t*>(e.ws + p->closed_off);
-    const int32_t* openq = reinterpret_cast<const int32_t*>(e.ws + p->open_off);
-    if (p->L > 1) {
-      hipError_t err = launch_sample(amps, p->L, p->n_open, closed, openq, p->n_qubits, seed, p->L,
-                                     cum, dout, e.s);
-      if (err != hipSuccess) fail(TNC_E_HIP, hipGetErrorString(err));
-      HIPCHK(hipMemcpyAsync(h_bits, dout, uint64_t(p->L) * 8, hipMemcpyDeviceToHost, e.s));
-      HIPCHK(hipStreamSynchronize(e.s));
-      return;
-    }
-    // one group: draws j = 0..n-1 in chunks (the draw index keeps counting across chunks)
-    for (int64_t done = 0; done < n_samples; done += p->sample_chunk) {
-      const int64_t c = std::min(p->sample_chunk, n_samples - done);
-      // shift the counter: uniform j uses state seed + (j + 1) gamma
-      const uint64_t seed_c = seed + uint64_t(done) * 0x9E3779B97F4A7C15ull;
-      hipError_t err = launch_sample(amps, 1, p->n_open, closed, openq, p->n_qubits, seed_c, c, cum,
-                                     dout, e.s);
-      if (err != hipSuccess) fail(TNC_E_HIP, hipGetErrorString(err));
-      HIPCHK(hipMemcpyAsync(h_bits + done, dout, uint64_t(c) * 8, hipMemcpyDeviceToHost, e.s));
-      HIPCHK(hipStreamSynchronize(e.s));
-    }
+    sample_into(*p, static_cast<uint8_t*>(ws), amps, seed, n_samples, h_bits,
+                static_cast<hipStream_t>(stream));
   });
 }
 
@@ -1171,4 +1401,126 @@ tnc_status tnc_plan_timing(tnc_plan p, double* ms, double* bytes, double* flops,
   });
 }
 
+
+tnc_status tnc_server_create(int device, void* d_arena, uint64_t arena_bytes, int32_t max_slots,
+                             int32_t chunk_batches, tnc_server* out) {
+  return guard([&] {
+    if (!out || !d_arena) fail(TNC_E_INVALID, "null argument");
+    *out = nullptr;
+    if (max_slots < 1 || max_slots > 64) fail(TNC_E_INVALID, "max_slots must be in [1, 64]");
+    if (chunk_batches < 1) fail(TNC_E_INVALID, "chunk_batches must be >= 1");
+    if (reinterpret_cast<uintptr_t>(d_arena) % kAlign) fail(TNC_E_INVALID, "arena must be 256-byte aligned");
+    DeviceGuard dg(device);
+    auto* s = new tnc_server_s();
+    try {
+      s->device = device;
+      s->arena = static_cast<uint8_t*>(d_arena);
+      s->arena_bytes = arena_bytes / kAlign * kAlign;
+      s->max_slots = max_slots;
+      s->chunk_batches = chunk_batches;
+      s->free_list[0] = s->arena_bytes;
+      s->slot_busy.assign(size_t(max_slots), false);
+      for (int k = 0; k < max_slots; ++k) {
+        hipStream_t st;
+        HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        s->streams.push_back(st);
+      }
+      s->worker = std::thread([s] { s->run(); });
+    } catch (...) {
+      delete s;
+      throw;
+    }
+    *out = s;
+  });
+}
+
+tnc_status tnc_server_submit(tnc_server s, tnc_net net, tnc_precision precision,
+                             int32_t max_batch_slices, int64_t n_samples, uint64_t seed,
+                             uint64_t* request_id) {
+  return guard([&] {
+    if (!s || !net || !request_id) fail(TNC_E_INVALID, "null argument");
+    auto* r = new Request();
+    try {
+      r->plan = make_plan(*net, precision, max_batch_slices);
+      if (n_samples < 0) fail(TNC_E_INVALID, "negative sample count");
+      if (r->plan->L > 1 && n_samples != 0 && n_samples != r->plan->L)
+        fail(TNC_E_INVALID, "with several groups, n_samples must be 0 or the number of groups");
+      r->n_samples = n_samples;
+      r->seed = seed;
+      r->ws_bytes = r->plan->ws_bytes;
+      r->amps_bytes = uint64_t(r->plan->L << r->plan->n_open) * 16;
+      r->footprint = align_up(r->ws_bytes) + align_up(r->amps_bytes);
+      r->total = int64_t(r->plan->slice_ids.size());
+      if (r->footprint > s->arena_bytes)
+        fail(TNC_E_OOM, "request needs " + std::to_string(r->footprint) + " bytes, arena has " +
+                            std::to_string(s->arena_bytes));
+    } catch (...) {
+      delete r;
+      throw;
+    }
+    {
+      std::lock_guard<std::mutex> g(s->mu);
+      r->id = s->next_id++;
+      r->t_submit = s->now();
+      s->all[r->id] = r;
+      s->pending.push_back(r);
+    }
+    s->cv.notify_all();
+    *request_id = r->id;
+  });
+}
+
+tnc_status tnc_server_poll(tnc_server s, uint64_t id, double* h_amps, uint64_t* h_bits,
+                           tnc_request_info* info) {
+  Request* done = nullptr;
+  tnc_status st = guard([&] {
+    if (!s) fail(TNC_E_INVALID, "null server");
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->all.find(id);
+    if (it == s->all.end()) fail(TNC_E_NOT_FOUND, "unknown request id");
+    Request* r = it->second;
+    // t_done is written under the lock when the worker retires the request; everything
+    // the worker wrote before that is visible from here on
+    const bool finished = r->t_done != 0;
+    if (info) {
+      info->t_submit = r->t_submit;
+      info->t_admit = r->t_admit;
+      info->t_done = r->t_done;
+      info->n_amplitudes = r->plan->L << r->plan->n_open;
+      info->n_samples = r->n_samples;
+      info->norm = finished ? r->norm : 0.0;
+      info->slices = r->total;
+      info->footprint_bytes = double(r->footprint);
+    }
+    if (!finished) fail(TNC_E_BUSY, "request not finished");
+    s->all.erase(it);
+    done = r;
+  });
+  if (st != TNC_OK) return st;
+  if (done->state == R_FAILED) {
+    g_err = done->err;
+    const tnc_status code = done->code;
+    delete done;
+    return code;
+  }
+  if (h_amps) std::memcpy(h_amps, done->amps.data(), done->amps.size() * sizeof(double));
+  if (h_bits && !done->bits.empty()) std::memcpy(h_bits, done->bits.data(), done->bits.size() * 8);
+  delete done;
+  return TNC_OK;
+}
+
+tnc_status tnc_server_pending(tnc_server s, int32_t* queued, int32_t* running) {
+  return guard([&] {
+    if (!s) fail(TNC_E_INVALID, "null server");
+    std::lock_guard<std::mutex> g(s->mu);
+    if (queued) *queued = int32_t(s->pending.size());
+    if (running) *running = int32_t(s->active.size());
+  });
+}
+
+tnc_status tnc_server_destroy(tnc_server s) {
+  return guard([&] { delete s; });
+}
+
 }  // extern "C"
+

@@ -59,6 +59,7 @@ struct GemmArgs {
   int64_t k_chunk;
   float2* partial;
   int config;                 // tile configuration id
+  int precision;              // 0: complex64 on FP32 MFMA; 1: BF16 hi+lo split, FP32 accumulate
 };
 
 struct ReduceArgs {           // C[i] = sum_s partial[s][i]  (i over every slice of the launch)

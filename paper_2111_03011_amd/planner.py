@@ -240,11 +240,13 @@ def _step_operands(prob: Problem, path):
 
 def choose_slices(prob: Problem, path, max_log2: float, exact: int | None = None,
                   forbidden: int = 0):
-    """Bond bits to slice along a fixed path (greedy): returns a bitset of label bits."""
+    """Bond bits to slice along a fixed path (greedy): returns a bitset of label bits.
+
+    Each round adds the bond that, once sliced, gives the smallest largest intermediate
+    (while the bound is not met) and then the smallest total cost over all slices.  Slicing
+    bond b halves every intermediate and every step that carries b, so both figures are
+    computed for all candidates at once from incidence matrices."""
     ops = _step_operands(prob, path)
-    leaves = list(zip(prob.dense, prob.qmask))
-    chosen = 0
-    # candidates: labels shared by two leaves (bonds); closed legs are never dense
     counts = {}
     for d in prob.dense:
         x = d
@@ -253,35 +255,33 @@ def choose_slices(prob: Problem, path, max_log2: float, exact: int | None = None
             counts[b] = counts.get(b, 0) + 1
             x ^= b
     cands = [b for b, c in counts.items() if c == 2 and not (b & forbidden)]
-
-    def peak_and_cost(mask):
-        peak = 0.0
-        for d, q in leaves:
-            peak = max(peak, math.log2(prob.rows(q)) + _popcount(d & ~mask))
-        cost = 0.0
-        for union, q, out in ops:
-            peak = max(peak, math.log2(prob.rows(q)) + _popcount(out & ~mask))
-            cost += prob.rows(q) * float(1 << _popcount(union & ~mask))
-        return peak, cost * (1 << _popcount(mask))
-
-    cur_peak, _ = peak_and_cost(0)
+    if not cands:
+        return 0, max((math.log2(prob.rows(q)) + _popcount(d) for d, q in zip(prob.dense, prob.qmask)), default=0.0)
+    inter = list(zip(prob.dense, prob.qmask)) + [(out, q) for _, q, out in ops]
+    O = np.array([[bool(d & b) for b in cands] for d, _ in inter], dtype=np.float64)
+    U = np.array([[bool(u & b) for b in cands] for u, _, _ in ops], dtype=np.float64)
+    ls = np.array([math.log2(prob.rows(q)) + _popcount(d) for d, q in inter])
+    lc = np.array([math.log2(prob.rows(q)) + _popcount(u) for u, q, _ in ops])
+    taken = np.zeros(len(cands), dtype=bool)
+    chosen, k = 0, 0
+    cur_peak = float(ls.max())
     while True:
-        k = _popcount(chosen)
         need_more = cur_peak > max_log2 + 1e-9 or (exact is not None and k < exact)
-        if not need_more or (exact is not None and k >= exact):
+        if not need_more or (exact is not None and k >= exact) or taken.all():
             break
-        best = None
-        for b in cands:
-            if b & chosen:
-                continue
-            pk, cost = peak_and_cost(chosen | b)
-            key = (max(pk, max_log2) if cur_peak > max_log2 else 0.0, cost, pk)
-            if best is None or key < best[0]:
-                best = (key, b, pk)
-        if best is None:
-            break
-        chosen |= best[1]
-        cur_peak = best[2]
+        ct = np.exp2(lc)
+        new_cost = (2.0 ** (k + 1)) * (ct.sum() - 0.5 * (ct @ U))
+        new_peak = (ls[:, None] - O).max(axis=0)
+        first = np.maximum(new_peak, max_log2) if cur_peak > max_log2 + 1e-9 else np.zeros_like(new_peak)
+        first = np.where(taken, np.inf, first)
+        order = np.lexsort((new_peak, new_cost, first))
+        c = int(order[0])
+        chosen |= cands[c]
+        taken[c] = True
+        ls = ls - O[:, c]
+        lc = lc - U[:, c]
+        k += 1
+        cur_peak = float(ls.max())
     return chosen, cur_peak
 
 
@@ -299,7 +299,7 @@ class Plan:
 
 def find_plan(net, open_qubits, closed_bits, max_log2: float = 26.0,
               n_sliced: int | None = None, trials: int = 16, seed: int = 0,
-              temperature: float = 0.3, rounds: int = 2) -> Plan:
+              temperature: float = 0.05, rounds: int = 2) -> Plan:
     """Random-greedy search of (path, sliced bonds) under the size bound.
 
     n_sliced=None slices as few bonds as the bound needs; an int asks for exactly that
@@ -345,3 +345,16 @@ def find_plan(net, open_qubits, closed_bits, max_log2: float = 26.0,
     if best is None:
         raise RuntimeError("no plan met the size bound; raise trials or the bound")
     return best
+
+
+def validate_path(n_tensors: int, pairs):
+    """Check a path in the (i, j) -> i format (Appendix E) against n_tensors leaves: every
+    pair names two distinct live tensors.  Returns the ids still alive at the end."""
+    alive = [True] * n_tensors
+    for step, (i, j) in enumerate(pairs):
+        if not (0 <= i < n_tensors and 0 <= j < n_tensors) or i == j:
+            raise ValueError(f"step {step}: invalid pair {(i, j)}")
+        if not (alive[i] and alive[j]):
+            raise ValueError(f"step {step}: pair {(i, j)} uses a retired tensor")
+        alive[j] = False
+    return [k for k in range(n_tensors) if alive[k]]

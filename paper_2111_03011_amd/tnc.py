@@ -34,6 +34,8 @@ EXPORTS = (
     "tnc_net_set_targets", "tnc_plan_create", "tnc_plan_workspace_bytes", "tnc_plan_stats",
     "tnc_contract", "tnc_contract_range", "tnc_sample", "tnc_plan_destroy", "tnc_net_destroy",
     "tnc_plan_n_launches", "tnc_plan_launch_info", "tnc_plan_set_timing", "tnc_plan_timing",
+    "tnc_server_create", "tnc_server_submit", "tnc_server_poll", "tnc_server_pending",
+    "tnc_server_destroy",
 )
 
 
@@ -53,6 +55,13 @@ class StepInfo(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("invariant", ctypes.c_int32),
                 ("rows", ctypes.c_int64), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
                 ("k", ctypes.c_int64), ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("n_amplitudes", ctypes.c_int64),
+                ("n_samples", ctypes.c_int64), ("slices", ctypes.c_int64),
+                ("norm", ctypes.c_double), ("footprint_bytes", ctypes.c_double)]
 
 
 _lib = None
@@ -84,6 +93,11 @@ def lib() -> ctypes.CDLL:
             "tnc_plan_launch_info": (_I32, [_P, _I32, ctypes.POINTER(StepInfo)]),
             "tnc_plan_set_timing": (_I32, [_P, _I32]),
             "tnc_plan_timing": (_I32, [_P, _P, _P, _P, _P, _I32]),
+            "tnc_server_create": (_I32, [ctypes.c_int, _P, _U64, _I32, _I32, ctypes.POINTER(_P)]),
+            "tnc_server_submit": (_I32, [_P, _P, ctypes.c_int, _I32, _I64, _U64, ctypes.POINTER(_U64)]),
+            "tnc_server_poll": (_I32, [_P, _U64, _P, _P, ctypes.POINTER(RequestInfo)]),
+            "tnc_server_pending": (_I32, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+            "tnc_server_destroy": (_I32, [_P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(l, name)
@@ -205,3 +219,43 @@ def tnc_plan_timing(plan: int, reset: bool = False):
                                  fl.ctypes.data_as(_P), n.ctypes.data_as(_P), 1 if reset else 0))
     return {KIND_NAMES[k]: {"ms": float(ms[k]), "bytes": float(by[k]), "flops": float(fl[k]),
                             "launches": int(n[k])} for k in range(6)}
+
+
+def tnc_server_create(device: int, arena: int, arena_bytes: int, max_slots: int,
+                      chunk_batches: int) -> int:
+    h = _P()
+    _check(lib().tnc_server_create(device, arena, arena_bytes, max_slots, chunk_batches,
+                                   ctypes.byref(h)))
+    return h.value
+
+
+def tnc_server_submit(server: int, net: int, precision: int, max_batch_slices: int,
+                      n_samples: int, seed: int) -> int:
+    rid = _U64()
+    _check(lib().tnc_server_submit(server, net, precision, max_batch_slices, n_samples,
+                                   seed & ((1 << 64) - 1), ctypes.byref(rid)))
+    return rid.value
+
+
+def tnc_server_poll(server: int, request_id: int, amps: np.ndarray | None,
+                    bits: np.ndarray | None):
+    """Returns (status, RequestInfo); status TNC_E_BUSY while the request runs.  Other
+    non-zero statuses raise."""
+    info = RequestInfo()
+    st = lib().tnc_server_poll(server, request_id,
+                               amps.ctypes.data_as(_P) if amps is not None else None,
+                               bits.ctypes.data_as(_P) if bits is not None else None,
+                               ctypes.byref(info))
+    if st not in (TNC_OK, TNC_E_BUSY):
+        raise TncError(st, lib().tnc_last_error().decode())
+    return st, info
+
+
+def tnc_server_pending(server: int):
+    q, r = _I32(), _I32()
+    _check(lib().tnc_server_pending(server, ctypes.byref(q), ctypes.byref(r)))
+    return q.value, r.value
+
+
+def tnc_server_destroy(server: int) -> None:
+    _check(lib().tnc_server_destroy(server))

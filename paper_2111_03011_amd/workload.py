@@ -45,10 +45,23 @@ def make_workload(circuit: dict, open_qubits, closed_bits, max_log2: float = 26,
                     plan, np.asarray(slice_ids, dtype=np.uint64))
 
 
-def config_workload(name: str, mode: str = "default", trials: int = 4) -> Workload:
+_CACHE = {}
+
+
+def config_workload(name: str, mode: str = "default", trials: int | None = None) -> Workload:
     """name: small | sliced | large.  For small, mode 'amplitudes' (64 bitstrings, no open
-    qubit) or 'samples' (all 12 qubits open, one group)."""
+    qubit) or 'samples' (all 12 qubits open, one group).  trials defaults to the
+    configuration's plan_trials.  Plans are deterministic and memoised per process."""
+    key = (name, mode, trials)
+    if key not in _CACHE:
+        _CACHE[key] = _config_workload(name, mode, trials)
+    return _CACHE[key]
+
+
+def _config_workload(name: str, mode: str, trials: int | None) -> Workload:
     cfg = synth.config(name)
+    if trials is None:
+        trials = cfg.get("plan_trials", 4)
     circuit = synth.circuit_from_config(cfg)
     n = circuit["n_qubits"]
     if name == "small":

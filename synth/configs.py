@@ -35,6 +35,7 @@ CONFIGS = {
         "oracle_slices": {"count": 8, "seed": 2003},
         "samples": {"count": 1000, "seed": 2004},
         "path_seed": 2005,
+        "plan_trials": 64,
     },
     "precision": {
         "name": "precision",
@@ -59,6 +60,7 @@ CONFIGS = {
         "max_log2_size": 30,
         "slice_subset": {"count": 256, "seed": 5003},
         "path_seed": 5004,
+        "plan_trials": 1,
     },
 }
 

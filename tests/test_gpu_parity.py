@@ -165,7 +165,7 @@ def test_sliced_config_sampled_slices_full_size():
     from paper_2111_03011_amd.workload import config_workload
     cfg = synth.config("sliced")
     log("sliced config at full size")
-    w = config_workload("sliced", trials=2)
+    w = config_workload("sliced")
     assert len(w.slice_ids) == 1024 and w.plan.cost.peak_log2 <= 26
     c = _contraction(w.net, w.plan.path, sliced_labels=w.plan.sliced_labels,
                      slice_ids=w.slice_ids, open_qubits=w.open_qubits, closed_bits=w.closed_bits)
