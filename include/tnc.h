@@ -96,6 +96,11 @@ tnc_status tnc_net_set_path(tnc_net net, const int32_t* pairs, int32_t n,
 tnc_status tnc_net_set_slices(tnc_net net, const int32_t* sliced_labels, int32_t k,
                               const uint64_t* slice_ids, int64_t n_ids);
 
+/* The same with up to 127 sliced labels: slice id i is the two words
+ * slice_ids[2i] (bits 0-63) and slice_ids[2i+1] (bits 64-127). */
+tnc_status tnc_net_set_slices_wide(tnc_net net, const int32_t* sliced_labels, int32_t k,
+                                   const uint64_t* slice_ids, int64_t n_ids);
+
 /* Sparse-state targets (Appendix A): L groups; group i is closed_bits[i] on the closed
  * qubits joined with all 2^n_open configurations of the open qubits.  Bits of open
  * qubits in closed_bits are ignored.  Closed parts must be distinct.  n_qubits <= 64. */
@@ -142,8 +147,9 @@ tnc_status tnc_plan_destroy(tnc_plan plan);
 tnc_status tnc_net_destroy(tnc_net net);
 
 /* Per-step description for reporting: kind 1 = GEMM, 2 = small-operand stream, 3 = slice
- * leaves, 4 = slice sum, 5 = split-K reduction (0 is reserved: operands are never
- * permuted, the GEMM reads them in their stored layouts); rows, m, n, k in
+ * leaves, 4 = slice sum, 5 = split-K reduction, 6 = BF16 hi/lo split of a GEMM operand
+ * (0 is reserved: operands are never permuted, the GEMM reads them in their stored
+ * layouts); rows, m, n, k in
  * elements; flops and bytes algorithmic; invariant = 1 if run once per call. */
 typedef struct {
   int32_t kind;
@@ -157,9 +163,11 @@ tnc_status tnc_plan_n_launches(tnc_plan plan, int32_t* n);
 tnc_status tnc_plan_launch_info(tnc_plan plan, int32_t i, tnc_step_info* info);
 
 /* Timing of launches by kind on the contraction stream.  enable = 1 makes later
- * tnc_contract calls record a HIP event pair around every launch; tnc_plan_timing then
- * returns, per kind (array of 6), the summed milliseconds, summed algorithmic bytes and
- * flops and the launch count since the last reset (synchronises on the events). */
+ * tnc_contract calls record a HIP event pair around every launch of a bounded sample of
+ * slice batches (about 4096 launches per call; the other batches replay the graph);
+ * tnc_plan_timing then returns, per kind (arrays of 7), the summed milliseconds, summed
+ * algorithmic bytes and flops and the launch count since the last reset (synchronises on
+ * the events). */
 tnc_status tnc_plan_set_timing(tnc_plan plan, int32_t enable);
 tnc_status tnc_plan_timing(tnc_plan plan, double* ms, double* bytes, double* flops,
                            int64_t* launches, int32_t reset);

@@ -26,13 +26,15 @@ class Contraction:
         self.sliced_labels = [int(x) for x in sliced_labels]
         if slice_ids is None:
             slice_ids = np.arange(1 << len(self.sliced_labels), dtype=np.uint64)
-        self.slice_ids = np.asarray(slice_ids, dtype=np.uint64)
+        # more than 63 sliced labels: ids are Python ints of up to 127 bits
+        self.slice_ids = (np.asarray(slice_ids, dtype=np.uint64) if len(self.sliced_labels) <= 63
+                          else [int(x) for x in slice_ids])
         self._net = tnc.tnc_net_create(device, net.n_qubits, net.ranks(), net.flat_labels(),
                                        net.flat_data(), net.out_label)
         self._plan = None
         try:
             tnc.tnc_net_set_path(self._net, path)
-            tnc.tnc_net_set_slices(self._net, self.sliced_labels, self.slice_ids)
+            tnc.set_slices_any(self._net, self.sliced_labels, self.slice_ids)
             tnc.tnc_net_set_targets(self._net, self.open_qubits, self.closed_bits)
             self._plan = tnc.tnc_plan_create(self._net, precision, max_batch_slices)
         except Exception:

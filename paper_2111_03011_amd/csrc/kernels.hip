@@ -352,7 +352,7 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   lo = __bf16(x - float(hi));
 }
 
-template <int WAVES_M, int WAVES_N, int UM, int UN, bool A_MFAST, bool B_NFAST>
+template <int WAVES_M, int WAVES_N, int UM, int UN, bool A_MFAST, bool B_NFAST, bool PRESPLIT>
 __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
   static_assert(WAVES_M * WAVES_N == 4, "four waves per workgroup");
   constexpr int BK = 16;                       // complex k per LDS stage (two MFMA steps)
@@ -385,6 +385,29 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
     __bf16* al = ah + A_PLANE;
     __bf16* bh = al + A_PLANE;
     __bf16* bl = bh + B_PLANE;
+    if (PRESPLIT) {
+      // operands already hold (re_hi, im_hi | re_lo, im_lo) as two 32-bit words per element
+#pragma unroll
+      for (int i = 0; i < A_LD; ++i) {
+        const uint2 w = __builtin_bit_cast(uint2, ra[i]);
+        const int o = t.a_row[i] * RS + 2 * t.a_col[i];
+        *reinterpret_cast<uint32_t*>(&ah[o]) = w.x;
+        *reinterpret_cast<uint32_t*>(&al[o]) = w.y;
+      }
+#pragma unroll
+      for (int i = 0; i < B_LD; ++i) {
+        if (!(BK * BN % kThreads == 0 || threadIdx.x + i * kThreads < BK * BN)) continue;
+        const uint2 w = __builtin_bit_cast(uint2, rb[i]);
+        const int o0 = (2 * t.b_n[i]) * RS + 2 * t.b_kr[i];
+        const int o1 = o0 + RS;
+        // column 2n: (re, -im) = flip the sign of the upper half; column 2n+1: (im, re)
+        *reinterpret_cast<uint32_t*>(&bh[o0]) = w.x ^ 0x80000000u;
+        *reinterpret_cast<uint32_t*>(&bh[o1]) = (w.x >> 16) | (w.x << 16);
+        *reinterpret_cast<uint32_t*>(&bl[o0]) = w.y ^ 0x80000000u;
+        *reinterpret_cast<uint32_t*>(&bl[o1]) = (w.y >> 16) | (w.y << 16);
+      }
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < A_LD; ++i) {
       __bf16 h0, l0, h1, l1;
@@ -474,6 +497,23 @@ __global__ __launch_bounds__(kThreads) void k_reduce(ReduceArgs a) {
   }
 }
 
+// out[i] = (bf16 re_hi, im_hi | bf16 re_lo, im_lo) of in[i]: hi = bf16(x), lo = bf16(x - hi)
+// (round to nearest even), packed low half first; same element offsets as the input.
+__global__ __launch_bounds__(kThreads) void k_split_bf16(const float2* in, uint2* out, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kThreads) {
+    const float2 v = in[i];
+    __bf16 rh, rl, ih, il;
+    split_bf16(v.x, rh, rl);
+    split_bf16(v.y, ih, il);
+    const uint32_t hi = uint32_t(__builtin_bit_cast(uint16_t, rh)) |
+                        (uint32_t(__builtin_bit_cast(uint16_t, ih)) << 16);
+    const uint32_t lo = uint32_t(__builtin_bit_cast(uint16_t, rl)) |
+                        (uint32_t(__builtin_bit_cast(uint16_t, il)) << 16);
+    out[i] = make_uint2(hi, lo);
+  }
+}
+
 // ---------------------------------------------------------------------------------
 // slices
 __global__ __launch_bounds__(kThreads) void k_slice_leaves(SliceLeafArgs a, int64_t per_slice) {
@@ -482,7 +522,7 @@ __global__ __launch_bounds__(kThreads) void k_slice_leaves(SliceLeafArgs a, int6
   for (int64_t g = int64_t(blockIdx.x) * kThreads + threadIdx.x; g < total;
        g += int64_t(gridDim.x) * kThreads) {
     const int64_t sl = g / per_slice, gg = g - sl * per_slice;
-    const uint64_t sigma = a.slice_ids[base + sl];
+    const uint64_t* sigma = a.slice_ids + 2 * (base + sl);   // two words per id
     int e = 0;
     while (e + 1 < a.n_entries && a.prefix[e + 1] <= gg) ++e;
     const SliceLeafEntry& t = a.table[e];
@@ -491,7 +531,8 @@ __global__ __launch_bounds__(kThreads) void k_slice_leaves(SliceLeafArgs a, int6
     int64_t d = o & ((int64_t(1) << t.dense_out) - 1);
     for (int j = 0; j < t.n_sl; ++j) {
       const int p = t.pos[j];
-      const int64_t v = (sigma >> t.bit[j]) & 1;
+      const int b = t.bit[j];
+      const int64_t v = (sigma[b >> 6] >> (b & 63)) & 1;
       d = ((d >> p) << (p + 1)) | (v << p) | (d & ((int64_t(1) << p) - 1));
     }
     const int64_t src = t.src_off + (row << (t.dense_out + t.n_sl)) + d;
@@ -692,12 +733,19 @@ hipError_t launch_gemm_cfg(const GemmArgs& a, hipStream_t s) {
       case 2: hipLaunchKernelGGL((k_gemm<WM, WN, UM, UN, BK, false, true>), grid, dim3(kThreads), 0, s, a); break;
       default: hipLaunchKernelGGL((k_gemm<WM, WN, UM, UN, BK, true, true>), grid, dim3(kThreads), 0, s, a); break;
     }
+  } else if (a.precision == 1) {
+    switch (sel) {
+      case 0: hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, false, false, false>), grid, dim3(kThreads), 0, s, a); break;
+      case 1: hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, true, false, false>), grid, dim3(kThreads), 0, s, a); break;
+      case 2: hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, false, true, false>), grid, dim3(kThreads), 0, s, a); break;
+      default: hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, true, true, false>), grid, dim3(kThreads), 0, s, a); break;
+    }
   } else {
     switch (sel) {
-      case 0: hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, false, false>), grid, dim3(kThreads), 0, s, a); break;
-      case 1: hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, true, false>), grid, dim3(kThreads), 0, s, a); break;
-      case 2: hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, false, true>), grid, dim3(kThreads), 0, s, a); break;
-      default: hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, true, true>), grid, dim3(kThreads), 0, s, a); break;
+      case 0: hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, false, false, true>), grid, dim3(kThreads), 0, s, a); break;
+      case 1: hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, true, false, true>), grid, dim3(kThreads), 0, s, a); break;
+      case 2: hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, false, true, true>), grid, dim3(kThreads), 0, s, a); break;
+      default: hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, true, true, true>), grid, dim3(kThreads), 0, s, a); break;
     }
   }
   return hipGetLastError();
@@ -729,6 +777,12 @@ hipError_t launch_gemm(const GemmArgs& a, hipStream_t s) {
     case 3: return launch_gemm_cfg<2, 2, 2, 4, 16>(a, s);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_split_bf16(const float2* in, void* out, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_split_bf16, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, in,
+                     static_cast<uint2*>(out), n);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {

@@ -87,7 +87,7 @@ struct tnc_net_s {
   std::vector<std::pair<int, int>> path;
   bool has_slices = false;
   std::vector<int32_t> sliced;
-  std::vector<uint64_t> slice_ids;
+  std::vector<uint64_t> slice_ids;   // two 64-bit words per id (bits 0-63, 64-127)
   bool has_targets = false;
   std::vector<int32_t> open;
   std::vector<uint64_t> closed;
@@ -95,8 +95,8 @@ struct tnc_net_s {
 
 namespace {
 
-enum Kind { K_PERMUTE = 0, K_GEMM = 1, K_STREAM = 2, K_LEAVES = 3, K_SUM = 4, K_REDUCE = 5 };
-constexpr int kKinds = 6;
+enum Kind { K_PERMUTE = 0, K_GEMM = 1, K_STREAM = 2, K_LEAVES = 3, K_SUM = 4, K_REDUCE = 5, K_SPLIT = 6 };
+constexpr int kKinds = 7;
 
 struct Buf {
   uint64_t bytes = 0;         // all copies
@@ -114,6 +114,7 @@ struct Launch {
   std::vector<int> bufs;  // buffers touched (for lifetimes)
   int b_in0 = -1, b_in1 = -1, b_out = -1, b_tmp = -1;
   int64_t g0 = -1, g1 = -1;   // byte offsets of row gathers in the constants block
+  int64_t n_elems = 0;        // elements per slice copy (split launches)
   StreamArgs st{};
   GemmArgs gm{};
   ReduceArgs rd{};
@@ -147,7 +148,8 @@ struct tnc_plan_s {
   int n_open = 0;
   std::vector<int32_t> open;
   std::vector<uint64_t> closed;
-  std::vector<uint64_t> slice_ids;
+  std::vector<uint64_t> slice_ids;   // two words per id
+  int64_t n_slices() const { return int64_t(slice_ids.size() / 2); }
 
   std::vector<Buf> bufs;
   std::vector<uint8_t> consts;
@@ -393,6 +395,30 @@ struct Compiler {
     }
   }
 
+  // Pre-splitting GEMM operands (instead of splitting while staging tiles) is off unless
+  // TNC_BF16_PRESPLIT is set: measured on MI355X it did not pay for its extra pass.
+  static bool presplit_wanted(int64_t M, int64_t N, int64_t K) {
+    static const bool on = std::getenv("TNC_BF16_PRESPLIT") != nullptr;
+    return on && M >= 256 && N >= 64 && K >= 128;
+  }
+
+  // hi/lo BF16 copy of an operand for the split-precision GEMM (same element offsets);
+  // an operand shared by every slice is split once per call
+  int emit_split(const TState& T) {
+    Launch L;
+    L.kind = K_SPLIT;
+    L.inv = !T.dep;
+    L.b_in0 = T.buf;
+    L.b_out = new_buf(uint64_t(T.elems()) * 8, false, T.dep);
+    L.n_elems = T.elems();
+    L.bufs = {L.b_in0, L.b_out};
+    L.info = tnc_step_info{K_SPLIT, L.inv, T.rows(), int64_t(1) << T.dense.size(), 0, 0, 0.0,
+                           16.0 * double(T.elems())};
+    account(L);
+    list(L.inv).push_back(L);
+    return L.b_out;
+  }
+
   TState step(TState& A, TState& B) {
     TState C;
     C.dep = A.dep || B.dep;
@@ -499,7 +525,7 @@ struct Compiler {
     for (int j = 0; j < nn; ++j) g.b_npos[j] = int8_t(pos_of(Q.dense, NQ[nn - 1 - j]));
     g.a_mfast = (!P.dense.empty() && std::find(MP.begin(), MP.end(), P.dense.back()) != MP.end());
     g.b_nfast = (!Q.dense.empty() && std::find(NQ.begin(), NQ.end(), Q.dense.back()) != NQ.end());
-    const int pbuf = P.buf, qbuf = Q.buf;
+    int pbuf = P.buf, qbuf = Q.buf;
     L.g0 = gather(P, C);
     L.g1 = gather(Q, C);
     g.a_rows = P.rows();
@@ -522,7 +548,17 @@ struct Compiler {
     g.rows = rows;
     g.c_row_stride = M * N;
     choose_tiles(g, M, N, Kd, rows);
-    g.precision = (plan.precision == TNC_BF16X3) ? 1 : 0;
+    g.precision = 0;
+    if (plan.precision == TNC_BF16X3) {
+      // fat products split each operand once (every output tile re-reads its panels);
+      // thin ones split while staging tiles into LDS
+      const bool fat = presplit_wanted(M, N, Kd);
+      g.precision = fat ? 2 : 1;
+      if (fat) {
+        pbuf = emit_split(P);
+        qbuf = emit_split(Q);
+      }
+    }
     C.dense = cat(MP, NQ);
     C.buf = new_buf(uint64_t(C.elems()) * 8, false, C.dep);
     g.a_slice_stride = sstride(pbuf);
@@ -697,6 +733,10 @@ struct Exec {
     return p.ev_pool[p.ev_used++];
   }
 
+  int64_t plan_copies(const Launch& L, int64_t nb) const {
+    return p.bufs[L.b_out].per_slice ? nb : 1;
+  }
+
   int64_t* counter() const { return reinterpret_cast<int64_t*>(ws + p.bufs[p.b_counter].off); }
 
   void check(hipError_t err) {
@@ -734,6 +774,11 @@ struct Exec {
         a.partial = L.b_tmp >= 0 ? ptr(L.b_tmp) : nullptr;
         a.nb = nb;
         err = launch_gemm(a, st);
+        break;
+      }
+      case K_SPLIT: {
+        const int64_t copies = plan_copies(L, nb);
+        err = launch_split_bf16(ptr(L.b_in0), ptr(L.b_out), L.n_elems * copies, st);
         break;
       }
       case K_REDUCE: {
@@ -910,7 +955,8 @@ tnc_plan_s* make_plan(tnc_net_s& net, tnc_precision precision, int32_t max_batch
     p->open = net.open;
     p->closed = net.closed;
     p->slice_ids = net.slice_ids;
-    p->batch = std::max<int32_t>(1, std::min<int32_t>(max_batch, int32_t(net.slice_ids.size())));
+    p->batch = std::max<int32_t>(
+        1, int32_t(std::min<int64_t>(max_batch, int64_t(net.slice_ids.size() / 2))));
     Compiler c(net, *p);
     c.run();
     pack(*p);
@@ -1191,7 +1237,7 @@ tnc_status tnc_net_create(int device, const tnc_network_desc* d, tnc_net* out) {
       for (auto& kv : n->holders)
         if (kv.second.size() == 1 && !outs.count(kv.first))
           fail(TNC_E_INVALID, "label " + std::to_string(kv.first) + " is dangling (one holder, not an output)");
-      n->slice_ids = {0};
+      n->slice_ids = {0, 0};
       n->closed = {0};
     } catch (...) {
       delete n;
@@ -1226,25 +1272,40 @@ tnc_status tnc_net_set_path(tnc_net net, const int32_t* pairs, int32_t n, const 
   });
 }
 
+static void set_slices(tnc_net net, const int32_t* sliced, int32_t k, const uint64_t* ids,
+                       int64_t n_ids, int words) {
+  if (!net) fail(TNC_E_NOT_FOUND, "null network");
+  const int kmax = words == 1 ? 63 : 127;
+  if (k < 0 || k > kmax) fail(TNC_E_INVALID, "k must be in [0, " + std::to_string(kmax) + "]");
+  if (n_ids < 1 || !ids || (k > 0 && !sliced)) fail(TNC_E_INVALID, "bad slice arrays");
+  std::set<int32_t> outs(net->out_label.begin(), net->out_label.end()), seen;
+  for (int b = 0; b < k; ++b) {
+    auto it = net->holders.find(sliced[b]);
+    if (it == net->holders.end() || it->second.size() != 2 || outs.count(sliced[b]))
+      fail(TNC_E_INVALID, "sliced label " + std::to_string(sliced[b]) + " is not a bond");
+    if (!seen.insert(sliced[b]).second) fail(TNC_E_INVALID, "a label is sliced twice");
+  }
+  std::vector<uint64_t> v(size_t(2 * n_ids), 0);
+  for (int64_t i = 0; i < n_ids; ++i) {
+    const uint64_t lo = ids[i * words], hi = words == 2 ? ids[i * words + 1] : 0;
+    const bool ok = k >= 64 ? (k == 128 || (hi >> (k - 64)) == 0) : (hi == 0 && (lo >> k) == 0);
+    if (!ok) fail(TNC_E_INVALID, "slice id out of range");
+    v[size_t(2 * i)] = lo;
+    v[size_t(2 * i + 1)] = hi;
+  }
+  net->sliced.assign(sliced, sliced + k);
+  net->slice_ids = std::move(v);
+  net->has_slices = true;
+}
+
 tnc_status tnc_net_set_slices(tnc_net net, const int32_t* sliced, int32_t k, const uint64_t* ids,
                               int64_t n_ids) {
-  return guard([&] {
-    if (!net) fail(TNC_E_NOT_FOUND, "null network");
-    if (k < 0 || k > 63) fail(TNC_E_INVALID, "k must be in [0, 63]");
-    if (n_ids < 1 || !ids || (k > 0 && !sliced)) fail(TNC_E_INVALID, "bad slice arrays");
-    std::set<int32_t> outs(net->out_label.begin(), net->out_label.end()), seen;
-    for (int b = 0; b < k; ++b) {
-      auto it = net->holders.find(sliced[b]);
-      if (it == net->holders.end() || it->second.size() != 2 || outs.count(sliced[b]))
-        fail(TNC_E_INVALID, "sliced label " + std::to_string(sliced[b]) + " is not a bond");
-      if (!seen.insert(sliced[b]).second) fail(TNC_E_INVALID, "a label is sliced twice");
-    }
-    for (int64_t i = 0; i < n_ids; ++i)
-      if (k < 64 && (ids[i] >> k) != 0) fail(TNC_E_INVALID, "slice id out of range");
-    net->sliced.assign(sliced, sliced + k);
-    net->slice_ids.assign(ids, ids + n_ids);
-    net->has_slices = true;
-  });
+  return guard([&] { set_slices(net, sliced, k, ids, n_ids, 1); });
+}
+
+tnc_status tnc_net_set_slices_wide(tnc_net net, const int32_t* sliced, int32_t k,
+                                   const uint64_t* ids, int64_t n_ids) {
+  return guard([&] { set_slices(net, sliced, k, ids, n_ids, 2); });
 }
 
 tnc_status tnc_net_set_targets(tnc_net net, const int32_t* open, int32_t n_open,
@@ -1311,7 +1372,7 @@ tnc_status tnc_contract_range(tnc_plan p, void* ws, uint64_t ws_bytes, void* str
   return guard([&] {
     if (!p || !amps) fail(TNC_E_INVALID, "null argument");
     check_ws(p, ws, ws_bytes);
-    if (first < 0 || count < 0 || first + count > int64_t(p->slice_ids.size()))
+    if (first < 0 || count < 0 || first + count > p->n_slices())
       fail(TNC_E_INVALID, "slice range outside the slice list");
     DeviceGuard dg(p->device);
     Exec e{*p, static_cast<uint8_t*>(ws), static_cast<hipStream_t>(stream)};
@@ -1326,7 +1387,7 @@ tnc_status tnc_contract(tnc_plan p, void* ws, uint64_t ws_bytes, void* stream, d
     check_ws(p, ws, ws_bytes);
     DeviceGuard dg(p->device);
     Exec e{*p, static_cast<uint8_t*>(ws), static_cast<hipStream_t>(stream)};
-    e.contract(amps, 0, int64_t(p->slice_ids.size()), false);
+    e.contract(amps, 0, p->n_slices(), false);
     if (h_norm) {
       double* parts = reinterpret_cast<double*>(e.ws + p->bufs[p->b_norm].off);
       hipError_t err = launch_norm(amps, p->L << p->n_open, parts, p->norm_parts,
@@ -1450,7 +1511,7 @@ tnc_status tnc_server_submit(tnc_server s, tnc_net net, tnc_precision precision,
       r->ws_bytes = r->plan->ws_bytes;
       r->amps_bytes = uint64_t(r->plan->L << r->plan->n_open) * 16;
       r->footprint = align_up(r->ws_bytes) + align_up(r->amps_bytes);
-      r->total = int64_t(r->plan->slice_ids.size());
+      r->total = r->plan->n_slices();
       if (r->footprint > s->arena_bytes)
         fail(TNC_E_OOM, "request needs " + std::to_string(r->footprint) + " bytes, arena has " +
                             std::to_string(s->arena_bytes));

@@ -59,7 +59,8 @@ struct GemmArgs {
   int64_t k_chunk;
   float2* partial;
   int config;                 // tile configuration id
-  int precision;              // 0: complex64 on FP32 MFMA; 1: BF16 hi+lo split, FP32 accumulate
+  int precision;              // 0: complex64 on FP32 MFMA; 1: BF16 hi+lo split in the kernel;
+                              // 2: BF16 hi+lo, operands already split by k_split_bf16
 };
 
 struct ReduceArgs {           // C[i] = sum_s partial[s][i]  (i over every slice of the launch)
@@ -80,8 +81,8 @@ struct SliceLeafEntry {
   int8_t bit[8];              // which bit of the slice id gives each value
 };
 
-// Slice s of a launch uses slice id slice_ids[*base + s] and writes its leaves at
-// dst_off + s * elems_out.
+// Slice s of a launch uses slice id number *base + s (two 64-bit words per id in
+// slice_ids) and writes its leaves at dst_off + s * elems_out.
 struct SliceLeafArgs {
   const SliceLeafEntry* table;
   const int64_t* prefix;      // [n_entries + 1] element prefix sums
@@ -111,6 +112,8 @@ struct SliceSumArgs {
 hipError_t launch_stream(const StreamArgs& a, hipStream_t s);
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
+// out (8 bytes per element): bf16 (re_hi, im_hi) then (re_lo, im_lo) of each complex64 input
+hipError_t launch_split_bf16(const float2* in, void* out, int64_t n, hipStream_t s);
 hipError_t launch_slice_leaves(const SliceLeafArgs& a, int64_t total_elems, hipStream_t s);
 hipError_t launch_slice_sum(const SliceSumArgs& a, hipStream_t s);
 hipError_t launch_fill_zero(double* p, int64_t n_doubles, hipStream_t s);

@@ -30,7 +30,7 @@ class Server:
                                net.flat_data(), net.out_label)
         try:
             tnc.tnc_net_set_path(h, path)
-            tnc.tnc_net_set_slices(h, sliced_labels, slice_ids)
+            tnc.set_slices_any(h, sliced_labels, slice_ids)
             tnc.tnc_net_set_targets(h, open_qubits, closed_bits)
             rid = tnc.tnc_server_submit(self._h, h, precision, max_batch_slices, n_samples, seed)
         finally:

@@ -27,11 +27,12 @@ TNC_E_INTERNAL = -7
 
 TNC_C64, TNC_FP16X3, TNC_BF16X3, TNC_FP16X3_3M, TNC_BF16X3_3M = range(5)
 
-KIND_NAMES = ("permute", "gemm", "stream", "slice_leaves", "slice_sum", "splitk_reduce")
+KIND_NAMES = ("permute", "gemm", "stream", "slice_leaves", "slice_sum", "splitk_reduce",
+              "split_bf16")
 
 EXPORTS = (
     "tnc_last_error", "tnc_net_create", "tnc_net_set_path", "tnc_net_set_slices",
-    "tnc_net_set_targets", "tnc_plan_create", "tnc_plan_workspace_bytes", "tnc_plan_stats",
+    "tnc_net_set_slices_wide", "tnc_net_set_targets", "tnc_plan_create", "tnc_plan_workspace_bytes", "tnc_plan_stats",
     "tnc_contract", "tnc_contract_range", "tnc_sample", "tnc_plan_destroy", "tnc_net_destroy",
     "tnc_plan_n_launches", "tnc_plan_launch_info", "tnc_plan_set_timing", "tnc_plan_timing",
     "tnc_server_create", "tnc_server_submit", "tnc_server_poll", "tnc_server_pending",
@@ -80,6 +81,7 @@ def lib() -> ctypes.CDLL:
             "tnc_net_create": (_I32, [ctypes.c_int, ctypes.POINTER(_Desc), ctypes.POINTER(_P)]),
             "tnc_net_set_path": (_I32, [_P, _P, _I32, _P]),
             "tnc_net_set_slices": (_I32, [_P, _P, _I32, _P, _I64]),
+            "tnc_net_set_slices_wide": (_I32, [_P, _P, _I32, _P, _I64]),
             "tnc_net_set_targets": (_I32, [_P, _P, _I32, _P, _I64]),
             "tnc_plan_create": (_I32, [_P, ctypes.c_int, _I32, ctypes.POINTER(_P)]),
             "tnc_plan_workspace_bytes": (_I32, [_P, ctypes.POINTER(_U64)]),
@@ -139,6 +141,21 @@ def tnc_net_set_slices(net: int, sliced_labels, slice_ids) -> None:
     s, sp = _arr(sliced_labels if len(sliced_labels) else np.zeros(0), np.int32)
     i, ip = _arr(slice_ids, np.uint64)
     _check(lib().tnc_net_set_slices(net, sp, len(s), ip, len(i)))
+
+
+def tnc_net_set_slices_wide(net: int, sliced_labels, slice_ids) -> None:
+    """slice_ids: Python ints below 2^127 (split into two 64-bit words here)."""
+    s, sp = _arr(sliced_labels if len(sliced_labels) else np.zeros(0), np.int32)
+    words = np.array([[int(x) & ((1 << 64) - 1), int(x) >> 64] for x in slice_ids], dtype=np.uint64)
+    w, wp = _arr(words.reshape(-1), np.uint64)
+    _check(lib().tnc_net_set_slices_wide(net, sp, len(s), wp, len(words)))
+
+
+def set_slices_any(net: int, sliced_labels, slice_ids) -> None:
+    if len(sliced_labels) <= 63:
+        tnc_net_set_slices(net, sliced_labels, np.asarray([int(x) for x in slice_ids], np.uint64))
+    else:
+        tnc_net_set_slices_wide(net, sliced_labels, slice_ids)
 
 
 def tnc_net_set_targets(net: int, open_qubits, closed_bits) -> None:
@@ -211,14 +228,15 @@ def tnc_plan_set_timing(plan: int, enable: bool) -> None:
 
 
 def tnc_plan_timing(plan: int, reset: bool = False):
-    ms = np.zeros(6)
-    by = np.zeros(6)
-    fl = np.zeros(6)
-    n = np.zeros(6, dtype=np.int64)
+    nk = len(KIND_NAMES)
+    ms = np.zeros(nk)
+    by = np.zeros(nk)
+    fl = np.zeros(nk)
+    n = np.zeros(nk, dtype=np.int64)
     _check(lib().tnc_plan_timing(plan, ms.ctypes.data_as(_P), by.ctypes.data_as(_P),
                                  fl.ctypes.data_as(_P), n.ctypes.data_as(_P), 1 if reset else 0))
     return {KIND_NAMES[k]: {"ms": float(ms[k]), "bytes": float(by[k]), "flops": float(fl[k]),
-                            "launches": int(n[k])} for k in range(6)}
+                            "launches": int(n[k])} for k in range(nk)}
 
 
 def tnc_server_create(device: int, arena: int, arena_bytes: int, max_slots: int,

@@ -40,9 +40,13 @@ def make_workload(circuit: dict, open_qubits, closed_bits, max_log2: float = 26,
     plan = find_plan(net, open_qubits, closed_bits, max_log2=max_log2, n_sliced=n_sliced,
                      trials=trials, seed=seed)
     if slice_ids is None:
+        if len(plan.sliced_labels) > 24:
+            raise ValueError("too many slices to enumerate; pass a slice subset")
         slice_ids = np.arange(plan.n_slices, dtype=np.uint64)
+    ids = (np.asarray(slice_ids, dtype=np.uint64) if len(plan.sliced_labels) <= 62
+           else np.asarray(slice_ids, dtype=object))
     return Workload(name, circuit, net, list(open_qubits), np.asarray(closed_bits, np.uint64),
-                    plan, np.asarray(slice_ids, dtype=np.uint64))
+                    plan, ids)
 
 
 _CACHE = {}
@@ -75,13 +79,14 @@ def _config_workload(name: str, mode: str, trials: int | None) -> Workload:
     open_q = cfg["open_qubits"]
     g = cfg["groups"]
     closed = synth.group_targets(n, open_q, g["L"], g["seed"])
-    ids = None
-    w = make_workload(circuit, open_q, closed, max_log2=cfg["max_log2_size"],
-                      n_sliced=cfg.get("sliced_labels"), trials=trials, seed=cfg["path_seed"],
-                      name=name)
+    net = circuit_network(circuit)
+    plan = find_plan(net, open_q, closed, max_log2=cfg["max_log2_size"],
+                     n_sliced=cfg.get("sliced_labels"), trials=trials, seed=cfg["path_seed"])
+    k = len(plan.sliced_labels)
     if "slice_subset" in cfg:
         sub = cfg["slice_subset"]
-        k = len(w.plan.sliced_labels)
         ids = synth.slice_subset(k, sub["count"], sub["seed"])
-        w.slice_ids = ids
-    return w
+    else:
+        ids = np.arange(plan.n_slices, dtype=np.uint64)
+    ids = np.asarray(ids, dtype=np.uint64) if k <= 62 else np.asarray(ids, dtype=object)
+    return Workload(name, circuit, net, list(open_q), np.asarray(closed, np.uint64), plan, ids)

@@ -68,7 +68,17 @@ def group_targets(n: int, open_qubits, L: int, seed: int) -> np.ndarray:
 
 
 def slice_subset(k: int, count: int, seed: int) -> np.ndarray:
-    """`count` distinct slice ids out of 2**k, uniform without replacement, ascending."""
+    """`count` distinct slice ids out of 2**k, uniform without replacement, ascending.
+
+    For k > 62 every id is k coin flips (bit b = flip b), repeats redrawn, and the ids are
+    returned as Python ints in an object array."""
+    if k > 62:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        seen = set()
+        while len(seen) < count:
+            flips = rng.integers(0, 2, size=k)
+            seen.add(sum(int(f) << b for b, f in enumerate(flips)))
+        return np.array(sorted(seen), dtype=object)
     total = 1 << k
     if count >= total:
         return np.arange(total, dtype=np.uint64)
