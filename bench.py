@@ -75,15 +75,109 @@ def measured_traffic(args):
     return rec["traffic_bytes_per_launch"]
 
 
+def serving_main(args):
+    """Poisson request stream through libtnc's server; one JSON line with throughput and
+    latency percentiles (latency = server completion time - submission time)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2111_03011_amd.serving import Server
+    from paper_2111_03011_amd.workload import serving_template
+
+    cfg = synth.config("serving")
+    rng = np.random.Generator(np.random.PCG64(cfg["seed"]))
+    t = time.perf_counter()
+    templates = [serving_template(cfg["seed"] * 10 + i) for i in range(args.templates)]
+    print(f"[serving] planned {len(templates)} request templates in {time.perf_counter() - t:.1f} s",
+          file=sys.stderr, flush=True)
+    # service time of each template alone (the server otherwise idle)
+    srv = Server(arena_bytes=args.arena_gb << 30, max_slots=args.slots, chunk_batches=2)
+    solo = []
+    for w, k in templates:
+        rid = srv.submit(w.net, w.plan.path, w.plan.sliced_labels, w.slice_ids, w.open_qubits,
+                         w.closed_bits, n_samples=k, seed=7,
+                         max_batch_slices=args.serving_batch)
+        while (r := srv.poll(rid)) is None:
+            time.sleep(0.0005)
+        solo.append(r["t_done"] - r["t_admit"])
+    srv.close()
+    print(f"[serving] solo service times (ms): {[round(1e3 * x, 1) for x in solo]}",
+          file=sys.stderr, flush=True)
+    R, warm = args.requests, min(cfg["warmup"], args.requests // 5)
+    arrivals = np.cumsum(rng.exponential(1.0 / cfg["rate_per_s"], size=R))
+    which = rng.integers(0, len(templates), size=R)
+    srv = Server(arena_bytes=args.arena_gb << 30, max_slots=args.slots, chunk_batches=2)
+    done, outstanding, i = {}, {}, 0
+    t0 = time.perf_counter()
+    while len(done) < R:
+        now = time.perf_counter() - t0
+        while i < R and arrivals[i] <= now:
+            w, k = templates[which[i]]
+            rid = srv.submit(w.net, w.plan.path, w.plan.sliced_labels, w.slice_ids,
+                             w.open_qubits, w.closed_bits, n_samples=k, seed=1000 + i,
+                             max_batch_slices=args.serving_batch)
+            outstanding[rid] = i
+            i += 1
+        for rid in list(outstanding):
+            r = srv.poll(rid)
+            if r is not None:
+                done[outstanding.pop(rid)] = r
+        if now > args.serving_timeout:
+            break
+        time.sleep(0.0005)
+    wall = time.perf_counter() - t0
+    srv.close()
+    meas = [done[j] for j in range(warm, R) if j in done]
+    lat = np.array([1e3 * (r["t_done"] - r["t_submit"]) for r in meas])
+    span = max(r["t_done"] for r in meas) - min(r["t_submit"] for r in meas)
+    amps = sum(templates[which[j]][0].n_amplitudes for j in range(warm, R) if j in done)
+    flops = sum(templates[which[j]][0].plan.total_flops for j in range(warm, R) if j in done)
+    ns = [templates[which[j]][0].circuit["n_qubits"] for j in range(R)]
+    out = {
+        "metric": "contraction TFLOP/s & MFMA util; amplitudes/s; p50/p99 request latency",
+        "value": len(meas) / span, "unit": "requests/s", "n_gpus": 1, "steps": len(meas),
+        "warmup": warm, "ms_per_step": float(np.mean(lat)), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+        "data": "synthetic (seeded circuits, Poisson arrivals)",
+        "config": {"workload": f"serving: Poisson {cfg['rate_per_s']} req/s, {R} requests "
+                               f"({warm} warm-up) drawn from {len(templates)} client-planned "
+                               "templates: 20-36 qubits, 10-16 cycles, 256-65536 amplitudes or "
+                               "1e3-1e5 samples, 2^4-2^12 slices, work <= 20 TFLOP per request",
+                   "slots": args.slots, "arena_gb": args.arena_gb,
+                   "batch_slices": args.serving_batch or "auto",
+                   "mean_qubits": float(np.mean(ns))},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "mean": float(np.mean(lat)), "max": float(np.max(lat))},
+        "completed": len(done), "unfinished": R - len(done),
+        "offered_rate_per_s": cfg["rate_per_s"], "achieved_rate_per_s": len(meas) / span,
+        "amplitudes_per_s": amps / span, "contraction_tflops": flops / span / 1e12,
+        "solo_service_ms": {"mean": 1e3 * float(np.mean([solo[j] for j in which])),
+                            "min": 1e3 * min(solo), "max": 1e3 * max(solo)},
+        "offered_load": cfg["rate_per_s"] * float(np.mean([solo[j] for j in which])),
+        "solo_tflops": sum(t[0].plan.total_flops for t in templates) / sum(solo) / 1e12,
+        "wall_s": wall,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="sliced", choices=["sliced", "small", "large"])
+    ap.add_argument("--workload", default="sliced", choices=["sliced", "small", "large", "serving"])
+    ap.add_argument("--requests", type=int, default=120, help="serving: requests in the stream")
+    ap.add_argument("--templates", type=int, default=16, help="serving: distinct request templates")
+    ap.add_argument("--slots", type=int, default=8, help="serving: concurrent requests")
+    ap.add_argument("--arena-gb", type=int, default=64, help="serving: device arena")
+    ap.add_argument("--serving-timeout", type=float, default=150.0)
+    ap.add_argument("--serving-batch", type=int, default=0,
+                    help="serving: slices per launch sequence (0 = chosen per request)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--samples", type=int, default=1000)
     ap.add_argument("--batch", type=int, default=8, help="slices per launch (hipGraph per batch)")
+    ap.add_argument("--autotune", type=int, default=1, help="time tile choices per GEMM first (1/0)")
     ap.add_argument("--precision", default="c64", choices=["c64", "bf16x3"])
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="run one plain device copy of BYTES before the timed region (a known "
@@ -94,6 +188,8 @@ def main():
               "across GPUs as independent blocks, which this build does not launch.",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "serving":
+        return serving_main(args)
 
     import numpy as np
     import torch
@@ -129,6 +225,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    tuned = c.autotune(reps=2) if args.autotune else 0
+    if args.autotune:
+        print(f"[bench] autotuner changed {tuned} GEMM launches", file=sys.stderr, flush=True)
     for i in range(args.warmup):
         norm, _ = one_step()
         print(f"[bench] warmup {i}: norm {norm:.6e}", file=sys.stderr, flush=True)
@@ -206,6 +305,7 @@ def main():
         },
         "amplitudes_per_s": w.n_amplitudes / (ms_step * 1e-3),
         "slices_per_s": len(w.slice_ids) / (ms_step * 1e-3),
+        "autotuned_launches": tuned,
         "mfma_util_gemm": roof["frac"] if roof["bound"] == "mfma" else None,
         "time_share": {k: v / tot for k, v in share.items()},
         "roofline": roof,

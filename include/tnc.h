@@ -108,9 +108,14 @@ tnc_status tnc_net_set_targets(tnc_net net, const int32_t* open_qubits, int32_t 
                                const uint64_t* closed_bits, int64_t L);
 
 /* Compile the step program of a network whose path, slices and targets are set.
- * max_batch_slices >= 1: slices contracted together per launch sequence. */
+ * max_batch_slices >= 1: slices contracted together per launch sequence (capped at the
+ * slice count).  0 = automatic: the smallest power of two whose batch carries >= 2.5e11
+ * flops of per-slice work, at most 256, with at most 16 GiB of workspace. */
 tnc_status tnc_plan_create(tnc_net net, tnc_precision precision, int32_t max_batch_slices,
                            tnc_plan* out);
+
+/* Slices per launch sequence the plan was compiled for. */
+tnc_status tnc_plan_batch_slices(tnc_plan plan, int32_t* batch);
 
 /* Bytes of device workspace tnc_contract needs. */
 tnc_status tnc_plan_workspace_bytes(tnc_plan plan, uint64_t* bytes);
@@ -159,6 +164,15 @@ typedef struct {
   double bytes;
 } tnc_step_info;
 
+/* Autotuner: for every GEMM launch, time each tile configuration (and split-K factors up
+ * to the one the plan sized its partial buffer for) `reps` times on this workspace and
+ * stream, keep the fastest, and drop the captured graph so the next call recaptures it.
+ * Results are cached per shape for the process; with TNC_TUNE_CACHE naming a file they are
+ * appended there and reused by later processes.  Overwrites the workspace's intermediates
+ * (contract afterwards).  n_changed (nullable) receives how many launches changed. */
+tnc_status tnc_plan_autotune(tnc_plan plan, void* d_workspace, uint64_t ws_bytes, void* hip_stream,
+                             int32_t reps, int32_t* n_changed);
+
 tnc_status tnc_plan_n_launches(tnc_plan plan, int32_t* n);
 tnc_status tnc_plan_launch_info(tnc_plan plan, int32_t i, tnc_step_info* info);
 
@@ -196,7 +210,9 @@ typedef struct {
 /* d_arena: caller-owned device memory (256-byte aligned) the server sub-allocates. */
 tnc_status tnc_server_create(int device, void* d_arena, uint64_t arena_bytes, int32_t max_slots,
                              int32_t chunk_batches, tnc_server* out);
-/* n_samples: 0 = amplitudes only; one group: any count; several groups: their number.
+/* max_batch_slices as in tnc_plan_create; with 0 the automatic batch is bounded by
+ * arena_bytes / max_slots of workspace.
+ * n_samples: 0 = amplitudes only; one group: any count; several groups: their number.
  * The network can be destroyed after the call.  TNC_E_OOM if the footprint exceeds the
  * whole arena (the request could never be admitted). */
 tnc_status tnc_server_submit(tnc_server server, tnc_net net, tnc_precision precision,

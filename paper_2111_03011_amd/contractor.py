@@ -17,6 +17,7 @@ class Contraction:
     def __init__(self, net: TensorNetwork, path, sliced_labels=(), slice_ids=None,
                  open_qubits=(), closed_bits=(0,), precision: int = tnc.TNC_C64,
                  device: int = 0, max_batch_slices: int = 1):
+        """max_batch_slices: slices per launch sequence; 0 lets the library choose."""
         import torch
 
         self.device = device
@@ -41,6 +42,7 @@ class Contraction:
             self.close()
             raise
         self.ws_bytes = tnc.tnc_plan_workspace_bytes(self._plan)
+        self.batch_slices = tnc.tnc_plan_batch_slices(self._plan)
         dev = torch.device("cuda", device)
         self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=dev)
         L, l = len(self.closed_bits), 1 << len(self.open_qubits)
@@ -65,6 +67,12 @@ class Contraction:
     def sample(self, seed: int, n_samples: int, stream=None) -> np.ndarray:
         return tnc.tnc_sample(self._plan, self.ws.data_ptr(), self.ws_bytes,
                               self.amps.data_ptr(), seed, n_samples, self._stream(stream))
+
+    def autotune(self, reps: int = 3, stream=None) -> int:
+        """Pick tile configurations and split-K per GEMM by timing them; returns how many
+        launches changed."""
+        return tnc.tnc_plan_autotune(self._plan, self.ws.data_ptr(), self.ws_bytes,
+                                     self._stream(stream), reps)
 
     def stats(self):
         return tnc.tnc_plan_stats(self._plan)

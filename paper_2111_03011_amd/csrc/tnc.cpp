@@ -115,6 +115,8 @@ struct Launch {
   int b_in0 = -1, b_in1 = -1, b_out = -1, b_tmp = -1;
   int64_t g0 = -1, g1 = -1;   // byte offsets of row gathers in the constants block
   int64_t n_elems = 0;        // elements per slice copy (split launches)
+  bool enabled = true;        // a split-K reduction is switched off when tuning drops split-K
+  int max_splits = 1;         // split-K factor the partial buffer was sized for
   StreamArgs st{};
   GemmArgs gm{};
   ReduceArgs rd{};
@@ -569,6 +571,7 @@ struct Compiler {
     L.b_out = C.buf;
     L.bufs = {pbuf, qbuf, C.buf};
     int part = -1;
+    L.max_splits = g.k_splits;
     if (g.k_splits > 1) {
       part = new_buf(uint64_t(g.k_splits) * uint64_t(rows) * uint64_t(M) * uint64_t(N) * 8, false,
                      C.dep);
@@ -745,6 +748,7 @@ struct Exec {
 
   // one launch of the program for nb slices (nb = 1 for the invariant phase)
   void launch(const Launch& L, int64_t nb, double* amps, hipStream_t st, bool timed) {
+    if (!L.enabled) return;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
       e0 = ev();
@@ -939,7 +943,35 @@ void sample_into(tnc_plan_s& p, uint8_t* ws, const double* amps, uint64_t seed, 
   }
 }
 
-tnc_plan_s* make_plan(tnc_net_s& net, tnc_precision precision, int32_t max_batch) {
+tnc_plan_s* compile_plan(tnc_net_s& net, tnc_precision precision, int32_t max_batch);
+
+// Automatic batch size: the smallest power of two whose batch carries at least
+// kAutoBatchFlops of dependent work (so launch latency stays small against it), capped at
+// kAutoBatchMax, at the slice count, and at what fits `budget` bytes of workspace.
+constexpr double kAutoBatchFlops = 2.5e11;
+constexpr int32_t kAutoBatchMax = 256;
+
+tnc_plan_s* make_plan(tnc_net_s& net, tnc_precision precision, int32_t max_batch,
+                      uint64_t budget = uint64_t(16) << 30) {
+  if (max_batch < 0) fail(TNC_E_INVALID, "max_batch_slices must be >= 0 (0 = automatic)");
+  if (max_batch > 0) return compile_plan(net, precision, max_batch);
+  tnc_plan_s* one = compile_plan(net, precision, 1);
+  const int64_t n = one->n_slices();
+  if (n <= 1) return one;
+  const uint64_t ws1 = one->ws_bytes;
+  const double f = std::max(1.0, one->flops_slice);
+  delete one;
+  tnc_plan_s* two = compile_plan(net, precision, 2);
+  const uint64_t per = two->ws_bytes > ws1 ? two->ws_bytes - ws1 : 1;
+  delete two;
+  int32_t S = 1;
+  while (S < kAutoBatchMax && S < n && double(S) * f < kAutoBatchFlops &&
+         ws1 + uint64_t(2 * S - 1) * per <= budget)
+    S *= 2;
+  return compile_plan(net, precision, S);
+}
+
+tnc_plan_s* compile_plan(tnc_net_s& net, tnc_precision precision, int32_t max_batch) {
   if (!net.has_path && net.labels.size() > 1) fail(TNC_E_INVALID, "no path set");
   if (!net.has_targets) fail(TNC_E_INVALID, "no targets set");
   if (precision != TNC_C64 && precision != TNC_BF16X3)
@@ -965,6 +997,129 @@ tnc_plan_s* make_plan(tnc_net_s& net, tnc_precision precision, int32_t max_batch
     throw;
   }
   return p;
+}
+
+// ------------------------------------------------------------------------------------
+// autotuner: per GEMM launch, time the tile configurations (and split-K factors up to the
+// one its partial buffer was sized for) on the real workspace and keep the fastest.
+// Results are cached per shape for the process and, when TNC_TUNE_CACHE names a file,
+// across processes (one "key config splits" line per shape).
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(const GemmArgs& g, int64_t nb) {
+  return std::to_string(g.M) + "x" + std::to_string(g.N) + "x" + std::to_string(g.K) + "/r" +
+         std::to_string(g.rows) + "/b" + std::to_string(nb) + "/f" + std::to_string(g.a_mfast) +
+         std::to_string(g.b_nfast) + "/p" + std::to_string(g.precision) + "/g" +
+         std::to_string(g.ga != nullptr || g.gb != nullptr);
+}
+
+void tune_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("TNC_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char key[256];
+  int c, sp;
+  while (std::fscanf(f, "%255s %d %d", key, &c, &sp) == 3) g_tune[key] = {c, sp};
+  std::fclose(f);
+}
+
+void tune_store(const std::string& key, int c, int sp) {
+  g_tune[key] = {c, sp};
+  const char* path = std::getenv("TNC_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %d\n", key.c_str(), c, sp);
+  std::fclose(f);
+}
+
+int autotune(tnc_plan_s& p, uint8_t* ws, hipStream_t st, int reps) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load();
+  Exec e{p, ws, st};
+  e.upload();
+  e.check(launch_set_i64(e.counter(), 0, st));
+  int changed = 0;
+  hipEvent_t t0, t1;
+  HIPCHK(hipEventCreate(&t0));
+  HIPCHK(hipEventCreate(&t1));
+  for (int phase = 0; phase < 2; ++phase) {
+    std::vector<Launch>& lst = phase == 0 ? p.inv : p.dep;
+    const int64_t nb = phase == 0 ? 1 : p.batch;
+    for (size_t i = 0; i < lst.size(); ++i) {
+      Launch& L = lst[i];
+      if (L.kind != K_GEMM) continue;
+      Launch* R = (i + 1 < lst.size() && lst[i + 1].kind == K_REDUCE && lst[i + 1].b_in0 == L.b_tmp)
+                      ? &lst[i + 1] : nullptr;
+      GemmArgs probe = L.gm;
+      probe.ga = e.gat(L.g0);
+      probe.gb = e.gat(L.g1);
+      const std::string key = tune_key(probe, nb);
+      std::pair<int, int> best{L.gm.config, L.gm.k_splits};
+      auto hit = g_tune.find(key);
+      if (hit != g_tune.end() && hit->second.second <= L.max_splits) {
+        best = hit->second;
+      } else {
+        // the planned choice is timed first, so that it survives ties
+        std::vector<std::pair<int, int>> cands{best};
+        for (int cfg = 0; cfg < 4; ++cfg)
+          for (int sp = 1; sp <= L.max_splits; sp *= 2)
+            if ((sp == 1 || L.gm.K / sp >= 256) && std::make_pair(cfg, sp) != best)
+              cands.push_back({cfg, sp});
+        float best_ms = 1e30f;
+        for (const auto& cand : cands) {
+          {
+            const int cfg = cand.first, sp = cand.second;
+            Launch G = L;
+            G.gm.config = cfg;
+            G.gm.k_splits = sp;
+            G.gm.k_chunk = L.gm.K / sp;
+            float total = 0;
+            for (int r = 0; r <= reps; ++r) {   // the first run warms caches, not counted
+              HIPCHK(hipEventRecord(t0, st));
+              e.launch(G, nb, nullptr, st, false);
+              if (sp > 1 && R) {
+                Launch Rr = *R;
+                Rr.enabled = true;
+                Rr.rd.splits = sp;
+                e.launch(Rr, nb, nullptr, st, false);
+              }
+              HIPCHK(hipEventRecord(t1, st));
+              HIPCHK(hipEventSynchronize(t1));
+              float ms = 0;
+              HIPCHK(hipEventElapsedTime(&ms, t0, t1));
+              if (r > 0) total += ms;
+            }
+            if (total < best_ms * 0.98f) {   // within 2%: keep the earlier choice
+              best_ms = total;
+              best = cand;
+            }
+          }
+        }
+        tune_store(key, best.first, best.second);
+      }
+      if (best.first != L.gm.config || best.second != L.gm.k_splits) ++changed;
+      L.gm.config = best.first;
+      L.gm.k_splits = best.second;
+      L.gm.k_chunk = L.gm.K / best.second;
+      if (R) {
+        R->enabled = best.second > 1;
+        R->rd.splits = best.second;
+      }
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (p.graph) {
+    HIPCHK(hipGraphExecDestroy(p.graph));
+    p.graph = nullptr;
+  }
+  return changed;
 }
 
 struct DeviceGuard {
@@ -1437,6 +1592,25 @@ tnc_status tnc_plan_launch_info(tnc_plan p, int32_t i, tnc_step_info* info) {
   });
 }
 
+tnc_status tnc_plan_batch_slices(tnc_plan p, int32_t* batch) {
+  return guard([&] {
+    if (!p || !batch) fail(TNC_E_INVALID, "null argument");
+    *batch = p->batch;
+  });
+}
+
+tnc_status tnc_plan_autotune(tnc_plan p, void* ws, uint64_t ws_bytes, void* stream, int32_t reps,
+                             int32_t* n_changed) {
+  return guard([&] {
+    if (!p) fail(TNC_E_INVALID, "null plan");
+    check_ws(p, ws, ws_bytes);
+    if (reps < 1) fail(TNC_E_INVALID, "reps must be >= 1");
+    DeviceGuard dg(p->device);
+    const int c = autotune(*p, static_cast<uint8_t*>(ws), static_cast<hipStream_t>(stream), reps);
+    if (n_changed) *n_changed = c;
+  });
+}
+
 tnc_status tnc_plan_set_timing(tnc_plan p, int32_t enable) {
   return guard([&] {
     if (!p) fail(TNC_E_INVALID, "null plan");
@@ -1502,7 +1676,7 @@ tnc_status tnc_server_submit(tnc_server s, tnc_net net, tnc_precision precision,
     if (!s || !net || !request_id) fail(TNC_E_INVALID, "null argument");
     auto* r = new Request();
     try {
-      r->plan = make_plan(*net, precision, max_batch_slices);
+      r->plan = make_plan(*net, precision, max_batch_slices, s->arena_bytes / uint64_t(s->max_slots));
       if (n_samples < 0) fail(TNC_E_INVALID, "negative sample count");
       if (r->plan->L > 1 && n_samples != 0 && n_samples != r->plan->L)
         fail(TNC_E_INVALID, "with several groups, n_samples must be 0 or the number of groups");

@@ -37,11 +37,16 @@ def _popcount(x: int) -> int:
 
 
 class RowCounter:
-    """rows(Q): number of distinct closed-bit restrictions to the qubit mask Q."""
+    """rows(Q): number of distinct closed-bit restrictions to the qubit mask Q.
 
-    def __init__(self, n_qubits: int, closed_bits):
+    Counted exactly for up to `exact_limit` groups; above that the planner uses the bound
+    min(L, 2^|Q|), which never underestimates, so a plan that meets the size bound with it
+    also meets it with the library's exact row counts."""
+
+    def __init__(self, n_qubits: int, closed_bits, exact_limit: int = 1 << 14):
         self.n = n_qubits
         self.bits = np.asarray(closed_bits, dtype=np.uint64)
+        self.exact = self.bits.size <= exact_limit
         self.cache = {0: 1}
 
     def qmask(self, qubits) -> int:
@@ -55,6 +60,8 @@ class RowCounter:
         if r is None:
             if self.bits.size <= 1:
                 r = 1
+            elif not self.exact:
+                r = int(min(self.bits.size, 1 << min(62, _popcount(mask))))
             else:
                 r = int(np.unique(self.bits & np.uint64(mask)).size)
             self.cache[mask] = r

@@ -25,7 +25,7 @@ class Server:
 
     def submit(self, net: TensorNetwork, path, sliced_labels, slice_ids, open_qubits,
                closed_bits, n_samples: int = 0, seed: int = 0, precision: int = tnc.TNC_C64,
-               max_batch_slices: int = 8) -> int:
+               max_batch_slices: int = 0) -> int:
         h = tnc.tnc_net_create(self.device, net.n_qubits, net.ranks(), net.flat_labels(),
                                net.flat_data(), net.out_label)
         try:

@@ -34,7 +34,7 @@ EXPORTS = (
     "tnc_last_error", "tnc_net_create", "tnc_net_set_path", "tnc_net_set_slices",
     "tnc_net_set_slices_wide", "tnc_net_set_targets", "tnc_plan_create", "tnc_plan_workspace_bytes", "tnc_plan_stats",
     "tnc_contract", "tnc_contract_range", "tnc_sample", "tnc_plan_destroy", "tnc_net_destroy",
-    "tnc_plan_n_launches", "tnc_plan_launch_info", "tnc_plan_set_timing", "tnc_plan_timing",
+    "tnc_plan_autotune", "tnc_plan_batch_slices", "tnc_plan_n_launches", "tnc_plan_launch_info", "tnc_plan_set_timing", "tnc_plan_timing",
     "tnc_server_create", "tnc_server_submit", "tnc_server_poll", "tnc_server_pending",
     "tnc_server_destroy",
 )
@@ -91,6 +91,8 @@ def lib() -> ctypes.CDLL:
             "tnc_sample": (_I32, [_P, _P, _U64, _P, _U64, _I64, _P, _P]),
             "tnc_plan_destroy": (_I32, [_P]),
             "tnc_net_destroy": (_I32, [_P]),
+            "tnc_plan_batch_slices": (_I32, [_P, ctypes.POINTER(_I32)]),
+            "tnc_plan_autotune": (_I32, [_P, _P, _U64, _P, _I32, ctypes.POINTER(_I32)]),
             "tnc_plan_n_launches": (_I32, [_P, ctypes.POINTER(_I32)]),
             "tnc_plan_launch_info": (_I32, [_P, _I32, ctypes.POINTER(StepInfo)]),
             "tnc_plan_set_timing": (_I32, [_P, _I32]),
@@ -209,6 +211,18 @@ def tnc_plan_destroy(plan: int) -> None:
 
 def tnc_net_destroy(net: int) -> None:
     _check(lib().tnc_net_destroy(net))
+
+
+def tnc_plan_batch_slices(plan: int) -> int:
+    b = _I32()
+    _check(lib().tnc_plan_batch_slices(plan, ctypes.byref(b)))
+    return b.value
+
+
+def tnc_plan_autotune(plan: int, ws: int, ws_bytes: int, stream: int, reps: int = 3) -> int:
+    n = _I32()
+    _check(lib().tnc_plan_autotune(plan, ws, ws_bytes, stream, reps, ctypes.byref(n)))
+    return n.value
 
 
 def tnc_plan_n_launches(plan: int) -> int:

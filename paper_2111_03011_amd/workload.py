@@ -90,3 +90,42 @@ def _config_workload(name: str, mode: str, trials: int | None) -> Workload:
         ids = np.arange(plan.n_slices, dtype=np.uint64)
     ids = np.asarray(ids, dtype=np.uint64) if k <= 62 else np.asarray(ids, dtype=object)
     return Workload(name, circuit, net, list(open_q), np.asarray(closed, np.uint64), plan, ids)
+
+
+def serving_template(seed: int, max_log2: float = 26, work_cap: float = 2e13,
+                     max_tries: int = 50):
+    """One request of the serving stream, planned by the client ahead of time.
+
+    Draws (seeded) n in [20, 36] qubits on a near-square grid (floor(sqrt n) rows, trailing
+    sites of the last row removed), m in [10, 16] cycles, a kind (amplitudes: 2^[8, 16]
+    bitstrings as groups of 64; samples: k in [1e3, 1e5], one group of 64 per sample) and
+    2^[4, 12] slices; draws are repeated until a plan meets the size bound with that slice
+    count and its total work stays below `work_cap` flops.  Returns (Workload, n_samples).
+    """
+    import math
+    rng = np.random.Generator(np.random.PCG64(seed))
+    for attempt in range(max_tries):
+        n = int(rng.integers(20, 37))
+        m = int(rng.integers(10, 17))
+        samples = bool(rng.random() < 0.5)
+        if samples:
+            k = int(10 ** rng.uniform(3, 5))
+            L = k
+        else:
+            L = (1 << int(rng.integers(8, 17))) // 64
+            k = 0
+        ks = int(rng.integers(4, 13))
+        r = math.isqrt(n)
+        cols = -(-n // r)
+        removed = [[r - 1, c] for c in range(cols) if (r - 1) * cols + c >= n]
+        circ = synth.make_circuit(r, cols, m, seed * 100 + attempt, removed=removed)
+        open_q = sorted(int(q) for q in rng.choice(n, 6, replace=False))
+        closed = synth.group_targets(n, open_q, L, seed * 100 + attempt + 1)
+        try:
+            w = make_workload(circ, open_q, closed, max_log2=max_log2, n_sliced=ks, trials=2,
+                              seed=seed, name=f"request-{seed}")
+        except RuntimeError:
+            continue
+        if w.plan.total_flops <= work_cap:
+            return w, k
+    raise RuntimeError("no request met the size bound and the work cap")

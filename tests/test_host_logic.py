@@ -215,3 +215,40 @@ def test_plan_compile_matches_planner_and_rows():
         tnc.tnc_plan_destroy(p)
     assert sizes[1] > sizes[0]                                       # 4 slice copies
     tnc.tnc_net_destroy(h)
+
+
+def test_automatic_batch_size():
+    """max_batch_slices = 0: the smallest power of two whose batch carries 2.5e11 flops,
+    capped at 256 and at the slice count; explicit sizes are capped at the slice count."""
+    c = synth.make_circuit(3, 3, 8, 21)
+    open_q = [4]
+    closed = synth.group_targets(9, open_q, 20, 2)
+    w = make_workload(c, open_q, closed, max_log2=7, trials=2, seed=3)
+    n = len(w.slice_ids)
+    h = tnc.tnc_net_create(0, 9, w.net.ranks(), w.net.flat_labels(), w.net.flat_data(), w.net.out_label)
+    tnc.tnc_net_set_path(h, w.plan.path)
+    tnc.tnc_net_set_slices(h, w.plan.sliced_labels, w.slice_ids)
+    tnc.tnc_net_set_targets(h, open_q, closed)
+    p = tnc.tnc_plan_create(h, tnc.TNC_C64, 0)
+    assert tnc.tnc_plan_batch_slices(p) == min(256, n)              # tiny slices
+    tnc.tnc_plan_destroy(p)
+    p = tnc.tnc_plan_create(h, tnc.TNC_C64, 10 ** 6)
+    assert tnc.tnc_plan_batch_slices(p) == n
+    tnc.tnc_plan_destroy(p)
+    with pytest.raises(tnc.TncError):
+        tnc.tnc_plan_create(h, tnc.TNC_C64, -1)
+    tnc.tnc_net_destroy(h)
+
+    from paper_2111_03011_amd.workload import config_workload
+    ws = config_workload("sliced")
+    h = tnc.tnc_net_create(0, ws.net.n_qubits, ws.net.ranks(), ws.net.flat_labels(),
+                           ws.net.flat_data(), ws.net.out_label)
+    tnc.tnc_net_set_path(h, ws.plan.path)
+    tnc.tnc_net_set_slices(h, ws.plan.sliced_labels, ws.slice_ids)
+    tnc.tnc_net_set_targets(h, ws.open_qubits, ws.closed_bits)
+    p = tnc.tnc_plan_create(h, tnc.TNC_C64, 0)
+    flops = tnc.tnc_plan_stats(p)[0]
+    b = tnc.tnc_plan_batch_slices(p)
+    assert b == 1 << math.ceil(math.log2(2.5e11 / flops))
+    tnc.tnc_plan_destroy(p)
+    tnc.tnc_net_destroy(h)
