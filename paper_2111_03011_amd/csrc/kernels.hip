@@ -110,18 +110,34 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb) {
 }
 
 // Scatter the low `nbits` bits of x to the bit positions pos[0..nbits) (a software pdep).
-__device__ __forceinline__ int64_t scatter_bits(int64_t x, const int8_t* pos, int nbits) {
+// Unrolled to MAXB >= nbits iterations so that pos[] is read at constant offsets (scalar
+// loads from the kernel arguments) instead of through a dynamically indexed array.
+template <int MAXB>
+__device__ __forceinline__ int64_t scatter_u(int64_t x, const int8_t* pos, int nbits) {
   int64_t o = 0;
-  for (int j = 0; j < nbits; ++j)
-    if ((x >> j) & 1) o += int64_t(1) << pos[j];
+#pragma unroll
+  for (int j = 0; j < MAXB; ++j)
+    if (j < nbits) o += ((x >> j) & 1) << pos[j];
   return o;
+}
+
+__device__ __forceinline__ float2 keep_if(float2 v, uint32_t mask) {
+  uint2 u = __builtin_bit_cast(uint2, v);
+  u.x &= mask;
+  u.y &= mask;
+  return __builtin_bit_cast(float2, u);
 }
 
 // Tile bookkeeping shared by the GEMM kernels: which output tile, slice, row and K range
 // this workgroup owns, the operand bases of the tile corner, and for every load slot of
-// this thread its fixed (row, col) inside the tile and its scattered element offset.
-// Tile sizes divide a label group whenever the group is larger than the tile, so the
-// corner bits and the in-tile bits never overlap.
+// this thread its scattered element offset inside the tile.  Tile sizes divide a label
+// group whenever the group is larger than the tile, so the corner bits and the in-tile
+// bits never overlap.
+//
+// The scattered offset of a K tile is a sum over 6-bit digits of the tile index: lane d of
+// the level-l table holds the offset of digit value d at level l, and the loop reads the
+// digits of the current tile with readlane (scalar, no memory traffic).  Offsets within
+// one operand row fit in 31 bits (checked when the plan is compiled).
 template <int BM, int BN, int BK, bool A_MFAST, bool B_NFAST>
 struct GemmTile {
   static constexpr int LBM = (BM == 128) ? 7 : (BM == 64 ? 6 : 5);
@@ -129,14 +145,36 @@ struct GemmTile {
   static constexpr int LBK = (BK == 16) ? 4 : (BK == 32 ? 5 : 3);
   static constexpr int A_LD = BM * BK / kThreads;
   static constexpr int B_LD = (BK * BN + kThreads - 1) / kThreads;
+  static constexpr int kLev = (kMaxRank - LBK + 5) / 6;
 
   const float2* A;
   const float2* B;
   int64_t M, N, m0, n0, k_begin, k_end, zr, sl, r;
-  int ks;
+  int ks, nlev;
+  int32_t ka_t[kLev], kb_t[kLev];
   int32_t a_off[A_LD], b_off[B_LD];
-  int16_t a_row[A_LD], a_col[A_LD], b_kr[B_LD], b_n[B_LD];
-  bool a_in[A_LD], b_in[B_LD];
+  uint32_t in_bits;   // bit i: A slot i in range; bit A_LD + i: B slot i in range
+
+  // (row, col) of A slot i and (k, n) of B slot i inside the tile
+  __device__ __forceinline__ static int a_row(int i) {
+    const int q = threadIdx.x + i * kThreads;
+    return A_MFAST ? q % BM : q / BK;
+  }
+  __device__ __forceinline__ static int a_col(int i) {
+    const int q = threadIdx.x + i * kThreads;
+    return A_MFAST ? q / BM : q % BK;
+  }
+  __device__ __forceinline__ static int b_kr(int i) {
+    const int q = threadIdx.x + i * kThreads;
+    return B_NFAST ? q / BN : q % BK;
+  }
+  __device__ __forceinline__ static int b_n(int i) {
+    const int q = threadIdx.x + i * kThreads;
+    return B_NFAST ? q % BN : q / BK;
+  }
+  __device__ __forceinline__ static bool b_slot(int i) {
+    return BK * BN % kThreads == 0 || threadIdx.x + i * kThreads < BK * BN;
+  }
 
   __device__ __forceinline__ bool init(const GemmArgs& a) {
     M = a.M;
@@ -158,52 +196,87 @@ struct GemmTile {
     n0 = tn * BN;
     const int64_t mloc_mask = (int64_t(1) << a.nm) - 1;
     A = a.A + sl * a.a_slice_stride + ar * a.a_row_stride +
-        (a.fold ? (m0 >> a.nm) * a.fold_stride : 0) + scatter_bits(m0 & mloc_mask, a.a_mpos, a.nm);
-    B = a.B + sl * a.b_slice_stride + br * a.b_row_stride + scatter_bits(n0, a.b_npos, a.nn);
+        (a.fold ? (m0 >> a.nm) * a.fold_stride : 0) +
+        scatter_u<kMaxRank>(m0 & mloc_mask, a.a_mpos, a.nm);
+    B = a.B + sl * a.b_slice_stride + br * a.b_row_stride + scatter_u<kMaxRank>(n0, a.b_npos, a.nn);
     k_begin = int64_t(ks) * a.k_chunk;
     k_end = (k_begin + a.k_chunk < a.K) ? k_begin + a.k_chunk : a.K;
+    const int lane = threadIdx.x & 63;
+    nlev = a.nk > LBK ? (a.nk - LBK + 5) / 6 : 0;
+#pragma unroll
+    for (int l = 0; l < kLev; ++l) {
+      const int lo = LBK + 6 * l;
+      const int nb = a.nk - lo < 0 ? 0 : (a.nk - lo > 6 ? 6 : a.nk - lo);
+      ka_t[l] = int32_t(scatter_u<6>(lane, a.a_kpos + lo, nb));
+      kb_t[l] = int32_t(scatter_u<6>(lane, a.b_kpos + lo, nb));
+    }
     const int nbm = a.nm < LBM ? a.nm : LBM, nbk = a.nk < LBK ? a.nk : LBK;
     const int nbn = a.nn < LBN ? a.nn : LBN;
+    in_bits = 0;
 #pragma unroll
     for (int i = 0; i < A_LD; ++i) {
-      const int q = threadIdx.x + i * kThreads;
-      int row, col;
-      if (A_MFAST) { row = q % BM; col = q / BM; } else { row = q / BK; col = q % BK; }
-      a_off[i] = int32_t(scatter_bits(row, a.a_mpos, nbm) + scatter_bits(col, a.a_kpos, nbk));
-      a_row[i] = int16_t(row);
-      a_col[i] = int16_t(col);
-      a_in[i] = (m0 + row < M);
+      const int row = a_row(i), col = a_col(i);
+      const bool in = (m0 + row < M);
+      // out-of-range slots read the tile corner (always valid) and are masked to zero
+      a_off[i] = in ? int32_t(scatter_u<LBM>(row, a.a_mpos, nbm) + scatter_u<LBK>(col, a.a_kpos, nbk)) : 0;
+      in_bits |= uint32_t(in) << i;
     }
 #pragma unroll
     for (int i = 0; i < B_LD; ++i) {
-      const int q = threadIdx.x + i * kThreads;
-      int kr, n;
-      if (B_NFAST) { kr = q / BN; n = q % BN; } else { n = q / BK; kr = q % BK; }
-      b_off[i] = int32_t(scatter_bits(kr, a.b_kpos, nbk) + scatter_bits(n, a.b_npos, nbn));
-      b_kr[i] = int16_t(kr);
-      b_n[i] = int16_t(n);
-      b_in[i] = (q < BK * BN) && (n0 + n < N);
+      const int kr = b_kr(i), n = b_n(i);
+      const bool in = b_slot(i) && (n0 + n < N);
+      b_off[i] = in ? int32_t(scatter_u<LBK>(kr, a.b_kpos, nbk) + scatter_u<LBN>(n, a.b_npos, nbn)) : 0;
+      in_bits |= uint32_t(in) << (A_LD + i);
     }
     return true;
   }
 
-  // global -> registers; out-of-range slots read the tile corner (always valid) and are zeroed
-  __device__ __forceinline__ void load(const GemmArgs& a, int64_t k0, float2* ra, float2* rb) const {
-    const float2* __restrict__ Ak = A + scatter_bits(k0, a.a_kpos, a.nk);
-    const float2* __restrict__ Bk = B + scatter_bits(k0, a.b_kpos, a.nk);
+  // global -> registers.  `valid` receives the in-range bits of the slots; they are applied
+  // (masked to zero) when the registers are written to LDS, so no wait is forced here.
+  __device__ __forceinline__ void load(const GemmArgs& a, int64_t k0, float2* ra, float2* rb,
+                                       uint32_t& valid) const {
+    const int64_t kt = k0 >> LBK;
+    int32_t oa = 0, ob = 0;
+#pragma unroll
+    for (int l = 0; l < kLev; ++l)
+      if (l < nlev) {
+        const int d = int((kt >> (6 * l)) & 63);
+        oa += __builtin_amdgcn_readlane(ka_t[l], d);
+        ob += __builtin_amdgcn_readlane(kb_t[l], d);
+      }
+    const float2* __restrict__ Ak = A + oa;
+    const float2* __restrict__ Bk = B + ob;
     const int64_t kl = k_end - k0;
+    if (kl >= BK) {
 #pragma unroll
-    for (int i = 0; i < A_LD; ++i) {
-      const bool ok = a_in[i] && a_col[i] < kl;
-      const float2 v = Ak[ok ? a_off[i] : 0];
-      ra[i] = ok ? v : make_float2(0.f, 0.f);
-    }
+      for (int i = 0; i < A_LD; ++i) ra[i] = Ak[a_off[i]];
 #pragma unroll
-    for (int i = 0; i < B_LD; ++i) {
-      const bool ok = b_in[i] && b_kr[i] < kl;
-      const float2 v = Bk[ok ? b_off[i] : 0];
-      rb[i] = ok ? v : make_float2(0.f, 0.f);
+      for (int i = 0; i < B_LD; ++i) rb[i] = Bk[b_off[i]];
+      valid = in_bits;
+    } else {
+      uint32_t v = in_bits;
+#pragma unroll
+      for (int i = 0; i < A_LD; ++i) {
+        const bool ok = a_col(i) < kl;
+        ra[i] = Ak[ok ? a_off[i] : 0];
+        if (!ok) v &= ~(1u << i);
+      }
+#pragma unroll
+      for (int i = 0; i < B_LD; ++i) {
+        const bool ok = b_kr(i) < kl;
+        rb[i] = Bk[ok ? b_off[i] : 0];
+        if (!ok) v &= ~(1u << (A_LD + i));
+      }
+      valid = v;
     }
+  }
+
+  // zero the slots that are out of range
+  __device__ __forceinline__ static void apply(uint32_t valid, float2* ra, float2* rb) {
+#pragma unroll
+    for (int i = 0; i < A_LD; ++i) ra[i] = keep_if(ra[i], ((valid >> i) & 1) ? ~0u : 0u);
+#pragma unroll
+    for (int i = 0; i < B_LD; ++i) rb[i] = keep_if(rb[i], ((valid >> (A_LD + i)) & 1) ? ~0u : 0u);
   }
 
   __device__ __forceinline__ float* out(const GemmArgs& a) const {
@@ -262,16 +335,18 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs a) {
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
 
   float2 ra[A_LD], rb[B_LD];
+  uint32_t valid = 0;
   auto store = [&](int stage) {
+    Tile::apply(valid, ra, rb);
     float* as = As + stage * A_STAGE;
     float* bs = Bs + stage * B_STAGE;
 #pragma unroll
     for (int i = 0; i < A_LD; ++i)
-      *reinterpret_cast<float2*>(&as[t.a_row[i] * AS + 2 * t.a_col[i]]) = ra[i];
+      *reinterpret_cast<float2*>(&as[Tile::a_row(i) * AS + 2 * Tile::a_col(i)]) = ra[i];
 #pragma unroll
     for (int i = 0; i < B_LD; ++i)
       if (BK * BN % kThreads == 0 || threadIdx.x + i * kThreads < BK * BN)
-        *reinterpret_cast<float2*>(&bs[t.b_kr[i] * BS + 2 * t.b_n[i]]) = rb[i];
+        *reinterpret_cast<float2*>(&bs[Tile::b_kr(i) * BS + 2 * Tile::b_n(i)]) = rb[i];
   };
 
   const int half = lane >> 5;          // 0: lanes carry Re(A); 1: lanes carry Im(A)
@@ -289,13 +364,13 @@ __global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs a) {
 
   int stage = 0;
   if (t.k_begin < t.k_end) {
-    t.load(a, t.k_begin, ra, rb);
+    t.load(a, t.k_begin, ra, rb, valid);
     store(0);
   }
   __syncthreads();
   for (int64_t k0 = t.k_begin; k0 < t.k_end; k0 += BK) {
     const bool more = k0 + BK < t.k_end;
-    if (more) t.load(a, k0 + BK, ra, rb);
+    if (more) t.load(a, k0 + BK, ra, rb, valid);
     const float* as = As + stage * A_STAGE;
     const float* bs = Bs + stage * B_STAGE;
     // fragments double-buffered in registers: step kk+1 is read from LDS before the
@@ -380,7 +455,9 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.f;
 
   float2 ra[A_LD], rb[B_LD];
+  uint32_t valid = 0;
   auto store = [&](int stage) {
+    Tile::apply(valid, ra, rb);
     __bf16* ah = lds + stage * STAGE;
     __bf16* al = ah + A_PLANE;
     __bf16* bh = al + A_PLANE;
@@ -390,7 +467,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
 #pragma unroll
       for (int i = 0; i < A_LD; ++i) {
         const uint2 w = __builtin_bit_cast(uint2, ra[i]);
-        const int o = t.a_row[i] * RS + 2 * t.a_col[i];
+        const int o = Tile::a_row(i) * RS + 2 * Tile::a_col(i);
         *reinterpret_cast<uint32_t*>(&ah[o]) = w.x;
         *reinterpret_cast<uint32_t*>(&al[o]) = w.y;
       }
@@ -398,7 +475,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
       for (int i = 0; i < B_LD; ++i) {
         if (!(BK * BN % kThreads == 0 || threadIdx.x + i * kThreads < BK * BN)) continue;
         const uint2 w = __builtin_bit_cast(uint2, rb[i]);
-        const int o0 = (2 * t.b_n[i]) * RS + 2 * t.b_kr[i];
+        const int o0 = (2 * Tile::b_n(i)) * RS + 2 * Tile::b_kr(i);
         const int o1 = o0 + RS;
         // column 2n: (re, -im) = flip the sign of the upper half; column 2n+1: (im, re)
         *reinterpret_cast<uint32_t*>(&bh[o0]) = w.x ^ 0x80000000u;
@@ -415,7 +492,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
       split_bf16(ra[i].y, h1, l1);
       bf16x2 h, l;
       h[0] = h0; h[1] = h1; l[0] = l0; l[1] = l1;
-      const int o = t.a_row[i] * RS + 2 * t.a_col[i];
+      const int o = Tile::a_row(i) * RS + 2 * Tile::a_col(i);
       *reinterpret_cast<bf16x2*>(&ah[o]) = h;
       *reinterpret_cast<bf16x2*>(&al[o]) = l;
     }
@@ -425,7 +502,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
       __bf16 rh, rl, ih, il;
       split_bf16(rb[i].x, rh, rl);
       split_bf16(rb[i].y, ih, il);
-      const int o0 = (2 * t.b_n[i]) * RS + 2 * t.b_kr[i];     // column 2n
+      const int o0 = (2 * Tile::b_n(i)) * RS + 2 * Tile::b_kr(i);     // column 2n
       const int o1 = o0 + RS;                                 // column 2n+1
       bf16x2 v;
       v[0] = rh; v[1] = -ih; *reinterpret_cast<bf16x2*>(&bh[o0]) = v;
@@ -444,13 +521,13 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
 
   int stage = 0;
   if (t.k_begin < t.k_end) {
-    t.load(a, t.k_begin, ra, rb);
+    t.load(a, t.k_begin, ra, rb, valid);
     store(0);
   }
   __syncthreads();
   for (int64_t k0 = t.k_begin; k0 < t.k_end; k0 += BK) {
     const bool more = k0 + BK < t.k_end;
-    if (more) t.load(a, k0 + BK, ra, rb);
+    if (more) t.load(a, k0 + BK, ra, rb, valid);
     const __bf16* ah = lds + stage * STAGE;
     const __bf16* al = ah + A_PLANE;
     const __bf16* bh = al + A_PLANE;

@@ -490,7 +490,10 @@ struct Compiler {
       return C;
     }
 
-    // GEMM: P supplies the M side, Q the N side
+    // GEMM: P supplies the M side, Q the N side.  The kernels address one operand row
+    // with 32-bit offsets.
+    if (A.dense.size() > 31 || B.dense.size() > 31)
+      fail(TNC_E_UNSUPPORTED, "a GEMM operand row holds more than 2^31 elements");
     const bool p_is_a = (double(A.rows()) * std::ldexp(1.0, int(MA.size()))) >=
                         (double(B.rows()) * std::ldexp(1.0, int(NB.size())));
     TState& P = p_is_a ? A : B;
