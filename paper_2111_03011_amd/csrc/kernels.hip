@@ -134,24 +134,29 @@ __device__ __forceinline__ float2 keep_if(float2 v, uint32_t mask) {
 // group whenever the group is larger than the tile, so the corner bits and the in-tile
 // bits never overlap.
 //
-// The scattered offset of a K tile is a sum over 6-bit digits of the tile index: lane d of
-// the level-l table holds the offset of digit value d at level l, and the loop reads the
-// digits of the current tile with readlane (scalar, no memory traffic).  Offsets within
-// one operand row fit in 31 bits (checked when the plan is compiled).
-template <int BM, int BN, int BK, bool A_MFAST, bool B_NFAST>
+// The scattered offset of a K tile is a sum over 6-bit digits of the tile index (at most
+// kKLevels digits: K <= 2^(4 + 6 kKLevels), checked when the plan is compiled); entry d of
+// the level-l table holds the offset of digit value d at level l.  The tables sit either
+// in LDS (LDS_TAB) or one entry per lane in registers, read with readlane.  Offsets within
+// one operand row fit in 31 bits (also checked when the plan is compiled).
+constexpr int kKLevels = 4;
+
+template <int BM, int BN, int BK, bool A_MFAST, bool B_NFAST, bool LDS_TAB>
 struct GemmTile {
   static constexpr int LBM = (BM == 128) ? 7 : (BM == 64 ? 6 : 5);
   static constexpr int LBN = (BN == 128) ? 7 : (BN == 64 ? 6 : (BN == 32 ? 5 : 4));
   static constexpr int LBK = (BK == 16) ? 4 : (BK == 32 ? 5 : 3);
   static constexpr int A_LD = BM * BK / kThreads;
   static constexpr int B_LD = (BK * BN + kThreads - 1) / kThreads;
-  static constexpr int kLev = (kMaxRank - LBK + 5) / 6;
+  static constexpr int kLev = kKLevels;
+  static constexpr int kTab = 2 * kLev * 64;   // LDS table entries (A levels, then B levels)
 
   const float2* A;
   const float2* B;
   int64_t M, N, m0, n0, k_begin, k_end, zr, sl, r;
   int ks, nlev;
-  int32_t ka_t[kLev], kb_t[kLev];
+  int32_t ka_t[LDS_TAB ? 1 : kLev], kb_t[LDS_TAB ? 1 : kLev];
+  const int32_t* tab;
   int32_t a_off[A_LD], b_off[B_LD];
   uint32_t in_bits;   // bit i: A slot i in range; bit A_LD + i: B slot i in range
 
@@ -176,7 +181,7 @@ struct GemmTile {
     return BK * BN % kThreads == 0 || threadIdx.x + i * kThreads < BK * BN;
   }
 
-  __device__ __forceinline__ bool init(const GemmArgs& a) {
+  __device__ __forceinline__ bool init(const GemmArgs& a, int32_t* lds_tab = nullptr) {
     M = a.M;
     N = a.N;
     const int64_t tiles_m = (M + BM - 1) / BM;
@@ -201,14 +206,24 @@ struct GemmTile {
     B = a.B + sl * a.b_slice_stride + br * a.b_row_stride + scatter_u<kMaxRank>(n0, a.b_npos, a.nn);
     k_begin = int64_t(ks) * a.k_chunk;
     k_end = (k_begin + a.k_chunk < a.K) ? k_begin + a.k_chunk : a.K;
-    const int lane = threadIdx.x & 63;
     nlev = a.nk > LBK ? (a.nk - LBK + 5) / 6 : 0;
+    if (LDS_TAB) {
+      for (int e = threadIdx.x; e < kTab; e += kThreads) {
+        const int op = e / (kLev * 64), l = (e / 64) % kLev, d = e % 64;
+        const int lo = LBK + 6 * l;
+        const int nb = a.nk - lo < 0 ? 0 : (a.nk - lo > 6 ? 6 : a.nk - lo);
+        lds_tab[e] = int32_t(scatter_u<6>(d, (op ? a.b_kpos : a.a_kpos) + lo, nb));
+      }
+      tab = lds_tab;
+    } else {
+      const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int l = 0; l < kLev; ++l) {
-      const int lo = LBK + 6 * l;
-      const int nb = a.nk - lo < 0 ? 0 : (a.nk - lo > 6 ? 6 : a.nk - lo);
-      ka_t[l] = int32_t(scatter_u<6>(lane, a.a_kpos + lo, nb));
-      kb_t[l] = int32_t(scatter_u<6>(lane, a.b_kpos + lo, nb));
+      for (int l = 0; l < kLev; ++l) {
+        const int lo = LBK + 6 * l;
+        const int nb = a.nk - lo < 0 ? 0 : (a.nk - lo > 6 ? 6 : a.nk - lo);
+        ka_t[l] = int32_t(scatter_u<6>(lane, a.a_kpos + lo, nb));
+        kb_t[l] = int32_t(scatter_u<6>(lane, a.b_kpos + lo, nb));
+      }
     }
     const int nbm = a.nm < LBM ? a.nm : LBM, nbk = a.nk < LBK ? a.nk : LBK;
     const int nbn = a.nn < LBN ? a.nn : LBN;
@@ -228,6 +243,7 @@ struct GemmTile {
       b_off[i] = in ? int32_t(scatter_u<LBK>(kr, a.b_kpos, nbk) + scatter_u<LBN>(n, a.b_npos, nbn)) : 0;
       in_bits |= uint32_t(in) << (A_LD + i);
     }
+    if (LDS_TAB) __syncthreads();
     return true;
   }
 
@@ -241,8 +257,13 @@ struct GemmTile {
     for (int l = 0; l < kLev; ++l)
       if (l < nlev) {
         const int d = int((kt >> (6 * l)) & 63);
-        oa += __builtin_amdgcn_readlane(ka_t[l], d);
-        ob += __builtin_amdgcn_readlane(kb_t[l], d);
+        if (LDS_TAB) {
+          oa += tab[l * 64 + d];
+          ob += tab[(kLev + l) * 64 + d];
+        } else {
+          oa += __builtin_amdgcn_readlane(ka_t[LDS_TAB ? 0 : l], d);
+          ob += __builtin_amdgcn_readlane(kb_t[LDS_TAB ? 0 : l], d);
+        }
       }
     const float2* __restrict__ Ak = A + oa;
     const float2* __restrict__ Bk = B + ob;
@@ -307,21 +328,22 @@ struct GemmTile {
 };
 
 template <int WAVES_M, int WAVES_N, int UM, int UN, int BK, bool A_MFAST, bool B_NFAST>
-__global__ __launch_bounds__(kThreads) void k_gemm(GemmArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_gemm(GemmArgs a) {
   static_assert(WAVES_M * WAVES_N == 4, "four waves per workgroup");
   constexpr int BM = WAVES_M * UM * 32;
   constexpr int BN = WAVES_N * UN * 16;
-  using Tile = GemmTile<BM, BN, BK, A_MFAST, B_NFAST>;
+  using Tile = GemmTile<BM, BN, BK, A_MFAST, B_NFAST, true>;
   constexpr int A_LD = Tile::A_LD, B_LD = Tile::B_LD;
   constexpr int AS = 2 * BK + 2;       // floats per LDS row of A (m-major)
-  constexpr int BS = 2 * BN + 2;       // floats per LDS row of B (k-major)
+  constexpr int BS = 2 * BN;           // floats per LDS row of B (k-major; reads are broadcasts)
   constexpr int A_STAGE = BM * AS, B_STAGE = BK * BS;
   // two LDS stages: stage t is read while the tile of stage t+1 is written
   __shared__ float As[2 * A_STAGE];
   __shared__ float Bs[2 * B_STAGE];
+  __shared__ int32_t ktab[Tile::kTab];
 
   Tile t;
-  if (!t.init(a)) return;
+  if (!t.init(a, ktab)) return;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int wm = wave % WAVES_M, wn = wave / WAVES_M;
@@ -433,7 +455,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
   constexpr int BK = 16;                       // complex k per LDS stage (two MFMA steps)
   constexpr int BM = WAVES_M * UM * 32;
   constexpr int BN = WAVES_N * UN * 16;
-  using Tile = GemmTile<BM, BN, BK, A_MFAST, B_NFAST>;
+  using Tile = GemmTile<BM, BN, BK, A_MFAST, B_NFAST, false>;
   constexpr int A_LD = Tile::A_LD, B_LD = Tile::B_LD;
   constexpr int RS = 2 * BK + 8;               // bf16 per LDS row (32 real k + 16 B pad)
   constexpr int A_PLANE = BM * RS, B_PLANE = 2 * BN * RS;

@@ -494,6 +494,7 @@ struct Compiler {
     // with 32-bit offsets.
     if (A.dense.size() > 31 || B.dense.size() > 31)
       fail(TNC_E_UNSUPPORTED, "a GEMM operand row holds more than 2^31 elements");
+    if (nk > 28) fail(TNC_E_UNSUPPORTED, "a GEMM contracts more than 28 labels (K > 2^28)");
     const bool p_is_a = (double(A.rows()) * std::ldexp(1.0, int(MA.size()))) >=
                         (double(B.rows()) * std::ldexp(1.0, int(NB.size())));
     TState& P = p_is_a ? A : B;
