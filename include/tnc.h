@@ -155,13 +155,17 @@ tnc_status tnc_net_destroy(tnc_net net);
  * leaves, 4 = slice sum, 5 = split-K reduction, 6 = BF16 hi/lo split of a GEMM operand
  * (0 is reserved: operands are never permuted, the GEMM reads them in their stored
  * layouts); rows, m, n, k in
- * elements; flops and bytes algorithmic; invariant = 1 if run once per call. */
+ * elements; flops and bytes algorithmic; invariant = 1 if run once per call.  For GEMMs:
+ * tile configuration (0 = 128x64, 1 = 128x16, 2 = 64x32, 3 = 128x128 complex), split-K
+ * factor, and row mode (0 = one launch row per output row, 1 = rows folded into M because
+ * the N-side operand is shared, 2 = output rows sharing an N-side row stacked along M). */
 typedef struct {
   int32_t kind;
   int32_t invariant;
   int64_t rows, m, n, k;
   double flops;
   double bytes;
+  int32_t config, k_splits, row_mode, reserved;
 } tnc_step_info;
 
 /* Autotuner: for every GEMM launch, time each tile configuration (and split-K factors up
@@ -185,6 +189,9 @@ tnc_status tnc_plan_launch_info(tnc_plan plan, int32_t i, tnc_step_info* info);
 tnc_status tnc_plan_set_timing(tnc_plan plan, int32_t enable);
 tnc_status tnc_plan_timing(tnc_plan plan, double* ms, double* bytes, double* flops,
                            int64_t* launches, int32_t reset);
+/* The same per launch index i (as tnc_plan_launch_info): summed milliseconds and the
+ * number of timed executions since the last reset of tnc_plan_timing. */
+tnc_status tnc_plan_launch_timing(tnc_plan plan, int32_t i, double* ms, int64_t* launches);
 
 /* Serving: a request loop on one device with continuous batching.  The caller hands over
  * one device arena; every submitted request (a network with path, slices and targets set)

@@ -87,6 +87,11 @@ class Contraction:
     def timing(self, reset: bool = False):
         return tnc.tnc_plan_timing(self._plan, reset)
 
+    def launch_timing(self):
+        """(ms, count) per launch index since the last timing reset."""
+        return [tnc.tnc_plan_launch_timing(self._plan, i)
+                for i in range(tnc.tnc_plan_n_launches(self._plan))]
+
     def close(self):
         if self._plan is not None:
             tnc.tnc_plan_destroy(self._plan)

@@ -154,6 +154,7 @@ struct GemmTile {
   const float2* A;
   const float2* B;
   int64_t M, N, m0, n0, k_begin, k_end, zr, sl, r;
+  int64_t stk_start, stk_count;   // stacked rows of this tile's 128-row block
   int ks, nlev;
   int32_t ka_t[LDS_TAB ? 1 : kLev], kb_t[LDS_TAB ? 1 : kLev];
   const int32_t* tab;
@@ -195,15 +196,24 @@ struct GemmTile {
     if (zr >= a.rows * a.nb) return false;
     sl = zr / a.rows;
     r = zr - sl * a.rows;
-    const int64_t ar = a.ga ? a.ga[r] : (a.a_rows == 1 ? 0 : r);
-    const int64_t br = a.gb ? a.gb[r] : (a.b_rows == 1 ? 0 : r);
     m0 = tm * BM;
     n0 = tn * BN;
     const int64_t mloc_mask = (int64_t(1) << a.nm) - 1;
-    A = a.A + sl * a.a_slice_stride + ar * a.a_row_stride +
-        (a.fold ? (m0 >> a.nm) * a.fold_stride : 0) +
-        scatter_u<kMaxRank>(m0 & mloc_mask, a.a_mpos, a.nm);
-    B = a.B + sl * a.b_slice_stride + br * a.b_row_stride + scatter_u<kMaxRank>(n0, a.b_npos, a.nn);
+    if (a.stk) {
+      const int32_t* e = a.stk + 3 * (m0 >> 7);
+      stk_start = e[0];
+      stk_count = e[1];
+      A = a.A + sl * a.a_slice_stride;
+      B = a.B + sl * a.b_slice_stride + int64_t(e[2]) * a.b_row_stride +
+          scatter_u<kMaxRank>(n0, a.b_npos, a.nn);
+    } else {
+      const int64_t ar = a.ga ? a.ga[r] : (a.a_rows == 1 ? 0 : r);
+      const int64_t br = a.gb ? a.gb[r] : (a.b_rows == 1 ? 0 : r);
+      A = a.A + sl * a.a_slice_stride + ar * a.a_row_stride +
+          (a.fold ? (m0 >> a.nm) * a.fold_stride : 0) +
+          scatter_u<kMaxRank>(m0 & mloc_mask, a.a_mpos, a.nm);
+      B = a.B + sl * a.b_slice_stride + br * a.b_row_stride + scatter_u<kMaxRank>(n0, a.b_npos, a.nn);
+    }
     k_begin = int64_t(ks) * a.k_chunk;
     k_end = (k_begin + a.k_chunk < a.K) ? k_begin + a.k_chunk : a.K;
     nlev = a.nk > LBK ? (a.nk - LBK + 5) / 6 : 0;
@@ -231,10 +241,22 @@ struct GemmTile {
 #pragma unroll
     for (int i = 0; i < A_LD; ++i) {
       const int row = a_row(i), col = a_col(i);
-      const bool in = (m0 + row < M);
-      // out-of-range slots read the tile corner (always valid) and are masked to zero
-      a_off[i] = in ? int32_t(scatter_u<LBM>(row, a.a_mpos, nbm) + scatter_u<LBK>(col, a.a_kpos, nbk)) : 0;
-      in_bits |= uint32_t(in) << i;
+      if (a.stk) {
+        // stacked: slot row -> (output row, m inside it); offsets from the slice base
+        const int64_t w = (m0 & 127) + row, rr = w >> a.nm, mm = w & mloc_mask;
+        const bool in = rr < stk_count;
+        const int64_t cr = in ? a.perm[stk_start + rr] : 0;
+        const int64_t ar = a.ga ? a.ga[cr] : (a.a_rows == 1 ? 0 : cr);
+        a_off[i] = in ? int32_t(ar * a.a_row_stride + scatter_u<7>(mm, a.a_mpos, a.nm) +
+                                scatter_u<LBK>(col, a.a_kpos, nbk))
+                      : 0;
+        in_bits |= uint32_t(in) << i;
+      } else {
+        const bool in = (m0 + row < M);
+        // out-of-range slots read the tile corner (always valid) and are masked to zero
+        a_off[i] = in ? int32_t(scatter_u<LBM>(row, a.a_mpos, nbm) + scatter_u<LBK>(col, a.a_kpos, nbk)) : 0;
+        in_bits |= uint32_t(in) << i;
+      }
     }
 #pragma unroll
     for (int i = 0; i < B_LD; ++i) {
@@ -311,8 +333,29 @@ struct GemmTile {
   template <int UM, int UN>
   __device__ __forceinline__ void store_acc(const GemmArgs& a, const f32x16 (&acc)[UM][UN],
                                             int wm_base, int wn_base) const {
-    float* o = out(a);
     const int lane = threadIdx.x & 63, half = lane >> 5, j32 = lane & 31;
+    if (a.stk) {
+      // stacked rows: each output row of the tile maps to (row of C, m inside it)
+      float* cb = reinterpret_cast<float*>(a.C + sl * a.c_slice_stride);
+      const int64_t mmask = (int64_t(1) << a.nm) - 1;
+#pragma unroll
+      for (int i = 0; i < UM; ++i)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int row = wm_base + i * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+          const int64_t w = (m0 & 127) + row, rr = w >> a.nm;
+          if (rr >= stk_count) continue;
+          const int64_t cr = a.perm[stk_start + rr];
+          float* orow = cb + (cr * a.c_row_stride + (w & mmask) * N) * 2;
+#pragma unroll
+          for (int j = 0; j < UN; ++j) {
+            const int64_t np = n0 + wn_base + j * 16 + (j32 >> 1);
+            if (np < N) orow[np * 2 + (j32 & 1)] = acc[i][j][v];
+          }
+        }
+      return;
+    }
+    float* o = out(a);
 #pragma unroll
     for (int i = 0; i < UM; ++i)
 #pragma unroll

@@ -20,6 +20,7 @@
 #include <condition_variable>
 #include <deque>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -114,6 +115,7 @@ struct Launch {
   std::vector<int> bufs;  // buffers touched (for lifetimes)
   int b_in0 = -1, b_in1 = -1, b_out = -1, b_tmp = -1;
   int64_t g0 = -1, g1 = -1;   // byte offsets of row gathers in the constants block
+  int64_t stk_off = -1, perm_off = -1;   // row-stacking tables (GEMM), same block
   int64_t n_elems = 0;        // elements per slice copy (split launches)
   bool enabled = true;        // a split-K reduction is switched off when tuning drops split-K
   int max_splits = 1;         // split-K factor the partial buffer was sized for
@@ -136,6 +138,7 @@ struct TState {
 
 struct TimingRec {
   int kind;
+  int index;   // launch index (invariant launches first), -1 if not one of the plan's
   double bytes, flops;
   hipEvent_t e0, e1;
 };
@@ -190,6 +193,8 @@ struct tnc_plan_s {
   size_t ev_used = 0;
   std::vector<TimingRec> pending;
   double t_ms[kKinds] = {}, t_bytes[kKinds] = {}, t_flops[kKinds] = {};
+  std::vector<double> l_ms;      // per launch index, summed over timed launches
+  std::vector<int64_t> l_n;
   int64_t t_n[kKinds] = {};
   ~tnc_plan_s() {
     for (auto e : ev_pool) (void)hipEventDestroy(e);
@@ -378,6 +383,56 @@ struct Compiler {
 
   // Tile configuration and split-K.  Debug overrides: TNC_GEMM_CONFIG forces a tile
   // configuration, TNC_SPLITK_BLOCKS sets the workgroup count split-K aims for.
+  // Row stacking of output rows that share one Q row: perm sorts the output rows by their
+  // Q row; each 128-row block holds up to 128 / M rows of one Q row (start, count, Q row).
+  // Returns the fraction of the stacked M extent that holds real rows.
+  static double stack_rows(const TState& Q, const TState& C, int64_t M, std::vector<int32_t>& stk,
+                           std::vector<int32_t>& perm) {
+    const int64_t rows = C.rows();
+    std::vector<int32_t> qrow(size_t(rows), 0);
+    if (Q.q != 0)
+      for (int64_t r = 0; r < rows; ++r) {
+        const uint64_t k = C.keys[size_t(r)] & Q.q;
+        qrow[size_t(r)] = int32_t(std::lower_bound(Q.keys.begin(), Q.keys.end(), k) - Q.keys.begin());
+      }
+    perm.resize(size_t(rows));
+    for (int64_t r = 0; r < rows; ++r) perm[size_t(r)] = int32_t(r);
+    std::stable_sort(perm.begin(), perm.end(),
+                     [&](int32_t x, int32_t y) { return qrow[size_t(x)] < qrow[size_t(y)]; });
+    stk.clear();
+    const int64_t per = 128 / M;
+    for (int64_t i = 0; i < rows;) {
+      int64_t j = i;
+      const int32_t q0 = qrow[size_t(perm[size_t(i)])];
+      while (j < rows && j - i < per && qrow[size_t(perm[size_t(j)])] == q0) ++j;
+      stk.insert(stk.end(), {int32_t(i), int32_t(j - i), q0});
+      i = j;
+    }
+    return double(rows * M) / (double(stk.size() / 3) * 128.0);
+  }
+
+  // Estimated fraction of the MFMA tile work that is useful, for P on the M side
+  static double tile_fill(const TState& P, const TState& Q, const TState& C, int nm, int nn) {
+    const int64_t M = int64_t(1) << nm, N = int64_t(1) << nn, rows = C.rows();
+    static const int64_t kBM[4] = {128, 128, 64, 128}, kBN[4] = {64, 16, 32, 128};
+    int64_t m_eff = M;
+    if (rows > 1 && Q.rows() == 1 && P.q == C.q && M >= 128) m_eff = M * rows;
+    double fm;
+    const int cfg = (N <= 16) ? 1 : ((m_eff <= 64 || N <= 32) ? 2 : 0);
+    fm = std::min(1.0, double(m_eff) / double(kBM[cfg]));
+    if (m_eff < 128 && rows > 1 && Q.rows() < rows && stacking_enabled()) {
+      std::vector<int32_t> stk, perm;
+      fm = std::max(fm, stack_rows(Q, C, M, stk, perm));
+    }
+    const int cfg_n = (N <= 16) ? 1 : (N <= 32 ? 2 : 0);
+    return fm * std::min(1.0, double(N) / double(kBN[cfg_n]));
+  }
+
+  static bool stacking_enabled() {
+    static const bool on = std::getenv("TNC_NO_STACK") == nullptr;
+    return on;
+  }
+
   static void choose_tiles(GemmArgs& g, int64_t M, int64_t N, int64_t Kd, int64_t rows) {
     const char* force = std::getenv("TNC_GEMM_CONFIG");
     const char* blocks_env = std::getenv("TNC_SPLITK_BLOCKS");
@@ -495,8 +550,18 @@ struct Compiler {
     if (A.dense.size() > 31 || B.dense.size() > 31)
       fail(TNC_E_UNSUPPORTED, "a GEMM operand row holds more than 2^31 elements");
     if (nk > 28) fail(TNC_E_UNSUPPORTED, "a GEMM contracts more than 28 labels (K > 2^28)");
-    const bool p_is_a = (double(A.rows()) * std::ldexp(1.0, int(MA.size()))) >=
-                        (double(B.rows()) * std::ldexp(1.0, int(NB.size())));
+    // P supplies the M side: by default the operand with more rows x free elements; the
+    // other orientation is taken when its tiles are clearly fuller (row stacking needs the
+    // operand whose rows are shared on the N side)
+    bool p_is_a = (double(A.rows()) * std::ldexp(1.0, int(MA.size()))) >=
+                  (double(B.rows()) * std::ldexp(1.0, int(NB.size())));
+    if (C.rows() > 1) {
+      const double f_keep = p_is_a ? tile_fill(A, B, C, int(MA.size()), int(NB.size()))
+                                   : tile_fill(B, A, C, int(NB.size()), int(MA.size()));
+      const double f_swap = p_is_a ? tile_fill(B, A, C, int(NB.size()), int(MA.size()))
+                                   : tile_fill(A, B, C, int(MA.size()), int(NB.size()));
+      if (f_swap > 1.2 * f_keep) p_is_a = !p_is_a;
+    }
     TState& P = p_is_a ? A : B;
     TState& Q = p_is_a ? B : A;
     const std::vector<int32_t>& MP = p_is_a ? MA : NB;
@@ -540,6 +605,8 @@ struct Compiler {
     g.b_row_stride = int64_t(1) << Q.dense.size();
     // rows folded into M when Q is shared by every row and P's rows line up with C's
     // (a tile never straddles two rows: the per-row M is at least the largest tile)
+    const int64_t rows_c = rows, m_c = M;
+    int64_t c_row_stride = M * N;
     if (rows > 1 && Q.rows() == 1 && P.q == C.q && M >= 128) {
       g.fold = 1;
       g.fold_stride = g.a_row_stride;
@@ -547,13 +614,35 @@ struct Compiler {
       rows = 1;
       g.a_rows = 1;
       g.a_row_stride = 0;
+      c_row_stride = M * N;
+    }
+    // row stacking: output rows whose M is below a tile and that share one Q row are
+    // stacked along M, 128 >> nm rows per 128-row block
+    std::vector<int32_t> stk, perm;
+    if (!g.fold && rows > 1 && M < 128 && Q.rows() < rows && stacking_enabled() &&
+        double(P.elems()) < 2147483648.0) {
+      const double fill_stacked = stack_rows(Q, C, M, stk, perm);
+      const double fill_plain = double(M) / (M <= 64 ? 64.0 : 128.0);
+      if (fill_stacked > 1.25 * fill_plain) {
+        M = int64_t(stk.size() / 3) * 128;
+        rows = 1;
+      } else {
+        stk.clear();
+        perm.clear();
+      }
     }
     g.M = M;
     g.N = N;
     g.K = Kd;
     g.rows = rows;
-    g.c_row_stride = M * N;
+    g.c_row_stride = c_row_stride;
     choose_tiles(g, M, N, Kd, rows);
+    if (!stk.empty()) {
+      g.k_splits = 1;   // the split-K reduce assumes C in the launch's own layout
+      g.k_chunk = Kd;
+      L.stk_off = add_const(stk.data(), stk.size() * sizeof(int32_t));
+      L.perm_off = add_const(perm.data(), perm.size() * sizeof(int32_t));
+    }
     g.precision = 0;
     if (plan.precision == TNC_BF16X3) {
       // fat products split each operand once (every output tile re-reads its panels);
@@ -582,7 +671,7 @@ struct Compiler {
       L.b_tmp = part;
       L.bufs.push_back(part);
     }
-    L.info = tnc_step_info{K_GEMM, inv, rows, M, N, Kd, 8.0 * macs,
+    L.info = tnc_step_info{K_GEMM, inv, rows_c, m_c, N, Kd, 8.0 * macs,
                            8.0 * double(P.elems() + Q.elems() + C.elems())};
     account(L);
     list(inv).push_back(L);
@@ -779,6 +868,8 @@ struct Exec {
         a.C = ptr(L.b_out);
         a.ga = gat(L.g0);
         a.gb = gat(L.g1);
+        a.stk = gat(L.stk_off);
+        a.perm = gat(L.perm_off);
         a.partial = L.b_tmp >= 0 ? ptr(L.b_tmp) : nullptr;
         a.nb = nb;
         err = launch_gemm(a, st);
@@ -824,7 +915,13 @@ struct Exec {
     check(err);
     if (timed) {
       HIPCHK(hipEventRecord(e1, st));
-      p.pending.push_back(TimingRec{L.kind, L.info.bytes * double(nb), L.info.flops * double(nb), e0, e1});
+      int index = -1;
+      if (!p.inv.empty() && &L >= p.inv.data() && &L < p.inv.data() + p.inv.size())
+        index = int(&L - p.inv.data());
+      else if (!p.dep.empty() && &L >= p.dep.data() && &L < p.dep.data() + p.dep.size())
+        index = int(p.inv.size()) + int(&L - p.dep.data());
+      p.pending.push_back(
+          TimingRec{L.kind, index, L.info.bytes * double(nb), L.info.flops * double(nb), e0, e1});
     }
   }
 
@@ -909,6 +1006,15 @@ void harvest(tnc_plan_s& p) {
     p.t_bytes[r.kind] += r.bytes;
     p.t_flops[r.kind] += r.flops;
     p.t_n[r.kind] += 1;
+    if (r.index >= 0) {
+      const size_t n = p.inv.size() + p.dep.size();
+      if (p.l_ms.size() != n) {
+        p.l_ms.assign(n, 0.0);
+        p.l_n.assign(n, 0);
+      }
+      p.l_ms[size_t(r.index)] += ms;
+      p.l_n[size_t(r.index)] += 1;
+    }
   }
   p.pending.clear();
   p.ev_used = 0;
@@ -948,6 +1054,22 @@ void sample_into(tnc_plan_s& p, uint8_t* ws, const double* amps, uint64_t seed, 
 }
 
 tnc_plan_s* compile_plan(tnc_net_s& net, tnc_precision precision, int32_t max_batch);
+
+// TNC_PLAN_LOG: one line per GEMM launch (shape, tiles, split-K, row folding or stacking)
+void log_plan(const tnc_plan_s& p) {
+  for (int phase = 0; phase < 2; ++phase)
+    for (const Launch& L : phase == 0 ? p.inv : p.dep) {
+      if (L.kind != K_GEMM) continue;
+      const GemmArgs& g = L.gm;
+      std::fprintf(stderr,
+                   "[tnc plan] %s gemm rows %lld M %lld N %lld K %lld | launch M %lld rows %lld "
+                   "config %d splits %d fold %d stacked %d | a_rows %lld b_rows %lld | %.3g GF\n",
+                   phase == 0 ? "inv" : "dep", (long long)L.info.rows, (long long)L.info.m,
+                   (long long)L.info.n, (long long)L.info.k, (long long)g.M, (long long)g.rows,
+                   g.config, g.k_splits, g.fold, L.stk_off >= 0 ? 1 : 0, (long long)g.a_rows,
+                   (long long)g.b_rows, L.info.flops / 1e9);
+    }
+}
 
 // Automatic batch size: the smallest power of two whose batch carries at least
 // kAutoBatchFlops of dependent work (so launch latency stays small against it), capped at
@@ -996,6 +1118,7 @@ tnc_plan_s* compile_plan(tnc_net_s& net, tnc_precision precision, int32_t max_ba
     Compiler c(net, *p);
     c.run();
     pack(*p);
+    if (std::getenv("TNC_PLAN_LOG")) log_plan(*p);
   } catch (...) {
     delete p;
     throw;
@@ -1016,7 +1139,7 @@ std::string tune_key(const GemmArgs& g, int64_t nb) {
   return std::to_string(g.M) + "x" + std::to_string(g.N) + "x" + std::to_string(g.K) + "/r" +
          std::to_string(g.rows) + "/b" + std::to_string(nb) + "/f" + std::to_string(g.a_mfast) +
          std::to_string(g.b_nfast) + "/p" + std::to_string(g.precision) + "/g" +
-         std::to_string(g.ga != nullptr || g.gb != nullptr);
+         std::to_string(g.ga != nullptr || g.gb != nullptr) + "/s" + std::to_string(g.stk != nullptr);
 }
 
 void tune_load() {
@@ -1063,6 +1186,7 @@ int autotune(tnc_plan_s& p, uint8_t* ws, hipStream_t st, int reps) {
       GemmArgs probe = L.gm;
       probe.ga = e.gat(L.g0);
       probe.gb = e.gat(L.g1);
+      probe.stk = e.gat(L.stk_off);
       const std::string key = tune_key(probe, nb);
       std::pair<int, int> best{L.gm.config, L.gm.k_splits};
       auto hit = g_tune.find(key);
@@ -1593,6 +1717,12 @@ tnc_status tnc_plan_launch_info(tnc_plan p, int32_t i, tnc_step_info* info) {
     *info = L.info;
     info->kind = L.kind;
     info->invariant = L.inv ? 1 : 0;
+    info->config = info->k_splits = info->row_mode = info->reserved = 0;
+    if (L.kind == K_GEMM) {
+      info->config = L.gm.config;
+      info->k_splits = L.gm.k_splits;
+      info->row_mode = L.stk_off >= 0 ? 2 : (L.gm.fold ? 1 : 0);
+    }
   });
 }
 
@@ -1636,7 +1766,22 @@ tnc_status tnc_plan_timing(tnc_plan p, double* ms, double* bytes, double* flops,
     }
     if (reset) {
       for (int k = 0; k < kKinds; ++k) p->t_ms[k] = p->t_bytes[k] = p->t_flops[k] = 0, p->t_n[k] = 0;
+      std::fill(p->l_ms.begin(), p->l_ms.end(), 0.0);
+      std::fill(p->l_n.begin(), p->l_n.end(), 0);
     }
+  });
+}
+
+tnc_status tnc_plan_launch_timing(tnc_plan p, int32_t i, double* ms, int64_t* launches) {
+  return guard([&] {
+    if (!p) fail(TNC_E_INVALID, "null plan");
+    const int n = int(p->inv.size() + p->dep.size());
+    if (i < 0 || i >= n) fail(TNC_E_INVALID, "launch index out of range");
+    DeviceGuard dg(p->device);
+    harvest(*p);
+    const bool have = p->l_ms.size() == size_t(n);
+    if (ms) *ms = have ? p->l_ms[size_t(i)] : 0.0;
+    if (launches) *launches = have ? p->l_n[size_t(i)] : 0;
   });
 }
 

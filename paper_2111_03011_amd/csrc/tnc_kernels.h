@@ -61,6 +61,13 @@ struct GemmArgs {
   int config;                 // tile configuration id
   int precision;              // 0: complex64 on FP32 MFMA; 1: BF16 hi+lo split in the kernel;
                               // 2: BF16 hi+lo, operands already split by k_split_bf16
+  // Row stacking (stk != nullptr): output rows that share one B row are stacked along M.
+  // M is then a multiple of 128 and each output row contributes 2^nm consecutive m; the
+  // 128-row block b holds output rows perm[stk[3b]], ..., perm[stk[3b] + stk[3b+1] - 1]
+  // and reads B row stk[3b+2].  Such a launch has rows = 1 and k_splits = 1, and A's
+  // offsets within one slice fit in 31 bits.
+  const int32_t* stk;
+  const int32_t* perm;
 };
 
 struct ReduceArgs {           // C[i] = sum_s partial[s][i]  (i over every slice of the launch)

@@ -35,6 +35,7 @@ EXPORTS = (
     "tnc_net_set_slices_wide", "tnc_net_set_targets", "tnc_plan_create", "tnc_plan_workspace_bytes", "tnc_plan_stats",
     "tnc_contract", "tnc_contract_range", "tnc_sample", "tnc_plan_destroy", "tnc_net_destroy",
     "tnc_plan_autotune", "tnc_plan_batch_slices", "tnc_plan_n_launches", "tnc_plan_launch_info", "tnc_plan_set_timing", "tnc_plan_timing",
+    "tnc_plan_launch_timing",
     "tnc_server_create", "tnc_server_submit", "tnc_server_poll", "tnc_server_pending",
     "tnc_server_destroy",
 )
@@ -55,7 +56,9 @@ class _Desc(ctypes.Structure):
 class StepInfo(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("invariant", ctypes.c_int32),
                 ("rows", ctypes.c_int64), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
-                ("k", ctypes.c_int64), ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
+                ("k", ctypes.c_int64), ("flops", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("config", ctypes.c_int32), ("k_splits", ctypes.c_int32),
+                ("row_mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class RequestInfo(ctypes.Structure):
@@ -94,6 +97,8 @@ def lib() -> ctypes.CDLL:
             "tnc_plan_batch_slices": (_I32, [_P, ctypes.POINTER(_I32)]),
             "tnc_plan_autotune": (_I32, [_P, _P, _U64, _P, _I32, ctypes.POINTER(_I32)]),
             "tnc_plan_n_launches": (_I32, [_P, ctypes.POINTER(_I32)]),
+            "tnc_plan_launch_timing": (_I32, [_P, _I32, ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_int64)]),
             "tnc_plan_launch_info": (_I32, [_P, _I32, ctypes.POINTER(StepInfo)]),
             "tnc_plan_set_timing": (_I32, [_P, _I32]),
             "tnc_plan_timing": (_I32, [_P, _P, _P, _P, _P, _I32]),
@@ -251,6 +256,13 @@ def tnc_plan_timing(plan: int, reset: bool = False):
                                  fl.ctypes.data_as(_P), n.ctypes.data_as(_P), 1 if reset else 0))
     return {KIND_NAMES[k]: {"ms": float(ms[k]), "bytes": float(by[k]), "flops": float(fl[k]),
                             "launches": int(n[k])} for k in range(nk)}
+
+
+def tnc_plan_launch_timing(plan: int, i: int):
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib().tnc_plan_launch_timing(plan, i, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def tnc_server_create(device: int, arena: int, arena_bytes: int, max_slots: int,

@@ -250,3 +250,65 @@ def test_autotuned_plan_matches_oracle_and_recaptures_graph():
     c.contract_range(0, 64)
     assert np.array_equal(a, c.amps.cpu().numpy())
     c.close()
+
+
+def _grouped_pair(n_ca, n_oa, n_cb, n_ob, nk, L, seed):
+    """Two random tensors sharing nk labels; each carries closed and open output legs.
+    Qubits: A's closed, A's open, B's closed, B's open.  L distinct closed parts."""
+    from paper_2111_03011_amd.network import TensorNetwork
+    rng = np.random.default_rng(seed)
+    k = list(range(nk))
+    nxt = nk
+    ca = list(range(nxt, nxt + n_ca)); nxt += n_ca
+    oa = list(range(nxt, nxt + n_oa)); nxt += n_oa
+    cb = list(range(nxt, nxt + n_cb)); nxt += n_cb
+    ob = list(range(nxt, nxt + n_ob)); nxt += n_ob
+    la, lb = ca + oa + k, k + cb + ob
+    ta = (rng.normal(size=(2,) * len(la)) + 1j * rng.normal(size=(2,) * len(la))) / np.sqrt(2)
+    tb = (rng.normal(size=(2,) * len(lb)) + 1j * rng.normal(size=(2,) * len(lb))) / np.sqrt(2)
+    outs = ca + oa + cb + ob
+    n = len(outs)
+    net = TensorNetwork(n_qubits=n, tensors=[ta, tb], labels=[la, lb], out_label=outs,
+                        bond_label={})
+    open_q = list(range(n_ca, n_ca + n_oa)) + list(range(n_ca + n_oa + n_cb, n))
+    closed = synth.group_targets(n, open_q, L, seed + 1)
+    return net, open_q, closed
+
+
+def _grouped_reference(net, open_q, closed):
+    full = ocontract.contract_path(net.tensors, net.labels, [(0, 1)], net.out_label)
+    n = net.n_qubits
+    full = full.reshape((2,) * n)
+    ref = np.zeros((len(closed), 1 << len(open_q)), dtype=np.complex128)
+    for i, cbits in enumerate(closed):
+        for mu in range(1 << len(open_q)):
+            idx = [(int(cbits) >> (n - 1 - q)) & 1 for q in range(n)]
+            for t, q in enumerate(open_q):
+                idx[q] = (mu >> (len(open_q) - 1 - t)) & 1
+            ref[i, mu] = full[tuple(idx)]
+    return ref
+
+
+@pytest.mark.parametrize("case", [
+    # (closed on A, open on A, closed on B, open on B, shared K labels, groups)
+    (5, 2, 5, 2, 8, 1024),    # every closed configuration: 32 output rows per shared row
+    (6, 3, 3, 4, 7, 300),     # ragged: groups of uneven size, partial 128-row blocks
+    (4, 1, 2, 3, 9, 64),      # M = 2 per row, 64 rows per block
+])
+@pytest.mark.parametrize("precision", [0, 2])
+def test_row_stacked_sparse_rows(case, precision):
+    """Sparse-row GEMMs whose per-row M is below a tile: output rows sharing one N-side row
+    are stacked along M (row mode 2).  Every group's amplitudes match the oracle's full
+    pairwise contraction indexed at the group's bits."""
+    net, open_q, closed = _grouped_pair(*case, seed=sum(case) + precision)
+    log(f"stacked case {case} precision {precision}")
+    ref = _grouped_reference(net, open_q, closed)
+    tol = TOL if precision == 0 else 1e-3
+    c = _contraction(net, [(0, 1)], open_qubits=open_q, closed_bits=closed, precision=precision)
+    modes = [l.row_mode for l in c.launches() if l.kind == 1]
+    assert modes == [2], modes
+    c.contract()
+    err = metrics.rel_error(c.amps.cpu().numpy(), ref)
+    c.close()
+    log(f"  stacked: rel err {err:.3e}")
+    assert err <= tol
