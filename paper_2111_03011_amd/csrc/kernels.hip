@@ -98,6 +98,95 @@ __global__ __launch_bounds__(kThreads) void k_stream(StreamArgs a) {
 }
 
 // ---------------------------------------------------------------------------------
+// big x small stream where the small operand differs per row (sparse-state rows) or per
+// slice: each workgroup stages the small operands of its rows in LDS once (coalesced along
+// each row), then every thread contracts one (row, m) item, or a 1/nsplit share of its N
+// outputs, reading the small operand from LDS.  Grid: x = row chunks (or 256-item
+// segments of one row when M >= 256), y/z = slices.
+constexpr int kStageElems = 4096;   // complex entries of staged small operands per workgroup
+
+template <int NK, int NN>
+__global__ __launch_bounds__(kThreads) void k_stream_rows(StreamArgs a, int rw, int nsplit) {
+  constexpr int KS = 1 << NK, NS = 1 << NN, E = KS * NS;
+  __shared__ float2 s_lds[kStageElems];
+  __shared__ int64_t koff[KS];
+  __shared__ int32_t soff[E];
+  const int64_t sl = int64_t(blockIdx.y) + int64_t(blockIdx.z) * gridDim.y;
+  if (sl >= a.nb) return;
+  for (int k = threadIdx.x; k < KS; k += kThreads) {
+    int64_t ko = 0;
+    for (int j = 0; j < NK; ++j)
+      if ((k >> j) & 1) ko += int64_t(1) << a.x_kpos[j];
+    koff[k] = ko;
+  }
+  for (int q = threadIdx.x; q < E; q += kThreads) {
+    const int k = q / NS, n = q % NS;
+    int so = 0;
+    for (int j = 0; j < NK; ++j)
+      if ((k >> j) & 1) so += 1 << a.s_kpos[j];
+    for (int j = 0; j < NN; ++j)
+      if ((n >> j) & 1) so += 1 << a.s_npos[j];
+    soff[q] = so;
+  }
+  __syncthreads();
+  const int64_t M = int64_t(1) << a.n_m;
+  int64_t r0, m_base, nrows;
+  if (M >= kThreads) {
+    const int64_t per_row = M / kThreads;
+    r0 = int64_t(blockIdx.x) / per_row;
+    m_base = (int64_t(blockIdx.x) % per_row) * kThreads;
+    nrows = 1;
+  } else {
+    r0 = int64_t(blockIdx.x) * rw;
+    m_base = 0;
+    nrows = (a.rows - r0 < rw) ? a.rows - r0 : rw;
+  }
+  for (int64_t e = threadIdx.x; e < nrows * E; e += kThreads) {
+    const int64_t rr = e / E, r = r0 + rr;
+    const int q = int(e % E);
+    const int64_t sr = a.gs ? a.gs[r] : (a.s_rows == 1 ? 0 : r);
+    s_lds[e] = a.S[sl * a.s_slice_stride + sr * a.s_row_stride + soff[q]];
+  }
+  __syncthreads();
+  const int item = threadIdx.x / nsplit, part = threadIdx.x % nsplit;
+  const int64_t items = (M >= kThreads) ? kThreads : nrows * M;
+  if (item >= items) return;
+  int64_t rr, m;
+  if (M >= kThreads) {
+    rr = 0;
+    m = m_base + item;
+  } else {
+    rr = item >> a.n_m;
+    m = item & (M - 1);
+  }
+  const int64_t r = r0 + rr;
+  const int64_t xr = a.gx ? a.gx[r] : (a.x_rows == 1 ? 0 : r);
+  const float2* X = a.X + sl * a.x_slice_stride + xr * a.x_row_stride;
+  int64_t xo = m;
+#pragma unroll
+  for (int j = 0; j < NK; ++j) {
+    const int p = a.x_kins[j];
+    xo = ((xo >> p) << (p + 1)) | (xo & ((int64_t(1) << p) - 1));
+  }
+  float2 xv[KS];
+#pragma unroll
+  for (int k = 0; k < KS; ++k) xv[k] = X[xo + koff[k]];
+  const float2* srow = s_lds + rr * E;
+  float2* C = a.C + sl * a.c_slice_stride + r * a.c_row_stride + (m << NN);
+  const int nper = NS / nsplit;
+  for (int n = part * nper; n < (part + 1) * nper; ++n) {
+    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const float2 sv = srow[k * NS + n];
+      acc.x += xv[k].x * sv.x - xv[k].y * sv.y;
+      acc.y += xv[k].x * sv.y + xv[k].y * sv.x;
+    }
+    C[n] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------------
 // complex64 GEMM on v_mfma_f32_32x32x2f32
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -841,9 +930,32 @@ int grid_for(int64_t work, int64_t per_block, int64_t cap = 8192) {
 
 template <int NK, int NN>
 hipError_t launch_stream_t(const StreamArgs& a, hipStream_t s) {
-  const int64_t total = (a.rows << a.n_m) * a.nb;
-  hipLaunchKernelGGL((k_stream<NK, NN>), dim3(grid_for(total, kThreads, 65536)), dim3(kThreads), 0,
-                     s, a);
+  const bool s_shared = (a.s_rows == 1 && a.gs == nullptr && a.s_slice_stride == 0);
+  if (s_shared) {
+    const int64_t total = (a.rows << a.n_m) * a.nb;
+    hipLaunchKernelGGL((k_stream<NK, NN>), dim3(grid_for(total, kThreads, 65536)), dim3(kThreads),
+                       0, s, a);
+    return hipGetLastError();
+  }
+  constexpr int KS = 1 << NK, NS = 1 << NN, E = KS * NS;
+  static_assert(E <= kStageElems, "one row of the small operand must fit the stage");
+  const int64_t M = int64_t(1) << a.n_m;
+  int rw = 1, nsplit = 1;
+  int64_t chunks;
+  if (M >= kThreads) {
+    chunks = a.rows * (M / kThreads);
+  } else {
+    const int64_t by_threads = kThreads / M, by_lds = kStageElems / E;
+    rw = int(by_threads < by_lds ? by_threads : by_lds);
+    const int64_t items = int64_t(rw) * M;
+    const int64_t ns = kThreads / items;
+    nsplit = int(ns < NS ? ns : NS);
+    chunks = (a.rows + rw - 1) / rw;
+  }
+  const int64_t gy = a.nb < 65535 ? a.nb : 65535;
+  const int64_t gz = (a.nb + gy - 1) / gy;
+  hipLaunchKernelGGL((k_stream_rows<NK, NN>), dim3(unsigned(chunks), unsigned(gy), unsigned(gz)),
+                     dim3(kThreads), 0, s, a, rw, nsplit);
   return hipGetLastError();
 }
 

@@ -1059,6 +1059,20 @@ tnc_plan_s* compile_plan(tnc_net_s& net, tnc_precision precision, int32_t max_ba
 void log_plan(const tnc_plan_s& p) {
   for (int phase = 0; phase < 2; ++phase)
     for (const Launch& L : phase == 0 ? p.inv : p.dep) {
+      if (L.kind == K_STREAM) {
+        const StreamArgs& a = L.st;
+        std::string kins, spos;
+        for (int j = 0; j < a.nk; ++j) kins += " " + std::to_string(a.x_kins[j]);
+        for (int j = 0; j < a.nk; ++j) spos += " k" + std::to_string(a.s_kpos[j]);
+        for (int j = 0; j < a.nn; ++j) spos += " n" + std::to_string(a.s_npos[j]);
+        std::fprintf(stderr,
+                     "[tnc plan] %s stream rows %lld x_rows %lld s_rows %lld | m 2^%d k 2^%d n 2^%d | "
+                     "x k-bits at%s | s bits%s | gx %d gs %d\n",
+                     phase == 0 ? "inv" : "dep", (long long)a.rows, (long long)a.x_rows,
+                     (long long)a.s_rows, a.n_m, a.nk, a.nn, kins.c_str(), spos.c_str(),
+                     L.g0 >= 0 ? 1 : 0, L.g1 >= 0 ? 1 : 0);
+        continue;
+      }
       if (L.kind != K_GEMM) continue;
       const GemmArgs& g = L.gm;
       std::fprintf(stderr,
