@@ -8,7 +8,7 @@
 //                  v_mfma_f32_32x32x2f32 consumes exactly one complex k; both operands
 //                  are read in their stored label order (per-slot scattered offsets), so
 //                  the path needs no transposes
-//   k_reduce       split-K partial sums, fixed order
+//   k_reduce(_wide) split-K partial sums, fixed order
 //   k_slice_leaves per-slice instantiation of the leaves that hold sliced bonds
 //   k_slice_sum    FP64 accumulation of a slice's result into psi_hat
 //   k_norm_*       FP64 sum of |amp|^2, two fixed-order passes
@@ -728,6 +728,45 @@ __global__ __launch_bounds__(kThreads) void k_reduce(ReduceArgs a) {
   }
 }
 
+// Many splits: 64 elements per workgroup, each wave sums a quarter of the splits (two
+// interleaved chains), and the four partial sums are added in wave order.  The summation
+// order is fixed by the split count alone.
+__global__ __launch_bounds__(kThreads) void k_reduce_wide(ReduceArgs a) {
+  __shared__ float2 red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i = int64_t(blockIdx.x) * 64 + lane;
+  const int per = (a.splits + 3) / 4;
+  const int s0 = w * per, s1 = (s0 + per < a.splits) ? s0 + per : a.splits;
+  float2 c0 = make_float2(0.f, 0.f), c1 = make_float2(0.f, 0.f);
+  if (i < a.elems) {
+    int k = s0;
+    for (; k + 1 < s1; k += 2) {
+      const float2 p0 = a.partial[int64_t(k) * a.elems + i];
+      const float2 p1 = a.partial[int64_t(k + 1) * a.elems + i];
+      c0.x += p0.x;
+      c0.y += p0.y;
+      c1.x += p1.x;
+      c1.y += p1.y;
+    }
+    if (k < s1) {
+      const float2 p0 = a.partial[int64_t(k) * a.elems + i];
+      c0.x += p0.x;
+      c0.y += p0.y;
+    }
+  }
+  red[w][lane] = make_float2(c0.x + c1.x, c0.y + c1.y);
+  __syncthreads();
+  if (w == 0 && i < a.elems) {
+    float2 t = red[0][lane];
+#pragma unroll
+    for (int q = 1; q < 4; ++q) {
+      t.x += red[q][lane].x;
+      t.y += red[q][lane].y;
+    }
+    a.C[i] = t;
+  }
+}
+
 // out[i] = (bf16 re_hi, im_hi | bf16 re_lo, im_lo) of in[i]: hi = bf16(x), lo = bf16(x - hi)
 // (round to nearest even), packed low half first; same element offsets as the input.
 __global__ __launch_bounds__(kThreads) void k_split_bf16(const float2* in, uint2* out, int64_t n) {
@@ -1040,6 +1079,10 @@ hipError_t launch_split_bf16(const float2* in, void* out, int64_t n, hipStream_t
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
+  if (a.splits >= 8) {
+    hipLaunchKernelGGL(k_reduce_wide, dim3(unsigned((a.elems + 63) / 64)), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_reduce, dim3(grid_for(a.elems, kThreads)), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
