@@ -312,3 +312,36 @@ def test_row_stacked_sparse_rows(case, precision):
     c.close()
     log(f"  stacked: rel err {err:.3e}")
     assert err <= tol
+
+
+def test_degenerate_cases():
+    """Edge cases of the path: contracting zero slices leaves psi_hat at zero (norm 0); a
+    group whose amplitudes are all zero draws mu = floor(u * l) exactly as the oracle does;
+    a batch size that does not divide the slice count (ragged last batch) and a batch
+    larger than the slice count give the one-at-a-time sum."""
+    w = _sliced_workload(3, 4, 8, 11, [0, 5, 11], 6, 9, 4)   # 16 slices, 6 groups
+    kw = dict(sliced_labels=w.plan.sliced_labels, slice_ids=w.slice_ids,
+              open_qubits=w.open_qubits, closed_bits=w.closed_bits)
+    n = len(w.slice_ids)
+    log(f"degenerate cases: {n} slices, {len(w.closed_bits)} groups")
+    c = _contraction(w.net, w.plan.path, **kw)
+    c.contract_range(0, 0)
+    zero = c.amps.cpu().numpy()
+    assert not zero.any()
+    bits = c.sample(5, len(w.closed_bits))
+    want = sampling.bitstrings(sampling.sample(zero, 5, len(w.closed_bits)), w.closed_bits,
+                               w.open_qubits, w.circuit["n_qubits"])
+    assert np.array_equal(bits, want)
+    c.contract()
+    ref = c.amps.cpu().numpy().copy()
+    c.close()
+    for S in (3, 4 * n):
+        c = _contraction(w.net, w.plan.path, max_batch_slices=S, **kw)
+        c.contract()
+        got = c.amps.cpu().numpy()
+        assert metrics.rel_error(got, ref) <= 1e-6, (S, metrics.rel_error(got, ref))
+        c.close()
+    oref = ocontract.sparse_amplitudes(w.circuit, w.open_qubits, w.closed_bits,
+                                       sliced_bonds=w.sliced_bonds,
+                                       slice_ids=[int(x) for x in w.slice_ids])
+    assert metrics.rel_error(ref, oref) <= TOL
