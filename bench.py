@@ -57,22 +57,70 @@ def cpu_baseline(w, flops_per_slice: float, budget_s: float = 20.0) -> dict:
             "amplitudes_per_s": w.n_amplitudes / (per_slice * len(w.slice_ids))}
 
 
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "k_gemm_sliced_5x6_m14_traffic.json")
+
+
+def kernels_sha256():
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2111_03011_amd", "csrc", "kernels.hip"), "rb").read()
+    return hashlib.sha256(src).hexdigest()
+
+
 def measured_traffic(args):
     """HBM bytes per k_gemm launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
     passes (calibrated against a plain 1 GiB copy), or None when they do not describe the
     kernel that runs now (different source, precision, workload or batch)."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "k_gemm_sliced_5x6_m14_traffic.json")
-    if not (args.workload == "sliced" and args.precision == "c64" and args.batch == 8):
-        return None
     try:
-        rec = json.load(open(path))
-        src = open(os.path.join(ROOT, "paper_2111_03011_amd", "csrc", "kernels.hip"), "rb").read()
+        rec = json.load(open(TRAFFIC_JSON))
+        sha = kernels_sha256()
     except OSError:
         return None
-    if hashlib.sha256(src).hexdigest() != rec.get("kernels_hip_sha256"):
+    if (rec.get("kernels_hip_sha256") != sha or rec.get("workload") != args.workload or
+            rec.get("precision") != args.precision or rec.get("batch") != args.batch):
         return None
     return rec["traffic_bytes_per_launch"]
+
+
+def write_traffic(args, fetch_csv, write_csv):
+    """Summarise two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE; one step of this
+    bench with --copy-calibration) into the traffic record bench.py reads: KiB per dispatch
+    of the dominant GEMM kernel, each counter scaled by what it reads for the plain device
+    copy of known size."""
+    import csv
+    name = "::k_gemm<" if args.precision == "c64" else "::k_gemm_bf16x3<"
+
+    def per_dispatch(path, counter):
+        gemm, copy = {}, {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            d = r["Dispatch_Id"]
+            v = float(r["Counter_Value"])
+            if name in r["Kernel_Name"]:
+                gemm[d] = gemm.get(d, 0.0) + v
+            elif "copyBuffer" in r["Kernel_Name"]:
+                copy[d] = copy.get(d, 0.0) + v
+        return sum(gemm.values()) / len(gemm), len(gemm), max(copy.values())
+
+    f_kib, n_f, f_copy = per_dispatch(fetch_csv, "FETCH_SIZE")
+    w_kib, n_w, w_copy = per_dispatch(write_csv, "WRITE_SIZE")
+    kib = args.copy_calibration / 1024.0
+    f_fac, w_fac = kib / f_copy, kib / w_copy
+    rec = {
+        "kernel": name.strip(":<"), "workload": args.workload, "precision": args.precision,
+        "batch": args.batch, "kernels_hip_sha256": kernels_sha256(),
+        "dispatches": [n_f, n_w],
+        "fetch_kib_per_launch_raw": round(f_kib, 2), "write_kib_per_launch_raw": round(w_kib, 2),
+        "copy_calibration": {"bytes": args.copy_calibration, "fetch_kib": f_copy,
+                             "write_kib": w_copy, "fetch_factor": round(f_fac, 4),
+                             "write_factor": round(w_fac, 4)},
+        "fetch_bytes_per_launch": round(f_kib * f_fac * 1024.0),
+        "write_bytes_per_launch": round(w_kib * w_fac * 1024.0),
+    }
+    rec["traffic_bytes_per_launch"] = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    with open(TRAFFIC_JSON, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
 
 
 def serving_main(args):
@@ -176,16 +224,23 @@ def main():
                     help="serving: slices per launch sequence (0 = chosen per request)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--samples", type=int, default=1000)
-    ap.add_argument("--batch", type=int, default=8, help="slices per launch (hipGraph per batch)")
+    ap.add_argument("--batch", type=int, default=64, help="slices per launch (hipGraph per batch)")
     ap.add_argument("--autotune", type=int, default=1, help="time tile choices per GEMM first (1/0)")
     ap.add_argument("--precision", default="c64", choices=["c64", "bf16x3"])
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="run one plain device copy of BYTES before the timed region (a known "
                          "reference for HBM traffic counters)")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE counter files of one step "
+                         "(run with --copy-calibration) into the traffic record, then exit")
     args = ap.parse_args()
+    if args.write_traffic:
+        if not args.copy_calibration:
+            sys.exit("--write-traffic needs the --copy-calibration size the passes used")
+        return write_traffic(args, *args.write_traffic)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); slices would shard "
-              "across GPUs as independent blocks, which this build does not launch.",
+              "across GPUs as independent blocks, which this program does not launch.",
               file=sys.stderr)
         sys.exit(2)
     if args.workload == "serving":

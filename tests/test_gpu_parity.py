@@ -168,7 +168,8 @@ def test_sliced_config_sampled_slices_full_size():
     w = config_workload("sliced")
     assert len(w.slice_ids) == 1024 and w.plan.cost.peak_log2 <= 26
     c = _contraction(w.net, w.plan.path, sliced_labels=w.plan.sliced_labels,
-                     slice_ids=w.slice_ids, open_qubits=w.open_qubits, closed_bits=w.closed_bits)
+                     slice_ids=w.slice_ids, open_qubits=w.open_qubits, closed_bits=w.closed_bits,
+                     max_batch_slices=64)
     picks = synth.slice_subset(len(w.plan.sliced_labels), cfg["oracle_slices"]["count"],
                                cfg["oracle_slices"]["seed"])[:2]
     for sid in picks:
@@ -222,7 +223,7 @@ def test_batches_and_graph_replays_are_bitwise_identical():
 
 def test_autotuned_plan_matches_oracle_and_recaptures_graph():
     """After the autotuner has re-chosen tiles and split-K for every GEMM of the full-size
-    5x6 / 14-cycle plan (batch of 8 slices, the configuration bench.py times), a seeded
+    5x6 / 14-cycle plan (batch of 64 slices, the configuration bench.py times), a seeded
     slice still matches the oracle element by element, and the captured graph is rebuilt:
     two graph replays of the whole sum agree bitwise with each other."""
     from paper_2111_03011_amd.workload import config_workload
@@ -231,8 +232,8 @@ def test_autotuned_plan_matches_oracle_and_recaptures_graph():
     w = config_workload("sliced")
     c = _contraction(w.net, w.plan.path, sliced_labels=w.plan.sliced_labels,
                      slice_ids=w.slice_ids, open_qubits=w.open_qubits,
-                     closed_bits=w.closed_bits, max_batch_slices=8)
-    c.contract_range(0, 16)
+                     closed_bits=w.closed_bits, max_batch_slices=64)
+    c.contract_range(0, 64)
     changed = c.autotune(reps=1)
     log(f"  autotuner changed {changed} launches")
     sid = synth.slice_subset(len(w.plan.sliced_labels), cfg["oracle_slices"]["count"],
@@ -245,9 +246,9 @@ def test_autotuned_plan_matches_oracle_and_recaptures_graph():
     err = metrics.rel_error(got, ref)
     log(f"  slice {int(sid)}: rel err {err:.3e}")
     assert err <= TOL
-    c.contract_range(0, 64)
+    c.contract_range(0, 192)
     a = c.amps.cpu().numpy().copy()
-    c.contract_range(0, 64)
+    c.contract_range(0, 192)
     assert np.array_equal(a, c.amps.cpu().numpy())
     c.close()
 

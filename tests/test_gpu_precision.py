@@ -66,7 +66,7 @@ def test_split_sliced_config_one_slice_and_sum():
     cfg = synth.config("sliced")
     w = config_workload("sliced")
     kw = dict(sliced_labels=w.plan.sliced_labels, slice_ids=w.slice_ids,
-              open_qubits=w.open_qubits, closed_bits=w.closed_bits, max_batch_slices=8)
+              open_qubits=w.open_qubits, closed_bits=w.closed_bits, max_batch_slices=64)
     cs = _contraction(w.net, w.plan.path, precision=tnc.TNC_BF16X3, **kw)
     sid = int(synth.slice_subset(len(w.plan.sliced_labels), cfg["oracle_slices"]["count"],
                                  cfg["oracle_slices"]["seed"])[0])
