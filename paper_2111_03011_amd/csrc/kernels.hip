@@ -249,6 +249,7 @@ struct GemmTile {
   const int32_t* tab;
   int32_t a_off[A_LD], b_off[B_LD];
   uint32_t in_bits;   // bit i: A slot i in range; bit A_LD + i: B slot i in range
+  uint32_t full_bits; // in_bits of an interior tile (every existing slot in range)
 
   // (row, col) of A slot i and (k, n) of B slot i inside the tile
   __device__ __forceinline__ static int a_row(int i) {
@@ -327,6 +328,9 @@ struct GemmTile {
     const int nbm = a.nm < LBM ? a.nm : LBM, nbk = a.nk < LBK ? a.nk : LBK;
     const int nbn = a.nn < LBN ? a.nn : LBN;
     in_bits = 0;
+    full_bits = (1u << A_LD) - 1;
+#pragma unroll
+    for (int i = 0; i < B_LD; ++i) full_bits |= uint32_t(b_slot(i)) << (A_LD + i);
 #pragma unroll
     for (int i = 0; i < A_LD; ++i) {
       const int row = a_row(i), col = a_col(i);
@@ -491,7 +495,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
   float2 ra[A_LD], rb[B_LD];
   uint32_t valid = 0;
   auto store = [&](int stage) {
-    Tile::apply(valid, ra, rb);
+    if (valid != t.full_bits) Tile::apply(valid, ra, rb);
     float* as = As + stage * A_STAGE;
     float* bs = Bs + stage * B_STAGE;
 #pragma unroll
@@ -581,6 +585,22 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   lo = __bf16(x - float(hi));
 }
 
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+
+// (re, im) -> packed bf16 words hi = (bf16(re), bf16(im)), lo = (bf16(re - hi.re),
+// bf16(im - hi.im)), low half first; conversions round to nearest even
+__device__ __forceinline__ void split_pair(float2 x, uint32_t& hi, uint32_t& lo) {
+  f32x2v v;
+  v[0] = x.x;
+  v[1] = x.y;
+  const bf16x2 h = __builtin_convertvector(v, bf16x2);
+  hi = __builtin_bit_cast(uint32_t, h);
+  f32x2v r;
+  r[0] = x.x - __builtin_bit_cast(float, hi << 16);
+  r[1] = x.y - __builtin_bit_cast(float, hi & 0xffff0000u);
+  lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf16x2));
+}
+
 template <int WAVES_M, int WAVES_N, int UM, int UN, bool A_MFAST, bool B_NFAST, bool PRESPLIT>
 __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
   static_assert(WAVES_M * WAVES_N == 4, "four waves per workgroup");
@@ -610,59 +630,52 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
 
   float2 ra[A_LD], rb[B_LD];
   uint32_t valid = 0;
+  // LDS element offsets of this thread's load slots (A: row-major k pairs; B: the two
+  // embedded columns 2n and 2n + 1 of its (k, n) value)
+  int a_so[A_LD], b_so[B_LD];
+#pragma unroll
+  for (int i = 0; i < A_LD; ++i) a_so[i] = Tile::a_row(i) * RS + 2 * Tile::a_col(i);
+#pragma unroll
+  for (int i = 0; i < B_LD; ++i) b_so[i] = (2 * Tile::b_n(i)) * RS + 2 * Tile::b_kr(i);
   auto store = [&](int stage) {
-    Tile::apply(valid, ra, rb);
+    if (valid != t.full_bits) Tile::apply(valid, ra, rb);
     __bf16* ah = lds + stage * STAGE;
     __bf16* al = ah + A_PLANE;
     __bf16* bh = al + A_PLANE;
     __bf16* bl = bh + B_PLANE;
+    uint32_t wh[A_LD + B_LD], wl[A_LD + B_LD];   // packed (re, im) hi and lo words
     if (PRESPLIT) {
       // operands already hold (re_hi, im_hi | re_lo, im_lo) as two 32-bit words per element
 #pragma unroll
       for (int i = 0; i < A_LD; ++i) {
         const uint2 w = __builtin_bit_cast(uint2, ra[i]);
-        const int o = Tile::a_row(i) * RS + 2 * Tile::a_col(i);
-        *reinterpret_cast<uint32_t*>(&ah[o]) = w.x;
-        *reinterpret_cast<uint32_t*>(&al[o]) = w.y;
+        wh[i] = w.x;
+        wl[i] = w.y;
       }
 #pragma unroll
       for (int i = 0; i < B_LD; ++i) {
-        if (!(BK * BN % kThreads == 0 || threadIdx.x + i * kThreads < BK * BN)) continue;
         const uint2 w = __builtin_bit_cast(uint2, rb[i]);
-        const int o0 = (2 * Tile::b_n(i)) * RS + 2 * Tile::b_kr(i);
-        const int o1 = o0 + RS;
-        // column 2n: (re, -im) = flip the sign of the upper half; column 2n+1: (im, re)
-        *reinterpret_cast<uint32_t*>(&bh[o0]) = w.x ^ 0x80000000u;
-        *reinterpret_cast<uint32_t*>(&bh[o1]) = (w.x >> 16) | (w.x << 16);
-        *reinterpret_cast<uint32_t*>(&bl[o0]) = w.y ^ 0x80000000u;
-        *reinterpret_cast<uint32_t*>(&bl[o1]) = (w.y >> 16) | (w.y << 16);
+        wh[A_LD + i] = w.x;
+        wl[A_LD + i] = w.y;
       }
-      return;
+    } else {
+#pragma unroll
+      for (int i = 0; i < A_LD + B_LD; ++i) split_pair(i < A_LD ? ra[i] : rb[i - A_LD], wh[i], wl[i]);
     }
 #pragma unroll
     for (int i = 0; i < A_LD; ++i) {
-      __bf16 h0, l0, h1, l1;
-      split_bf16(ra[i].x, h0, l0);
-      split_bf16(ra[i].y, h1, l1);
-      bf16x2 h, l;
-      h[0] = h0; h[1] = h1; l[0] = l0; l[1] = l1;
-      const int o = Tile::a_row(i) * RS + 2 * Tile::a_col(i);
-      *reinterpret_cast<bf16x2*>(&ah[o]) = h;
-      *reinterpret_cast<bf16x2*>(&al[o]) = l;
+      *reinterpret_cast<uint32_t*>(&ah[a_so[i]]) = wh[i];
+      *reinterpret_cast<uint32_t*>(&al[a_so[i]]) = wl[i];
     }
 #pragma unroll
     for (int i = 0; i < B_LD; ++i) {
-      if (!(BK * BN % kThreads == 0 || threadIdx.x + i * kThreads < BK * BN)) continue;
-      __bf16 rh, rl, ih, il;
-      split_bf16(rb[i].x, rh, rl);
-      split_bf16(rb[i].y, ih, il);
-      const int o0 = (2 * Tile::b_n(i)) * RS + 2 * Tile::b_kr(i);     // column 2n
-      const int o1 = o0 + RS;                                 // column 2n+1
-      bf16x2 v;
-      v[0] = rh; v[1] = -ih; *reinterpret_cast<bf16x2*>(&bh[o0]) = v;
-      v[0] = ih; v[1] = rh;  *reinterpret_cast<bf16x2*>(&bh[o1]) = v;
-      v[0] = rl; v[1] = -il; *reinterpret_cast<bf16x2*>(&bl[o0]) = v;
-      v[0] = il; v[1] = rl;  *reinterpret_cast<bf16x2*>(&bl[o1]) = v;
+      if (!Tile::b_slot(i)) continue;
+      const uint32_t h = wh[A_LD + i], l = wl[A_LD + i];
+      // column 2n: (re, -im) = flip the sign of the upper half; column 2n+1: (im, re)
+      *reinterpret_cast<uint32_t*>(&bh[b_so[i]]) = h ^ 0x80000000u;
+      *reinterpret_cast<uint32_t*>(&bh[b_so[i] + RS]) = (h >> 16) | (h << 16);
+      *reinterpret_cast<uint32_t*>(&bl[b_so[i]]) = l ^ 0x80000000u;
+      *reinterpret_cast<uint32_t*>(&bl[b_so[i] + RS]) = (l >> 16) | (l << 16);
     }
   };
 
