@@ -251,22 +251,24 @@ struct GemmTile {
   uint32_t in_bits;   // bit i: A slot i in range; bit A_LD + i: B slot i in range
   uint32_t full_bits; // in_bits of an interior tile (every existing slot in range)
 
-  // (row, col) of A slot i and (k, n) of B slot i inside the tile
+  // (row, col) of A slot i and (k, n) of B slot i inside the tile.  Consecutive lanes take
+  // consecutive addresses of the operand's fastest index (coalesced loads); when that index
+  // is m (n), a thread's slots are consecutive k of one row (column).
   __device__ __forceinline__ static int a_row(int i) {
     const int q = threadIdx.x + i * kThreads;
-    return A_MFAST ? q % BM : q / BK;
+    return A_MFAST ? int(threadIdx.x) % BM : q / BK;
   }
   __device__ __forceinline__ static int a_col(int i) {
     const int q = threadIdx.x + i * kThreads;
-    return A_MFAST ? q / BM : q % BK;
+    return A_MFAST ? (int(threadIdx.x) / BM) * A_LD + i : q % BK;
   }
   __device__ __forceinline__ static int b_kr(int i) {
     const int q = threadIdx.x + i * kThreads;
-    return B_NFAST ? q / BN : q % BK;
+    return B_NFAST ? (BK * BN >= kThreads ? (int(threadIdx.x) / BN) * B_LD + i : q / BN) : q % BK;
   }
   __device__ __forceinline__ static int b_n(int i) {
     const int q = threadIdx.x + i * kThreads;
-    return B_NFAST ? q % BN : q / BK;
+    return B_NFAST ? (BK * BN >= kThreads ? int(threadIdx.x) % BN : q % BN) : q / BK;
   }
   __device__ __forceinline__ static bool b_slot(int i) {
     return BK * BN % kThreads == 0 || threadIdx.x + i * kThreads < BK * BN;
@@ -279,7 +281,19 @@ struct GemmTile {
     const int64_t tiles_n = (N + BN - 1) / BN;
     const int64_t tile = xcd_remap(blockIdx.x, gridDim.x);
     if (tile >= tiles_m * tiles_n) return false;
-    const int64_t tm = tile % tiles_m, tn = tile / tiles_m;
+    // grouped numbering: consecutive tiles (one XCD's range after the remap) cover a block
+    // of group_m tile rows by several tile columns, so they share A and B panels in L2
+    int64_t tm, tn;
+    if (a.group_m > 1) {
+      const int64_t gm = a.group_m;
+      const int64_t per_group = gm * tiles_n, g = tile / per_group, first = g * gm;
+      const int64_t gsize = (tiles_m - first < gm) ? tiles_m - first : gm;
+      tm = first + (tile % per_group) % gsize;
+      tn = (tile % per_group) / gsize;
+    } else {
+      tm = tile % tiles_m;
+      tn = tile / tiles_m;
+    }
     const int64_t z = int64_t(blockIdx.y) + int64_t(blockIdx.z) * gridDim.y;
     zr = z / a.k_splits;      // slice * rows + row
     ks = int(z % a.k_splits);
@@ -630,13 +644,22 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
 
   float2 ra[A_LD], rb[B_LD];
   uint32_t valid = 0;
+  // LDS rows hold 32 bf16 of k in four 16-byte chunks; chunk c of row r is stored at
+  // position c ^ ((r >> 4) & 3), so that lanes writing the same k of consecutive rows hit
+  // different banks while the 16-lane groups of the fragment reads stay conflict-free
+  auto lds_off = [](int row, int kq) {
+    return row * RS + ((((kq >> 3) ^ (row >> 4)) & 3) << 3) + (kq & 7);
+  };
   // LDS element offsets of this thread's load slots (A: row-major k pairs; B: the two
   // embedded columns 2n and 2n + 1 of its (k, n) value)
-  int a_so[A_LD], b_so[B_LD];
+  int a_so[A_LD], b_so0[B_LD], b_so1[B_LD];
 #pragma unroll
-  for (int i = 0; i < A_LD; ++i) a_so[i] = Tile::a_row(i) * RS + 2 * Tile::a_col(i);
+  for (int i = 0; i < A_LD; ++i) a_so[i] = lds_off(Tile::a_row(i), 2 * Tile::a_col(i));
 #pragma unroll
-  for (int i = 0; i < B_LD; ++i) b_so[i] = (2 * Tile::b_n(i)) * RS + 2 * Tile::b_kr(i);
+  for (int i = 0; i < B_LD; ++i) {
+    b_so0[i] = lds_off(2 * Tile::b_n(i), 2 * Tile::b_kr(i));
+    b_so1[i] = lds_off(2 * Tile::b_n(i) + 1, 2 * Tile::b_kr(i));
+  }
   auto store = [&](int stage) {
     if (valid != t.full_bits) Tile::apply(valid, ra, rb);
     __bf16* ah = lds + stage * STAGE;
@@ -672,19 +695,22 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
       if (!Tile::b_slot(i)) continue;
       const uint32_t h = wh[A_LD + i], l = wl[A_LD + i];
       // column 2n: (re, -im) = flip the sign of the upper half; column 2n+1: (im, re)
-      *reinterpret_cast<uint32_t*>(&bh[b_so[i]]) = h ^ 0x80000000u;
-      *reinterpret_cast<uint32_t*>(&bh[b_so[i] + RS]) = (h >> 16) | (h << 16);
-      *reinterpret_cast<uint32_t*>(&bl[b_so[i]]) = l ^ 0x80000000u;
-      *reinterpret_cast<uint32_t*>(&bl[b_so[i] + RS]) = (l >> 16) | (l << 16);
+      *reinterpret_cast<uint32_t*>(&bh[b_so0[i]]) = h ^ 0x80000000u;
+      *reinterpret_cast<uint32_t*>(&bh[b_so1[i]]) = (h >> 16) | (h << 16);
+      *reinterpret_cast<uint32_t*>(&bl[b_so0[i]]) = l ^ 0x80000000u;
+      *reinterpret_cast<uint32_t*>(&bl[b_so1[i]]) = (l >> 16) | (l << 16);
     }
   };
 
   const int half = lane >> 5, j32 = lane & 31;
-  int a_rd[UM], b_rd[UN];
+  int a_rd[2][UM], b_rd[2][UN];   // per k step: 16 bytes at k = 8 (half + 2 step)
 #pragma unroll
-  for (int i = 0; i < UM; ++i) a_rd[i] = (wm * UM * 32 + i * 32 + j32) * RS + 8 * half;
+  for (int ks = 0; ks < 2; ++ks) {
 #pragma unroll
-  for (int j = 0; j < UN; ++j) b_rd[j] = (2 * (wn * UN * 16 + j * 16) + j32) * RS + 8 * half;
+    for (int i = 0; i < UM; ++i) a_rd[ks][i] = lds_off(wm * UM * 32 + i * 32 + j32, 8 * (half + 2 * ks));
+#pragma unroll
+    for (int j = 0; j < UN; ++j) b_rd[ks][j] = lds_off(2 * (wn * UN * 16 + j * 16) + j32, 8 * (half + 2 * ks));
+  }
 
   int stage = 0;
   if (t.k_begin < t.k_end) {
@@ -704,13 +730,13 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
       bf16x8 xah[UM], xal[UM], xbh[UN], xbl[UN];
 #pragma unroll
       for (int i = 0; i < UM; ++i) {
-        xah[i] = *reinterpret_cast<const bf16x8*>(&ah[a_rd[i] + 16 * kstep]);
-        xal[i] = *reinterpret_cast<const bf16x8*>(&al[a_rd[i] + 16 * kstep]);
+        xah[i] = *reinterpret_cast<const bf16x8*>(&ah[a_rd[kstep][i]]);
+        xal[i] = *reinterpret_cast<const bf16x8*>(&al[a_rd[kstep][i]]);
       }
 #pragma unroll
       for (int j = 0; j < UN; ++j) {
-        xbh[j] = *reinterpret_cast<const bf16x8*>(&bh[b_rd[j] + 16 * kstep]);
-        xbl[j] = *reinterpret_cast<const bf16x8*>(&bl[b_rd[j] + 16 * kstep]);
+        xbh[j] = *reinterpret_cast<const bf16x8*>(&bh[b_rd[kstep][j]]);
+        xbl[j] = *reinterpret_cast<const bf16x8*>(&bl[b_rd[kstep][j]]);
       }
 #pragma unroll
       for (int i = 0; i < UM; ++i)

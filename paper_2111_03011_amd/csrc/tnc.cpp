@@ -434,6 +434,8 @@ struct Compiler {
   }
 
   static void choose_tiles(GemmArgs& g, int64_t M, int64_t N, int64_t Kd, int64_t rows) {
+    static const int group = std::getenv("TNC_GEMM_GROUP") ? std::atoi(std::getenv("TNC_GEMM_GROUP")) : 4;
+    g.group_m = group;
     const char* force = std::getenv("TNC_GEMM_CONFIG");
     const char* blocks_env = std::getenv("TNC_SPLITK_BLOCKS");
     const int64_t target = blocks_env ? std::atoll(blocks_env) : 2048;

@@ -68,6 +68,7 @@ struct GemmArgs {
   // offsets within one slice fit in 31 bits.
   const int32_t* stk;
   const int32_t* perm;
+  int group_m;                // tiles are numbered in groups of group_m tile rows (L2 reuse)
 };
 
 struct ReduceArgs {           // C[i] = sum_s partial[s][i]  (i over every slice of the launch)
