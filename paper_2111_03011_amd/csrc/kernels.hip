@@ -1100,13 +1100,14 @@ hipError_t launch_stream(const StreamArgs& a, hipStream_t s) {
 
 // Tile configurations (complex elements): 0 = 128 x 64 (2x2 waves, 2x2 MFMA tiles each),
 // 1 = 128 x 16 (4x1 waves, one MFMA tile each), 2 = 64 x 32 (2x2 waves, one tile each),
-// 3 = 128 x 128 (2x2 waves, 2x4 MFMA tiles each).
+// 3 = 128 x 128 (2x2 waves, 2x4 MFMA tiles each), 4 = 128 x 32 (4x1 waves, 1x2 tiles each).
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t s) {
   switch (a.config) {
     case 0: return launch_gemm_cfg<2, 2, 2, 2, 16>(a, s);
     case 1: return launch_gemm_cfg<4, 1, 1, 1, 16>(a, s);
     case 2: return launch_gemm_cfg<2, 2, 1, 1, 16>(a, s);
     case 3: return launch_gemm_cfg<2, 2, 2, 4, 16>(a, s);
+    case 4: return launch_gemm_cfg<4, 1, 1, 2, 16>(a, s);
   }
   return hipErrorInvalidValue;
 }

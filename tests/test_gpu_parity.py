@@ -46,6 +46,8 @@ def _pair_case(rank_a, rank_b, shared, seed, order_a=None, order_b=None):
     (15, 13, 5, list(range(5)) + list(range(5, 15)), list(range(15, 23)) + list(range(5)), 1),
     # GEMM after permutes (labels interleaved)
     (14, 12, 5, [5, 0, 6, 1, 7, 2, 8, 3, 9, 4, 10, 11, 12, 13], None, 1),
+    # N = 32 with M >= 128 (128 x 32 tiles)
+    (14, 11, 6, None, None, 1),
     # narrow N (<= 16), small M (<= 64), long K with split-K
     (20, 16, 12, None, None, 1),
     (10, 17, 5, None, None, 1),
