@@ -252,3 +252,77 @@ def test_automatic_batch_size():
     assert b == 1 << math.ceil(math.log2(2.5e11 / flops))
     tnc.tnc_plan_destroy(p)
     tnc.tnc_net_destroy(h)
+
+
+def _grouped_pair_net(n_ca, n_oa, n_cb, n_ob, nk, L, seed):
+    from paper_2111_03011_amd.network import TensorNetwork
+    rng = np.random.default_rng(seed)
+    k = list(range(nk))
+    nxt = nk
+    ca = list(range(nxt, nxt + n_ca)); nxt += n_ca
+    oa = list(range(nxt, nxt + n_oa)); nxt += n_oa
+    cb = list(range(nxt, nxt + n_cb)); nxt += n_cb
+    ob = list(range(nxt, nxt + n_ob)); nxt += n_ob
+    la, lb = ca + oa + k, k + cb + ob
+    ta = rng.normal(size=(2,) * len(la)) + 0j
+    tb = rng.normal(size=(2,) * len(lb)) + 0j
+    outs = ca + oa + cb + ob
+    n = len(outs)
+    net = TensorNetwork(n_qubits=n, tensors=[ta, tb], labels=[la, lb], out_label=outs,
+                        bond_label={})
+    open_q = list(range(n_ca, n_ca + n_oa)) + list(range(n_ca + n_oa + n_cb, n))
+    closed = synth.group_targets(n, open_q, L, seed + 1)
+    return net, open_q, closed
+
+
+@pytest.mark.parametrize("case,mode", [
+    ((5, 2, 5, 2, 8, 1024), 2),   # 1024 rows share 32 rows of each operand: stacked
+    ((1, 7, 1, 7, 8, 4), 0),      # M = N = 128 per row: plain per-row tiles
+])
+def test_sparse_row_gemm_plan(case, mode):
+    """The compiled GEMM of a grouped pair network: per-row shape and algorithmic flops
+    (rows x 8MNK) follow from the groups (Appendix A), and small per-row M with shared
+    N-side rows is stacked (row mode 2)."""
+    net, open_q, closed = _grouped_pair_net(*case, seed=17)
+    h = tnc.tnc_net_create(0, net.n_qubits, net.ranks(), net.flat_labels(), net.flat_data(),
+                           net.out_label)
+    tnc.tnc_net_set_path(h, [(0, 1)])
+    tnc.tnc_net_set_targets(h, open_q, closed)
+    p = tnc.tnc_plan_create(h, tnc.TNC_C64, 1)
+    infos = [tnc.tnc_plan_launch_info(p, i) for i in range(tnc.tnc_plan_n_launches(p))]
+    g = [i for i in infos if i.kind == 1]
+    assert len(g) == 1
+    g = g[0]
+    n_ca, n_oa, n_cb, n_ob, nk, L = case
+    assert g.rows == L and g.k == 1 << nk
+    assert {g.m, g.n} == {1 << n_oa, 1 << n_ob}
+    assert math.isclose(g.flops, 8.0 * L * (1 << (n_oa + n_ob + nk)), rel_tol=1e-12)
+    assert g.row_mode == mode
+    tnc.tnc_plan_destroy(p)
+    tnc.tnc_net_destroy(h)
+
+
+def test_plan_log_lists_gemms():
+    """TNC_PLAN_LOG prints one line per GEMM and stream launch of a compiled plan."""
+    import subprocess
+    import sys
+    code = ("import synth\n"
+            "from paper_2111_03011_amd import tnc\n"
+            "from paper_2111_03011_amd.workload import make_workload\n"
+            "c = synth.make_circuit(3, 3, 8, 21)\n"
+            "closed = synth.group_targets(9, [4], 20, 2)\n"
+            "w = make_workload(c, [4], closed, max_log2=7, trials=2, seed=3)\n"
+            "h = tnc.tnc_net_create(0, 9, w.net.ranks(), w.net.flat_labels(), w.net.flat_data(), w.net.out_label)\n"
+            "tnc.tnc_net_set_path(h, w.plan.path)\n"
+            "tnc.tnc_net_set_slices(h, w.plan.sliced_labels, w.slice_ids)\n"
+            "tnc.tnc_net_set_targets(h, [4], closed)\n"
+            "p = tnc.tnc_plan_create(h, tnc.TNC_C64, 1)\n"
+            "print(sum(1 for i in range(tnc.tnc_plan_n_launches(p)) if tnc.tnc_plan_launch_info(p, i).kind in (1, 2)))\n")
+    root = __file__.rsplit("/", 2)[0]
+    env = dict(__import__("os").environ, TNC_PLAN_LOG="1", PYTHONPATH=root)
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                         cwd=root, timeout=120)
+    assert out.returncode == 0, out.stderr[-2000:]
+    n = int(out.stdout.strip().splitlines()[-1])
+    lines = [l for l in out.stderr.splitlines() if l.startswith("[tnc plan]")]
+    assert len(lines) == n and n > 0
