@@ -645,10 +645,10 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
   float2 ra[A_LD], rb[B_LD];
   uint32_t valid = 0;
   // LDS rows hold 32 bf16 of k in four 16-byte chunks; chunk c of row r is stored at
-  // position c ^ ((r >> 4) & 3), so that lanes writing the same k of consecutive rows hit
-  // different banks while the 16-lane groups of the fragment reads stay conflict-free
+  // position c ^ ((r >> 3) & 3), so that 16-byte writes to every other row (the embedded
+  // B columns 2n) and fragment reads of eight consecutive rows are free of bank conflicts
   auto lds_off = [](int row, int kq) {
-    return row * RS + ((((kq >> 3) ^ (row >> 4)) & 3) << 3) + (kq & 7);
+    return row * RS + ((((kq >> 3) ^ (row >> 3)) & 3) << 3) + (kq & 7);
   };
   // LDS element offsets of this thread's load slots (A: row-major k pairs; B: the two
   // embedded columns 2n and 2n + 1 of its (k, n) value)
@@ -685,20 +685,47 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
 #pragma unroll
       for (int i = 0; i < A_LD + B_LD; ++i) split_pair(i < A_LD ? ra[i] : rb[i - A_LD], wh[i], wl[i]);
     }
+    if (A_MFAST) {
+      // a thread's A slots are consecutive k of one row: whole 16-byte chunks
 #pragma unroll
-    for (int i = 0; i < A_LD; ++i) {
-      *reinterpret_cast<uint32_t*>(&ah[a_so[i]]) = wh[i];
-      *reinterpret_cast<uint32_t*>(&al[a_so[i]]) = wl[i];
+      for (int c = 0; c < A_LD / 4; ++c) {
+        *reinterpret_cast<uint4*>(&ah[a_so[4 * c]]) =
+            make_uint4(wh[4 * c], wh[4 * c + 1], wh[4 * c + 2], wh[4 * c + 3]);
+        *reinterpret_cast<uint4*>(&al[a_so[4 * c]]) =
+            make_uint4(wl[4 * c], wl[4 * c + 1], wl[4 * c + 2], wl[4 * c + 3]);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < A_LD; ++i) {
+        *reinterpret_cast<uint32_t*>(&ah[a_so[i]]) = wh[i];
+        *reinterpret_cast<uint32_t*>(&al[a_so[i]]) = wl[i];
+      }
     }
+    // embedded B: column 2n holds (re, -im) = the hi/lo word with the upper half's sign
+    // flipped, column 2n+1 holds (im, re) = the halves swapped
+    auto col0 = [](uint32_t w) { return w ^ 0x80000000u; };
+    auto col1 = [](uint32_t w) { return (w >> 16) | (w << 16); };
+    if (B_NFAST && B_LD % 4 == 0) {
+      // a thread's B slots are consecutive k of one column: whole 16-byte chunks
 #pragma unroll
-    for (int i = 0; i < B_LD; ++i) {
-      if (!Tile::b_slot(i)) continue;
-      const uint32_t h = wh[A_LD + i], l = wl[A_LD + i];
-      // column 2n: (re, -im) = flip the sign of the upper half; column 2n+1: (im, re)
-      *reinterpret_cast<uint32_t*>(&bh[b_so0[i]]) = h ^ 0x80000000u;
-      *reinterpret_cast<uint32_t*>(&bh[b_so1[i]]) = (h >> 16) | (h << 16);
-      *reinterpret_cast<uint32_t*>(&bl[b_so0[i]]) = l ^ 0x80000000u;
-      *reinterpret_cast<uint32_t*>(&bl[b_so1[i]]) = (l >> 16) | (l << 16);
+      for (int c = 0; c < B_LD / 4; ++c) {
+        const uint32_t* h = wh + A_LD + 4 * c;
+        const uint32_t* l = wl + A_LD + 4 * c;
+        *reinterpret_cast<uint4*>(&bh[b_so0[4 * c]]) = make_uint4(col0(h[0]), col0(h[1]), col0(h[2]), col0(h[3]));
+        *reinterpret_cast<uint4*>(&bh[b_so1[4 * c]]) = make_uint4(col1(h[0]), col1(h[1]), col1(h[2]), col1(h[3]));
+        *reinterpret_cast<uint4*>(&bl[b_so0[4 * c]]) = make_uint4(col0(l[0]), col0(l[1]), col0(l[2]), col0(l[3]));
+        *reinterpret_cast<uint4*>(&bl[b_so1[4 * c]]) = make_uint4(col1(l[0]), col1(l[1]), col1(l[2]), col1(l[3]));
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < B_LD; ++i) {
+        if (!Tile::b_slot(i)) continue;
+        const uint32_t h = wh[A_LD + i], l = wl[A_LD + i];
+        *reinterpret_cast<uint32_t*>(&bh[b_so0[i]]) = col0(h);
+        *reinterpret_cast<uint32_t*>(&bh[b_so1[i]]) = col1(h);
+        *reinterpret_cast<uint32_t*>(&bl[b_so0[i]]) = col0(l);
+        *reinterpret_cast<uint32_t*>(&bl[b_so1[i]]) = col1(l);
+      }
     }
   };
 
