@@ -233,7 +233,7 @@ constexpr int kKLevels = 4;
 template <int BM, int BN, int BK, bool A_MFAST, bool B_NFAST, bool LDS_TAB>
 struct GemmTile {
   static constexpr int LBM = (BM == 128) ? 7 : (BM == 64 ? 6 : 5);
-  static constexpr int LBN = (BN == 128) ? 7 : (BN == 64 ? 6 : (BN == 32 ? 5 : 4));
+  static constexpr int LBN = (BN == 128) ? 7 : (BN == 64 ? 6 : (BN == 32 ? 5 : (BN == 16 ? 4 : 3)));
   static constexpr int LBK = (BK == 16) ? 4 : (BK == 32 ? 5 : 3);
   static constexpr int A_LD = BM * BK / kThreads;
   static constexpr int B_LD = (BK * BN + kThreads - 1) / kThreads;
@@ -435,6 +435,20 @@ struct GemmTile {
                : reinterpret_cast<float*>(a.C + sl * a.c_slice_stride + r * a.c_row_stride);
   }
 
+  // first float of output row `row` of this tile (plain, split-K partial or stacked), or
+  // nullptr when that row lies outside the output
+  __device__ __forceinline__ float* row_ptr(const GemmArgs& a, int row) const {
+    if (a.stk) {
+      const int64_t w = (m0 & 127) + row, rr = w >> a.nm;
+      if (rr >= stk_count) return nullptr;
+      const int64_t cr = a.perm[stk_start + rr];
+      return reinterpret_cast<float*>(a.C + sl * a.c_slice_stride) +
+             (cr * a.c_row_stride + (w & ((int64_t(1) << a.nm) - 1)) * N) * 2;
+    }
+    if (m0 + row >= M) return nullptr;
+    return out(a) + (m0 + row) * N * 2;
+  }
+
   // 32x32 accumulator layout: column = lane % 32, row = 8 (v/4) + 4 (lane/32) + v%4; the
   // real column j is complex column j/2, real part for even j
   template <int UM, int UN>
@@ -580,6 +594,94 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
     stage ^= 1;
   }
   t.template store_acc<UM, UN>(a, acc, wm * UM * 32, wn * UN * 16);
+}
+
+// ---------------------------------------------------------------------------------
+// complex64 GEMM for N <= 8 on v_mfma_f32_16x16x4f32: the same real embedding with 16 real
+// output columns (8 complex), each instruction consuming two complex k, so narrow steps do
+// not pay for a 32-column MFMA tile.  Tile 128 x 8 complex: four waves of 32 rows, two
+// 16-row MFMA tiles each.  Lane layout of the 16x16x4 operands: A row = lane % 16, real k =
+// lane / 16; B real k = lane / 16, column = lane % 16; D rows 4 (lane / 16) + v, column
+// lane % 16 (real column j is complex column j / 2, real part for even j).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <bool A_MFAST, bool B_NFAST>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_gemm_n8(GemmArgs a) {
+  constexpr int BM = 128, BN = 8, BK = 16, UM = 2;
+  using Tile = GemmTile<BM, BN, BK, A_MFAST, B_NFAST, true>;
+  constexpr int A_LD = Tile::A_LD, B_LD = Tile::B_LD;
+  constexpr int AS = 2 * BK + 2, BS = 2 * BN;
+  constexpr int A_STAGE = BM * AS, B_STAGE = BK * BS;
+  __shared__ float As[2 * A_STAGE];
+  __shared__ float Bs[2 * B_STAGE];
+  __shared__ int32_t ktab[Tile::kTab];
+
+  Tile t;
+  if (!t.init(a, ktab)) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  f32x4 acc[UM];
+#pragma unroll
+  for (int i = 0; i < UM; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[i][v] = 0.f;
+
+  float2 ra[A_LD], rb[B_LD];
+  uint32_t valid = 0;
+  auto store = [&](int stage) {
+    if (valid != t.full_bits) Tile::apply(valid, ra, rb);
+    float* as = As + stage * A_STAGE;
+    float* bs = Bs + stage * B_STAGE;
+#pragma unroll
+    for (int i = 0; i < A_LD; ++i)
+      *reinterpret_cast<float2*>(&as[Tile::a_row(i) * AS + 2 * Tile::a_col(i)]) = ra[i];
+#pragma unroll
+    for (int i = 0; i < B_LD; ++i)
+      if (Tile::b_slot(i))
+        *reinterpret_cast<float2*>(&bs[Tile::b_kr(i) * BS + 2 * Tile::b_n(i)]) = rb[i];
+  };
+
+  const int r16 = lane & 15, q = lane >> 4;     // q: real k within the instruction
+  const int part = q & 1, col = r16, bc = col & 1;
+  const bool b_take_im = (part != bc);
+  const float b_sign = (part == 1 && bc == 0) ? -1.f : 1.f;
+  int a_rd[UM];
+#pragma unroll
+  for (int i = 0; i < UM; ++i) a_rd[i] = (wave * 32 + i * 16 + r16) * AS + q;
+  const int b_rd = (q >> 1) * BS + 2 * (col >> 1);
+
+  int stage = 0;
+  if (t.k_begin < t.k_end) {
+    t.load(a, t.k_begin, ra, rb, valid);
+    store(0);
+  }
+  __syncthreads();
+  for (int64_t k0 = t.k_begin; k0 < t.k_end; k0 += BK) {
+    const bool more = k0 + BK < t.k_end;
+    if (more) t.load(a, k0 + BK, ra, rb, valid);
+    const float* as = As + stage * A_STAGE;
+    const float* bs = Bs + stage * B_STAGE;
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 2) {
+      float af[UM];
+#pragma unroll
+      for (int i = 0; i < UM; ++i) af[i] = as[a_rd[i] + 2 * kk];
+      const float2 bv = *reinterpret_cast<const float2*>(&bs[kk * BS + b_rd]);
+      const float bf = (b_take_im ? bv.y : bv.x) * b_sign;
+#pragma unroll
+      for (int i = 0; i < UM; ++i) acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf, acc[i], 0, 0, 0);
+    }
+    if (more) store(stage ^ 1);
+    __syncthreads();
+    stage ^= 1;
+  }
+  const int64_t np = t.n0 + (col >> 1);
+#pragma unroll
+  for (int i = 0; i < UM; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      float* o = t.row_ptr(a, wave * 32 + i * 16 + 4 * q + v);
+      if (o && np < t.N) o[np * 2 + bc] = acc[i][v];
+    }
 }
 
 // ---------------------------------------------------------------------------------
@@ -1127,8 +1229,30 @@ hipError_t launch_stream(const StreamArgs& a, hipStream_t s) {
 
 // Tile configurations (complex elements): 0 = 128 x 64 (2x2 waves, 2x2 MFMA tiles each),
 // 1 = 128 x 16 (4x1 waves, one MFMA tile each), 2 = 64 x 32 (2x2 waves, one tile each),
-// 3 = 128 x 128 (2x2 waves, 2x4 MFMA tiles each), 4 = 128 x 32 (4x1 waves, 1x2 tiles each).
+// 3 = 128 x 128 (2x2 waves, 2x4 MFMA tiles each), 4 = 128 x 32 (4x1 waves, 1x2 tiles each),
+// 5 = 128 x 8 on 16x16x4 MFMA tiles (complex64 only; split precision uses 1).
+hipError_t launch_gemm_n8(const GemmArgs& a, hipStream_t s) {
+  const int64_t tiles = ((a.M + 127) / 128) * ((a.N + 7) / 8);
+  const int64_t zs = a.rows * a.nb * a.k_splits;
+  const int64_t gy = zs < 65535 ? zs : 65535;
+  const int64_t gz = (zs + gy - 1) / gy;
+  const dim3 grid{unsigned(tiles), unsigned(gy), unsigned(gz)};
+  switch ((a.a_mfast ? 1 : 0) | (a.b_nfast ? 2 : 0)) {
+    case 0: hipLaunchKernelGGL((k_gemm_n8<false, false>), grid, dim3(kThreads), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_gemm_n8<true, false>), grid, dim3(kThreads), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_gemm_n8<false, true>), grid, dim3(kThreads), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_gemm_n8<true, true>), grid, dim3(kThreads), 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t s) {
+  if (a.config == 5) {
+    if (a.precision == 0) return launch_gemm_n8(a, s);
+    GemmArgs b = a;            // the split-precision kernels have no 8-wide tile
+    b.config = 1;
+    return launch_gemm(b, s);
+  }
   switch (a.config) {
     case 0: return launch_gemm_cfg<2, 2, 2, 2, 16>(a, s);
     case 1: return launch_gemm_cfg<4, 1, 1, 1, 16>(a, s);

@@ -414,7 +414,8 @@ struct Compiler {
   // Estimated fraction of the MFMA tile work that is useful, for P on the M side
   static double tile_fill(const TState& P, const TState& Q, const TState& C, int nm, int nn) {
     const int64_t M = int64_t(1) << nm, N = int64_t(1) << nn, rows = C.rows();
-    static const int64_t kBM[5] = {128, 128, 64, 128, 128}, kBN[5] = {64, 16, 32, 128, 32};
+    static const int64_t kBM[kConfigs] = {128, 128, 64, 128, 128, 128};
+    static const int64_t kBN[kConfigs] = {64, 16, 32, 128, 32, 8};
     int64_t m_eff = M;
     if (rows > 1 && Q.rows() == 1 && P.q == C.q && M >= 128) m_eff = M * rows;
     double fm;
@@ -424,11 +425,13 @@ struct Compiler {
       std::vector<int32_t> stk, perm;
       fm = std::max(fm, stack_rows(Q, C, M, stk, perm));
     }
+    // an N <= 8 step is charged as a 16-wide tile: its 16x16x4 tiles reuse operands less
+    // than a stacked orientation of the same step would
     const int cfg_n = (N <= 16) ? 1 : (N <= 32 ? 4 : 0);
     return fm * std::min(1.0, double(N) / double(kBN[cfg_n]));
   }
 
-  static constexpr int kConfigs = 5;   // GEMM tile configurations (see launch_gemm)
+  static constexpr int kConfigs = 6;   // GEMM tile configurations (see launch_gemm)
 
   static bool stacking_enabled() {
     static const bool on = std::getenv("TNC_NO_STACK") == nullptr;
@@ -441,10 +444,10 @@ struct Compiler {
     const char* force = std::getenv("TNC_GEMM_CONFIG");
     const char* blocks_env = std::getenv("TNC_SPLITK_BLOCKS");
     const int64_t target = blocks_env ? std::atoll(blocks_env) : 2048;
-    g.config = (N <= 16) ? 1 : (M <= 64 ? 2 : (N <= 32 ? 4 : 0));
+    g.config = (N <= 8) ? 5 : (N <= 16) ? 1 : (M <= 64 ? 2 : (N <= 32 ? 4 : 0));
     if (force) g.config = std::min(kConfigs - 1, std::max(0, std::atoi(force)));
-    static const int64_t kBM[kConfigs] = {128, 128, 64, 128, 128};
-    static const int64_t kBN[kConfigs] = {64, 16, 32, 128, 32};
+    static const int64_t kBM[kConfigs] = {128, 128, 64, 128, 128, 128};
+    static const int64_t kBN[kConfigs] = {64, 16, 32, 128, 32, 8};
     const int64_t BM = kBM[g.config], BN = kBN[g.config];
     const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN) * rows;
     g.k_splits = 1;
@@ -1215,6 +1218,7 @@ int autotune(tnc_plan_s& p, uint8_t* ws, hipStream_t st, int reps) {
         // the planned choice is timed first, so that it survives ties
         std::vector<std::pair<int, int>> cands{best};
         for (int cfg = 0; cfg < Compiler::kConfigs; ++cfg)
+          if (cfg != 5 || L.gm.precision == 0)
           for (int sp = 1; sp <= L.max_splits; sp *= 2)
             if ((sp == 1 || L.gm.K / sp >= 256) && std::make_pair(cfg, sp) != best)
               cands.push_back({cfg, sp});

@@ -48,6 +48,9 @@ def _pair_case(rank_a, rank_b, shared, seed, order_a=None, order_b=None):
     (14, 12, 5, [5, 0, 6, 1, 7, 2, 8, 3, 9, 4, 10, 11, 12, 13], None, 1),
     # N = 32 with M >= 128 (128 x 32 tiles)
     (14, 11, 6, None, None, 1),
+    # N = 8 and N = 2 (128 x 8 tiles on 16x16x4 matrix instructions), ragged K order
+    (18, 10, 7, None, None, 1),
+    (16, 8, 7, None, [16, 0, 1, 2, 3, 4, 5, 6], 1),
     # narrow N (<= 16), small M (<= 64), long K with split-K
     (20, 16, 12, None, None, 1),
     (10, 17, 5, None, None, 1),
