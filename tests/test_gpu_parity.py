@@ -351,3 +351,35 @@ def test_degenerate_cases():
                                        sliced_bonds=w.sliced_bonds,
                                        slice_ids=[int(x) for x in w.slice_ids])
     assert metrics.rel_error(ref, oref) <= TOL
+
+
+@pytest.mark.parametrize("precision", [0, 2])
+@pytest.mark.parametrize("config", [0, 1, 2, 3, 4, 5])
+def test_every_tile_configuration(config, precision):
+    """Each GEMM tile configuration (forced with TNC_GEMM_CONFIG), without and with split-K
+    (TNC_SPLITK_BLOCKS), on a product whose M and N are smaller than some tiles (partial
+    tiles) and whose operands are read in interleaved label orders."""
+    import os
+    log(f"tile configuration {config}, precision {precision}")
+    tol = TOL if precision == 0 else 1e-3
+    # A: 6 free labels interleaved with 10 shared; B: 4 free labels after the shared ones
+    order_a = [10, 0, 11, 1, 12, 2, 13, 3, 14, 4, 15, 5, 6, 7, 8, 9]
+    net = random_pair_network(16, 14, 10, 4242 + config, order_a, None)
+    ref = ocontract.contract_path(net.tensors, net.labels, [(0, 1)], net.out_label).reshape(-1)
+    for blocks in ("1", "1000000"):     # split-K off, then as many splits as allowed
+        os.environ["TNC_GEMM_CONFIG"] = str(config)
+        os.environ["TNC_SPLITK_BLOCKS"] = blocks
+        try:
+            c = _contraction(net, [(0, 1)], open_qubits=list(range(net.n_qubits)),
+                             closed_bits=[0], precision=precision)
+        finally:
+            os.environ.pop("TNC_GEMM_CONFIG", None)
+            os.environ.pop("TNC_SPLITK_BLOCKS", None)
+        g = [l for l in c.launches() if l.kind == 1]
+        assert len(g) == 1 and g[0].config == config
+        assert (g[0].k_splits > 1) == (blocks != "1")
+        c.contract()
+        err = metrics.rel_error(c.amps.cpu().numpy()[0], ref)
+        log(f"  split-K {g[0].k_splits}: rel err {err:.3e}")
+        assert err <= tol
+        c.close()
