@@ -588,8 +588,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
         for (int j = 0; j < UN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[cur][i], bf[j], acc[i][j], 0, 0, 0);
       __builtin_amdgcn_sched_barrier(0);
+      // the next K tile goes to the other LDS stage halfway through this one, so that
+      // the writes overlap the matrix instructions instead of preceding the barrier
+      if (kk == BK / 2 && more) store(stage ^ 1);
     }
-    if (more) store(stage ^ 1);
     __syncthreads();
     stage ^= 1;
   }
