@@ -226,7 +226,7 @@ def main():
     ap.add_argument("--samples", type=int, default=1000)
     ap.add_argument("--batch", type=int, default=64, help="slices per launch (hipGraph per batch)")
     ap.add_argument("--autotune", type=int, default=1, help="time tile choices per GEMM first (1/0)")
-    ap.add_argument("--precision", default="c64", choices=["c64", "bf16x3"])
+    ap.add_argument("--precision", default="c64", choices=["c64", "bf16x3", "fp16x3"])
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="run one plain device copy of BYTES before the timed region (a known "
                          "reference for HBM traffic counters)")
@@ -262,7 +262,7 @@ def main():
     c = Contraction(w.net, w.plan.path, sliced_labels=w.plan.sliced_labels,
                     slice_ids=w.slice_ids, open_qubits=w.open_qubits, closed_bits=w.closed_bits,
                     max_batch_slices=args.batch,
-                    precision={"c64": 0, "bf16x3": 2}[args.precision])
+                    precision={"c64": 0, "fp16x3": 1, "bf16x3": 2}[args.precision])
     flops_slice, bytes_slice, n_steps = c.stats()
     flops_inv = sum(l.flops for l in c.launches() if l.invariant)
     flops_step = flops_slice * len(w.slice_ids) + flops_inv
@@ -314,8 +314,10 @@ def main():
                     "achieved": algo, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
                     "frac": algo / (PEAK_FP32_MFMA / 1e12)}
         else:
-            # three BF16 products (hi*hi, hi*lo, lo*hi) per algorithmic flop
-            roof = {"kernel": "k_gemm_bf16x3 (v_mfma_f32_32x32x16_bf16, 3 products)",
+            # three products (hi*hi, hi*lo, lo*hi) per algorithmic flop; the FP16 and BF16
+            # matrix instructions share one peak
+            mfma = "f16" if args.precision == "fp16x3" else "bf16"
+            roof = {"kernel": f"k_gemm_bf16x3 (v_mfma_f32_32x32x16_{mfma}, 3 products)",
                     "bound": "mfma", "achieved": 3 * algo, "peak": PEAK_BF16_MFMA / 1e12,
                     "unit": "TFLOP/s", "frac": 3 * algo / (PEAK_BF16_MFMA / 1e12),
                     "algorithmic_tflops": algo}

@@ -50,7 +50,12 @@ const char* tnc_last_error(void);
  *               lo = bf16(x - hi) and accumulate hi*hi + hi*lo + lo*hi in FP32 on the BF16
  *               matrix cores (about 16 significant bits per operand; BF16 keeps FP32's
  *               exponent range, so no scaling is needed).
- *   the FP16 and 3M forms are declared for ABI stability and return TNC_E_UNSUPPORTED. */
+ *   TNC_FP16X3  the same three products in FP16, with a power-of-two scale per operand and
+ *               slice: a preceding pass finds each operand's largest component m in
+ *               [2^e, 2^(e+1)), values are scaled by 2^(13 - e) before the split (so
+ *               |hi| < 2^14, far below FP16's limit) and the product is scaled back when
+ *               it is stored (about 22 significant bits per operand).
+ *   the 3M forms are declared for ABI stability and return TNC_E_UNSUPPORTED. */
 typedef enum {
   TNC_C64 = 0,
   TNC_FP16X3 = 1,
@@ -152,7 +157,8 @@ tnc_status tnc_plan_destroy(tnc_plan plan);
 tnc_status tnc_net_destroy(tnc_net net);
 
 /* Per-step description for reporting: kind 1 = GEMM, 2 = small-operand stream, 3 = slice
- * leaves, 4 = slice sum, 5 = split-K reduction, 6 = BF16 hi/lo split of a GEMM operand
+ * leaves, 4 = slice sum, 5 = split-K reduction, 6 = operand preparation for a split-precision
+ * GEMM (BF16 hi/lo copy, or the per-slice largest component that sets the FP16 scale)
  * (0 is reserved: operands are never permuted, the GEMM reads them in their stored
  * layouts); rows, m, n, k in
  * elements; flops and bytes algorithmic; invariant = 1 if run once per call.  For GEMMs:

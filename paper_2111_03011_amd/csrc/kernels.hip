@@ -449,6 +449,29 @@ struct GemmTile {
     return out(a) + (m0 + row) * N * 2;
   }
 
+  // largest |value| among the accumulator entries store_acc writes (same layout and bounds)
+  template <int UM, int UN>
+  __device__ __forceinline__ float acc_absmax(const GemmArgs& a, const f32x16 (&acc)[UM][UN],
+                                              int wm_base, int wn_base) const {
+    const int lane = threadIdx.x & 63, half = lane >> 5, j32 = lane & 31;
+    float m = 0.f;
+#pragma unroll
+    for (int i = 0; i < UM; ++i)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = wm_base + i * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+        bool row_ok;
+        if (a.stk) row_ok = (((m0 & 127) + row) >> a.nm) < stk_count;
+        else row_ok = m0 + row < M;
+#pragma unroll
+        for (int j = 0; j < UN; ++j) {
+          const int64_t np = n0 + wn_base + j * 16 + (j32 >> 1);
+          if (row_ok && np < N) m = fmaxf(m, fabsf(acc[i][j][v]));
+        }
+      }
+    return m;
+  }
+
   // 32x32 accumulator layout: column = lane % 32, row = 8 (v/4) + 4 (lane/32) + v%4; the
   // real column j is complex column j/2, real part for even j
   template <int UM, int UN>
@@ -705,6 +728,42 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
 
 typedef float f32x2v __attribute__((ext_vector_type(2)));
 
+// Fold per-lane maxima m >= 0 into amax[slice * step] with atomic maxima on the float bits
+// (non-negative floats order like their bits).  Every lane of the wave calls this; a lane
+// without an element passes slice = -1.  When the lanes with an element share one slice the
+// wave reduces first and issues one atomic.
+__device__ __forceinline__ void amax_commit(float m, int64_t slice, uint32_t* amax, int step) {
+  int64_t s0 = slice;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const int64_t o = __shfl_xor(s0, off);
+    s0 = s0 > o ? s0 : o;
+  }
+  if (s0 < 0) return;
+  if (__all(slice == s0 || slice < 0)) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0 && m > 0.f) atomicMax(amax + s0 * step, __float_as_uint(m));
+  } else if (slice >= 0 && m > 0.f) {
+    atomicMax(amax + slice * step, __float_as_uint(m));
+  }
+}
+
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// (re, im) * scale -> packed FP16 words hi = fp16(x), lo = fp16(x - hi) (x = scaled value,
+// round to nearest even); the power-of-two scale keeps |x| below 2^14
+__device__ __forceinline__ void split_pair_f16(float2 v, float scale, uint32_t& hi, uint32_t& lo) {
+  f32x2v x;
+  x[0] = v.x * scale;
+  x[1] = v.y * scale;
+  const f16x2 h = __builtin_convertvector(x, f16x2);
+  hi = __builtin_bit_cast(uint32_t, h);
+  const f32x2v r = x - __builtin_convertvector(h, f32x2v);
+  lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, f16x2));
+}
+
 // (re, im) -> packed bf16 words hi = (bf16(re), bf16(im)), lo = (bf16(re - hi.re),
 // bf16(im - hi.im)), low half first; conversions round to nearest even
 __device__ __forceinline__ void split_pair(float2 x, uint32_t& hi, uint32_t& lo) {
@@ -719,8 +778,11 @@ __device__ __forceinline__ void split_pair(float2 x, uint32_t& hi, uint32_t& lo)
   lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf16x2));
 }
 
-template <int WAVES_M, int WAVES_N, int UM, int UN, bool A_MFAST, bool B_NFAST, bool PRESPLIT>
+// MODE 0: BF16 split while staging; 1: BF16 operands pre-split; 2: FP16 split of operands
+// scaled by a power of two per slice (from their largest component), undone on the output
+template <int WAVES_M, int WAVES_N, int UM, int UN, bool A_MFAST, bool B_NFAST, int MODE>
 __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
+  constexpr bool PRESPLIT = (MODE == 1), F16 = (MODE == 2);
   static_assert(WAVES_M * WAVES_N == 4, "four waves per workgroup");
   constexpr int BK = 16;                       // complex k per LDS stage (two MFMA steps)
   constexpr int BM = WAVES_M * UM * 32;
@@ -737,6 +799,23 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int wm = wave % WAVES_M, wn = wave / WAVES_M;
+  // FP16: operand scales 2^(13 - e) for a largest component in [2^e, 2^(e+1)); e is read
+  // from the exponent field and clamped to [-110, 127] (zero, subnormal or infinite maxima),
+  // so every scale and inverse scale is a normal FP32 power of two
+  float sc_a = 1.f, sc_b = 1.f, us_a = 1.f, us_b = 1.f;
+  if (F16) {
+    auto expo = [](uint32_t bits) {
+      const int e = int((bits >> 23) & 0xffu) - 127;
+      return e < -110 ? -110 : (e > 127 ? 127 : e);
+    };
+    auto pow2 = [](int k) { return __uint_as_float(uint32_t(127 + k) << 23); };
+    const int ea = expo(a.amax_a[t.sl * a.amax_a_step]);
+    const int eb = expo(a.amax_b[t.sl * a.amax_b_step]);
+    sc_a = pow2(13 - ea);
+    sc_b = pow2(13 - eb);
+    us_a = pow2(ea - 13);
+    us_b = pow2(eb - 13);
+  }
 
   f32x16 acc[UM][UN];
 #pragma unroll
@@ -785,6 +864,11 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
         wh[A_LD + i] = w.x;
         wl[A_LD + i] = w.y;
       }
+    } else if (F16) {
+#pragma unroll
+      for (int i = 0; i < A_LD; ++i) split_pair_f16(ra[i], sc_a, wh[i], wl[i]);
+#pragma unroll
+      for (int i = 0; i < B_LD; ++i) split_pair_f16(rb[i], sc_b, wh[A_LD + i], wl[A_LD + i]);
     } else {
 #pragma unroll
       for (int i = 0; i < A_LD + B_LD; ++i) split_pair(i < A_LD ? ra[i] : rb[i - A_LD], wh[i], wl[i]);
@@ -873,19 +957,82 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
       for (int i = 0; i < UM; ++i)
 #pragma unroll
         for (int j = 0; j < UN; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xal[i], xbh[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xah[i], xbl[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xah[i], xbh[j], acc[i][j], 0, 0, 0);
+          if constexpr (F16) {
+            const f16x8 ah8 = __builtin_bit_cast(f16x8, xah[i]), al8 = __builtin_bit_cast(f16x8, xal[i]);
+            const f16x8 bh8 = __builtin_bit_cast(f16x8, xbh[j]), bl8 = __builtin_bit_cast(f16x8, xbl[j]);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al8, bh8, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah8, bl8, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah8, bh8, acc[i][j], 0, 0, 0);
+          } else {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xal[i], xbh[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xah[i], xbl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xah[i], xbh[j], acc[i][j], 0, 0, 0);
+          }
         }
     }
     if (more) store(stage ^ 1);
     __syncthreads();
     stage ^= 1;
   }
+  if (F16) {
+#pragma unroll
+    for (int i = 0; i < UM; ++i)
+#pragma unroll
+      for (int jj = 0; jj < UN; ++jj)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[i][jj][v] = acc[i][jj][v] * us_a * us_b;
+    if (a.amax_c && a.k_splits == 1)
+      amax_commit(t.template acc_absmax<UM, UN>(a, acc, wm * UM * 32, wn * UN * 16), t.sl,
+                  a.amax_c, a.amax_c_step);
+  }
   t.template store_acc<UM, UN>(a, acc, wm * UM * 32, wn * UN * 16);
 }
 
+// largest |re|, |im| of each slice copy: grid-stride maximum, wave reduction, one unsigned
+// atomic maximum per wave on the float's bits (non-negative floats order like their bits)
+__global__ __launch_bounds__(kThreads) void k_absmax(const float2* X, int64_t elems, int64_t sstride,
+                                                    uint32_t* out, int out_step) {
+  const int64_t s = blockIdx.y;
+  const float2* x = X + s * sstride;
+  float m = 0.f;
+  for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < elems;
+       i += int64_t(gridDim.x) * kThreads) {
+    const float2 v = x[i];
+    m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) atomicMax(out + s * out_step, __float_as_uint(m));
+}
+
+__global__ __launch_bounds__(kThreads) void k_zero_u32(uint32_t* p, int64_t n, int step) {
+  const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+  if (i < n) p[i * step] = 0u;
+}
+
 __global__ __launch_bounds__(kThreads) void k_reduce(ReduceArgs a) {
+  if (a.amax) {
+    // wave-uniform trip count, so that every lane takes part in amax_commit
+    for (int64_t b = int64_t(blockIdx.x) * kThreads + (threadIdx.x & ~63); b < a.elems;
+         b += int64_t(gridDim.x) * kThreads) {
+      const int64_t i = b + (threadIdx.x & 63);
+      float m = 0.f;
+      int64_t slice = -1;
+      if (i < a.elems) {
+        float2 s = a.partial[i];
+        for (int k = 1; k < a.splits; ++k) {
+          const float2 p = a.partial[int64_t(k) * a.elems + i];
+          s.x += p.x;
+          s.y += p.y;
+        }
+        a.C[i] = s;
+        m = fmaxf(fabsf(s.x), fabsf(s.y));
+        slice = i / a.slice_elems;
+      }
+      amax_commit(m, slice, a.amax, a.amax_step);
+    }
+    return;
+  }
   for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < a.elems;
        i += int64_t(gridDim.x) * kThreads) {
     float2 s = a.partial[i];
@@ -926,14 +1073,21 @@ __global__ __launch_bounds__(kThreads) void k_reduce_wide(ReduceArgs a) {
   }
   red[w][lane] = make_float2(c0.x + c1.x, c0.y + c1.y);
   __syncthreads();
-  if (w == 0 && i < a.elems) {
-    float2 t = red[0][lane];
+  if (w == 0) {
+    float m = 0.f;
+    int64_t slice = -1;
+    if (i < a.elems) {
+      float2 t = red[0][lane];
 #pragma unroll
-    for (int q = 1; q < 4; ++q) {
-      t.x += red[q][lane].x;
-      t.y += red[q][lane].y;
+      for (int q = 1; q < 4; ++q) {
+        t.x += red[q][lane].x;
+        t.y += red[q][lane].y;
+      }
+      a.C[i] = t;
+      m = fmaxf(fabsf(t.x), fabsf(t.y));
+      slice = i / a.slice_elems;
     }
-    a.C[i] = t;
+    if (a.amax) amax_commit(m, slice, a.amax, a.amax_step);
   }
 }
 
@@ -1196,19 +1350,19 @@ hipError_t launch_gemm_cfg(const GemmArgs& a, hipStream_t s) {
       case 2: hipLaunchKernelGGL((k_gemm<WM, WN, UM, UN, BK, false, true>), grid, dim3(kThreads), 0, s, a); break;
       default: hipLaunchKernelGGL((k_gemm<WM, WN, UM, UN, BK, true, true>), grid, dim3(kThreads), 0, s, a); break;
     }
-  } else if (a.precision == 1) {
-    switch (sel) {
-      case 0: hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, false, false, false>), grid, dim3(kThreads), 0, s, a); break;
-      case 1: hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, true, false, false>), grid, dim3(kThreads), 0, s, a); break;
-      case 2: hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, false, true, false>), grid, dim3(kThreads), 0, s, a); break;
-      default: hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, true, true, false>), grid, dim3(kThreads), 0, s, a); break;
-    }
   } else {
-    switch (sel) {
-      case 0: hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, false, false, true>), grid, dim3(kThreads), 0, s, a); break;
-      case 1: hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, true, false, true>), grid, dim3(kThreads), 0, s, a); break;
-      case 2: hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, false, true, true>), grid, dim3(kThreads), 0, s, a); break;
-      default: hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, true, true, true>), grid, dim3(kThreads), 0, s, a); break;
+    const int mode = a.precision == 1 ? 0 : (a.precision == 2 ? 1 : 2);
+    switch (sel * 3 + mode) {
+#define TNC_SPLIT_CASE(S, MD, AF, BF)                                                          \
+  case S * 3 + MD:                                                                            \
+    hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, AF, BF, MD>), grid, dim3(kThreads), 0, s, a); \
+    break;
+      TNC_SPLIT_CASE(0, 0, false, false) TNC_SPLIT_CASE(0, 1, false, false) TNC_SPLIT_CASE(0, 2, false, false)
+      TNC_SPLIT_CASE(1, 0, true, false) TNC_SPLIT_CASE(1, 1, true, false) TNC_SPLIT_CASE(1, 2, true, false)
+      TNC_SPLIT_CASE(2, 0, false, true) TNC_SPLIT_CASE(2, 1, false, true) TNC_SPLIT_CASE(2, 2, false, true)
+      TNC_SPLIT_CASE(3, 0, true, true) TNC_SPLIT_CASE(3, 1, true, true) TNC_SPLIT_CASE(3, 2, true, true)
+#undef TNC_SPLIT_CASE
+      default: return hipErrorInvalidValue;
     }
   }
   return hipGetLastError();
@@ -1268,6 +1422,22 @@ hipError_t launch_gemm(const GemmArgs& a, hipStream_t s) {
 hipError_t launch_split_bf16(const float2* in, void* out, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_split_bf16, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, in,
                      static_cast<uint2*>(out), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(uint32_t* p, int64_t n, int step, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, p, n, step);
+  return hipGetLastError();
+}
+
+hipError_t launch_absmax(const float2* X, int64_t elems, int64_t slice_stride, int64_t copies,
+                         uint32_t* out, int out_step, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(copies, kThreads)), dim3(kThreads), 0, s, out, copies,
+                     out_step);
+  int64_t bx = (elems + 4 * kThreads - 1) / (4 * kThreads);
+  bx = bx < 1 ? 1 : (bx > 1024 ? 1024 : bx);
+  hipLaunchKernelGGL(k_absmax, dim3(unsigned(bx), unsigned(copies)), dim3(kThreads), 0, s, X, elems,
+                     slice_stride, out, out_step);
   return hipGetLastError();
 }
 

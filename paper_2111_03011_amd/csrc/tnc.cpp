@@ -98,6 +98,10 @@ namespace {
 
 enum Kind { K_PERMUTE = 0, K_GEMM = 1, K_STREAM = 2, K_LEAVES = 3, K_SUM = 4, K_REDUCE = 5, K_SPLIT = 6 };
 constexpr int kKinds = 7;
+// operand preparation launches (kind K_SPLIT): the BF16 hi/lo copy, the largest-component
+// pass of an operand whose producer does not record it, and the clearing of a slot that
+// the producing launch folds its output's largest component into
+enum SplitOp { SPLIT_BF16 = 0, SPLIT_AMAX = 1, SPLIT_ZERO = 2 };
 
 struct Buf {
   uint64_t bytes = 0;         // all copies
@@ -116,6 +120,9 @@ struct Launch {
   int b_in0 = -1, b_in1 = -1, b_out = -1, b_tmp = -1;
   int64_t g0 = -1, g1 = -1;   // byte offsets of row gathers in the constants block
   int64_t stk_off = -1, perm_off = -1;   // row-stacking tables (GEMM), same block
+  int b_amax_a = -1, b_amax_b = -1;      // FP16 split: largest component of A and B per slice
+  int b_amax_c = -1;                     // FP16 split: the output's, folded in by this launch
+  int split_op = 0;                      // K_SPLIT: SPLIT_BF16, SPLIT_AMAX or SPLIT_ZERO
   int64_t n_elems = 0;        // elements per slice copy (split launches)
   bool enabled = true;        // a split-K reduction is switched off when tuning drops split-K
   int max_splits = 1;         // split-K factor the partial buffer was sized for
@@ -131,6 +138,7 @@ struct TState {
   std::vector<uint64_t> keys;
   bool dep = false;
   int buf = -1;
+  int amax = -1;                // FP16 split: buffer with the largest |re|, |im| per slice
   bool alive = true;
   int64_t rows() const { return int64_t(keys.size()); }
   int64_t elems() const { return rows() << dense.size(); }
@@ -484,6 +492,39 @@ struct Compiler {
     return L.b_out;
   }
 
+  // largest |re|, |im| of an operand for the FP16 split (one value per slice copy); an
+  // operand shared by every slice is measured once per call
+  int emit_amax(const TState& T) {
+    Launch L;
+    L.kind = K_SPLIT;
+    L.split_op = SPLIT_AMAX;
+    L.inv = !T.dep;
+    L.b_in0 = T.buf;
+    L.b_out = new_buf(8, false, T.dep);
+    L.n_elems = T.elems();
+    L.bufs = {L.b_in0, L.b_out};
+    L.info = tnc_step_info{K_SPLIT, L.inv, T.rows(), int64_t(1) << T.dense.size(), 0, 0, 0.0,
+                           8.0 * double(T.elems())};
+    account(L);
+    list(L.inv).push_back(L);
+    return L.b_out;
+  }
+
+  // slot for the largest component of a tensor about to be produced, cleared before the
+  // producing launch folds into it
+  int emit_amax_slot(bool inv, bool per_slice) {
+    Launch L;
+    L.kind = K_SPLIT;
+    L.split_op = SPLIT_ZERO;
+    L.inv = inv;
+    L.b_out = new_buf(8, false, per_slice);
+    L.bufs = {L.b_out};
+    L.info = tnc_step_info{K_SPLIT, inv, 1, 1, 0, 0, 0.0, 8.0};
+    account(L);
+    list(inv).push_back(L);
+    return L.b_out;
+  }
+
   TState step(TState& A, TState& B) {
     TState C;
     C.dep = A.dep || B.dep;
@@ -652,6 +693,16 @@ struct Compiler {
       L.perm_off = add_const(perm.data(), perm.size() * sizeof(int32_t));
     }
     g.precision = 0;
+    if (plan.precision != TNC_C64 && g.config == 5) g.config = 1;   // no 8-wide split tile
+    int amax_a = -1, amax_b = -1;
+    if (plan.precision == TNC_FP16X3) {
+      g.precision = 3;
+      if (P.amax < 0) P.amax = emit_amax(P);
+      if (Q.amax < 0) Q.amax = emit_amax(Q);
+      amax_a = P.amax;
+      amax_b = Q.amax;
+      C.amax = emit_amax_slot(inv, C.dep);
+    }
     if (plan.precision == TNC_BF16X3) {
       // fat products split each operand once (every output tile re-reads its panels);
       // thin ones split while staging tiles into LDS
@@ -671,6 +722,14 @@ struct Compiler {
     L.b_in1 = qbuf;
     L.b_out = C.buf;
     L.bufs = {pbuf, qbuf, C.buf};
+    if (amax_a >= 0) {
+      L.b_amax_a = amax_a;
+      L.b_amax_b = amax_b;
+      L.b_amax_c = C.amax;
+      L.bufs.push_back(amax_a);
+      L.bufs.push_back(amax_b);
+      L.bufs.push_back(C.amax);
+    }
     int part = -1;
     L.max_splits = g.k_splits;
     if (g.k_splits > 1) {
@@ -692,6 +751,11 @@ struct Compiler {
       R.b_in0 = part;
       R.b_out = C.buf;
       R.bufs = {part, C.buf};
+      R.rd.slice_elems = rows * M * N;
+      if (C.amax >= 0) {
+        R.b_amax_c = C.amax;
+        R.bufs.push_back(C.amax);
+      }
       R.info = tnc_step_info{K_REDUCE, inv, rows, M, N, 0, 0.0,
                              8.0 * double(g.k_splits + 1) * double(rows * M * N)};
       account(R);
@@ -878,6 +942,14 @@ struct Exec {
         a.gb = gat(L.g1);
         a.stk = gat(L.stk_off);
         a.perm = gat(L.perm_off);
+        if (L.b_amax_a >= 0) {
+          a.amax_a = reinterpret_cast<const uint32_t*>(ptr(L.b_amax_a));
+          a.amax_b = reinterpret_cast<const uint32_t*>(ptr(L.b_amax_b));
+          a.amax_a_step = p.bufs[L.b_amax_a].per_slice ? 2 : 0;
+          a.amax_b_step = p.bufs[L.b_amax_b].per_slice ? 2 : 0;
+          a.amax_c = reinterpret_cast<uint32_t*>(ptr(L.b_amax_c));
+          a.amax_c_step = p.bufs[L.b_amax_c].per_slice ? 2 : 0;
+        }
         a.partial = L.b_tmp >= 0 ? ptr(L.b_tmp) : nullptr;
         a.nb = nb;
         err = launch_gemm(a, st);
@@ -885,7 +957,15 @@ struct Exec {
       }
       case K_SPLIT: {
         const int64_t copies = plan_copies(L, nb);
-        err = launch_split_bf16(ptr(L.b_in0), ptr(L.b_out), L.n_elems * copies, st);
+        if (L.split_op == SPLIT_ZERO) {
+          err = launch_zero_u32(reinterpret_cast<uint32_t*>(ptr(L.b_out)), copies, 2, st);
+        } else if (L.split_op == SPLIT_AMAX) {
+          const int64_t sstride = p.bufs[L.b_in0].per_slice ? int64_t(p.bufs[L.b_in0].elems) : 0;
+          err = launch_absmax(ptr(L.b_in0), L.n_elems, sstride, copies,
+                              reinterpret_cast<uint32_t*>(ptr(L.b_out)), 2, st);
+        } else {
+          err = launch_split_bf16(ptr(L.b_in0), ptr(L.b_out), L.n_elems * copies, st);
+        }
         break;
       }
       case K_REDUCE: {
@@ -893,6 +973,10 @@ struct Exec {
         a.partial = ptr(L.b_in0);
         a.C = ptr(L.b_out);
         a.elems = L.rd.elems * nb;
+        if (L.b_amax_c >= 0) {
+          a.amax = reinterpret_cast<uint32_t*>(ptr(L.b_amax_c));
+          a.amax_step = p.bufs[L.b_amax_c].per_slice ? 2 : 0;
+        }
         err = launch_reduce(a, st);
         break;
       }
@@ -1122,8 +1206,8 @@ tnc_plan_s* make_plan(tnc_net_s& net, tnc_precision precision, int32_t max_batch
 tnc_plan_s* compile_plan(tnc_net_s& net, tnc_precision precision, int32_t max_batch) {
   if (!net.has_path && net.labels.size() > 1) fail(TNC_E_INVALID, "no path set");
   if (!net.has_targets) fail(TNC_E_INVALID, "no targets set");
-  if (precision != TNC_C64 && precision != TNC_BF16X3)
-    fail(TNC_E_UNSUPPORTED, "implemented precisions: TNC_C64, TNC_BF16X3");
+  if (precision != TNC_C64 && precision != TNC_BF16X3 && precision != TNC_FP16X3)
+    fail(TNC_E_UNSUPPORTED, "implemented precisions: TNC_C64, TNC_BF16X3, TNC_FP16X3");
   if (max_batch < 1) fail(TNC_E_INVALID, "max_batch_slices must be >= 1");
   auto* p = new tnc_plan_s();
   try {

@@ -60,7 +60,8 @@ struct GemmArgs {
   float2* partial;
   int config;                 // tile configuration id
   int precision;              // 0: complex64 on FP32 MFMA; 1: BF16 hi+lo split in the kernel;
-                              // 2: BF16 hi+lo, operands already split by k_split_bf16
+                              // 2: BF16 hi+lo, operands already split by k_split_bf16;
+                              // 3: FP16 hi+lo of operands scaled by a power of two per slice
   // Row stacking (stk != nullptr): output rows that share one B row are stacked along M.
   // M is then a multiple of 128 and each output row contributes 2^nm consecutive m; the
   // 128-row block b holds output rows perm[stk[3b]], ..., perm[stk[3b] + stk[3b+1] - 1]
@@ -69,6 +70,16 @@ struct GemmArgs {
   const int32_t* stk;
   const int32_t* perm;
   int group_m;                // tiles are numbered in groups of group_m tile rows (L2 reuse)
+  // precision 3 (FP16 hi+lo): largest |re|, |im| of A and B per slice, as float bits, at
+  // amax_a[slice * amax_a_step] (step 0: operand shared by every slice)
+  const uint32_t* amax_a;
+  const uint32_t* amax_b;
+  int amax_a_step, amax_b_step;
+  // precision 3: when set and the launch writes C itself (k_splits == 1), the largest
+  // |re|, |im| of C per slice is folded into amax_c[slice * amax_c_step] with an atomic
+  // maximum (the slot is zero before the launch)
+  uint32_t* amax_c;
+  int amax_c_step;
 };
 
 struct ReduceArgs {           // C[i] = sum_s partial[s][i]  (i over every slice of the launch)
@@ -76,6 +87,11 @@ struct ReduceArgs {           // C[i] = sum_s partial[s][i]  (i over every slice
   float2* C;
   int64_t elems;
   int splits;
+  // optional: largest |re|, |im| of C per slice (slice = i / slice_elems) folded into
+  // amax[slice * amax_step] with an atomic maximum (the slots are zero before the launch)
+  uint32_t* amax;
+  int amax_step;
+  int64_t slice_elems;
 };
 
 // Sliced leaves: for each table entry, out[o] = src[insert(o, slice bits)].
@@ -119,6 +135,11 @@ struct SliceSumArgs {
 // Launchers (return hipError_t of the launch).
 hipError_t launch_stream(const StreamArgs& a, hipStream_t s);
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t s);
+// out[s * out_step] = bits of max |re|, |im| over the `elems` elements of copy s of X
+// (copies at X + s * slice_stride), for s < copies
+hipError_t launch_zero_u32(uint32_t* p, int64_t n, int step, hipStream_t s);
+hipError_t launch_absmax(const float2* X, int64_t elems, int64_t slice_stride, int64_t copies,
+                         uint32_t* out, int out_step, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 // out (8 bytes per element): bf16 (re_hi, im_hi) then (re_lo, im_lo) of each complex64 input
 hipError_t launch_split_bf16(const float2* in, void* out, int64_t n, hipStream_t s);

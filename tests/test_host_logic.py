@@ -181,7 +181,7 @@ def test_network_validation():
     assert _err(tnc.tnc_net_set_targets, h, [0, 0], [0]) == tnc.TNC_E_INVALID   # repeated open
     assert _err(tnc.tnc_net_set_targets, h, [], [1, 1]) == tnc.TNC_E_INVALID    # same groups
     tnc.tnc_net_set_targets(h, [0], [0, 1])
-    assert _err(tnc.tnc_plan_create, h, tnc.TNC_FP16X3) == tnc.TNC_E_UNSUPPORTED
+    assert _err(tnc.tnc_plan_create, h, tnc.TNC_BF16X3_3M) == tnc.TNC_E_UNSUPPORTED
     p = tnc.tnc_plan_create(h, tnc.TNC_C64, 4)
     ws = tnc.tnc_plan_workspace_bytes(p)
     assert ws > 0
