@@ -28,9 +28,10 @@ PEAK_BF16_MFMA = 2.5e15
 PEAK_HBM = 8.0e12
 
 
-def cpu_baseline(w, flops_per_slice: float, budget_s: float = 20.0) -> dict:
+def cpu_baseline(w, flops_per_slice: float, budget_s: float = 20.0):
     """The oracle, as it stands, on a bounded sample of the same workload: as many slices
-    as fit in about `budget_s` seconds (at least one), each contracted alone."""
+    as fit in about `budget_s` seconds (at least one), each contracted alone.  Returns the
+    baseline record and the oracle amplitudes of the sampled slices by slice index."""
     import numpy as np
 
     from oracle import contract as ocontract
@@ -40,10 +41,12 @@ def cpu_baseline(w, flops_per_slice: float, budget_s: float = 20.0) -> dict:
     except Exception:  # pragma: no cover - informational only
         threads = os.cpu_count()
     done, t0 = 0, time.perf_counter()
+    refs = {}
     while True:
-        sid = [int(w.slice_ids[done % len(w.slice_ids)])]
-        ocontract.sparse_amplitudes(w.circuit, w.open_qubits, w.closed_bits,
-                                    sliced_bonds=w.sliced_bonds, slice_ids=sid)
+        idx = done % len(w.slice_ids)
+        sid = [int(w.slice_ids[idx])]
+        refs[idx] = ocontract.sparse_amplitudes(w.circuit, w.open_qubits, w.closed_bits,
+                                                sliced_bonds=w.sliced_bonds, slice_ids=sid)
         done += 1
         if time.perf_counter() - t0 > budget_s or done >= len(w.slice_ids):
             break
@@ -54,7 +57,67 @@ def cpu_baseline(w, flops_per_slice: float, budget_s: float = 20.0) -> dict:
             "sample": f"{done} slice(s) of the same workload, numpy complex128 tensordot "
                       f"along the oracle's own greedy path, {per_slice:.2f} s per slice; value = "
                       f"the library's algorithmic flops per slice / oracle seconds per slice",
-            "amplitudes_per_s": w.n_amplitudes / (per_slice * len(w.slice_ids))}
+            "amplitudes_per_s": w.n_amplitudes / (per_slice * len(w.slice_ids))}, refs
+
+
+def rel_error(got, ref) -> float:
+    import numpy as np
+    got, ref = np.asarray(got).reshape(-1), np.asarray(ref).reshape(-1)
+    return float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def infidelity(got, ref) -> float:
+    import numpy as np
+    got, ref = np.asarray(got).reshape(-1), np.asarray(ref).reshape(-1)
+    den = np.vdot(got, got).real * np.vdot(ref, ref).real
+    return float(1.0 - abs(np.vdot(ref, got)) ** 2 / den) if den > 0 else 0.0
+
+
+def slice_errors(c, refs) -> float:
+    """Largest normwise relative error of single-slice contractions against the oracle."""
+    worst = 0.0
+    for idx, ref in refs.items():
+        c.contract_range(idx, 1)
+        worst = max(worst, rel_error(c.amps.cpu().numpy(), ref))
+    return worst
+
+
+def split_compare(w, args, plain_amps, refs, stream) -> dict:
+    """The split-precision forms on the same workload: throughput over the same timed
+    step (contract + sample) and their amplitude error against the complex64 sum and,
+    slice by slice, against the oracle."""
+    import torch
+    from paper_2111_03011_amd.contractor import Contraction
+    res = {}
+    for name, prec in (("bf16x3", 2), ("fp16x3", 1)):
+        c = Contraction(w.net, w.plan.path, sliced_labels=w.plan.sliced_labels,
+                        slice_ids=w.slice_ids, open_qubits=w.open_qubits,
+                        closed_bits=w.closed_bits, max_batch_slices=args.batch, precision=prec)
+        if args.autotune:
+            c.autotune(reps=2)
+        n_samp = args.samples if len(w.closed_bits) == 1 else len(w.closed_bits)
+        c.contract(norm=True)
+        c.sample(2004, n_samp)
+        steps = max(1, min(args.steps, 3))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            c.contract(norm=True)
+            c.sample(2004, n_samp)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        amps = c.amps.cpu().numpy().copy()
+        r = {"amplitudes_per_s": w.n_amplitudes / (ms * 1e-3), "ms_per_step": ms,
+             "tflops": c.stats()[0] * len(w.slice_ids) / (ms * 1e-3) / 1e12,
+             "rel_err_vs_c64_sum": rel_error(amps, plain_amps),
+             "infidelity_vs_c64_sum": infidelity(amps, plain_amps)}
+        if refs:
+            r["rel_err_vs_oracle_slices"] = slice_errors(c, refs)
+        c.close()
+        res[name] = r
+        print(f"[bench] {name}: {r['amplitudes_per_s']:.0f} amplitudes/s, rel err vs c64 "
+              f"{r['rel_err_vs_c64_sum']:.2e}", file=sys.stderr, flush=True)
+    return res
 
 
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "k_gemm_sliced_5x6_m14_traffic.json")
@@ -227,6 +290,9 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="slices per launch (hipGraph per batch)")
     ap.add_argument("--autotune", type=int, default=1, help="time tile choices per GEMM first (1/0)")
     ap.add_argument("--precision", default="c64", choices=["c64", "bf16x3", "fp16x3"])
+    ap.add_argument("--split-compare", type=int, default=1,
+                    help="sliced, c64: also time the split-precision forms and report their "
+                         "amplitude errors (1/0)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="run one plain device copy of BYTES before the timed region (a known "
                          "reference for HBM traffic counters)")
@@ -367,9 +433,17 @@ def main():
         "time_share": {k: v / tot for k, v in share.items()},
         "roofline": roof,
     }
+    refs = {}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, flops_slice)
-    c.close()
+        out["cpu_baseline"], refs = cpu_baseline(w, flops_slice)
+        out["rel_err_vs_oracle_slices"] = slice_errors(c, refs)
+    if args.split_compare and args.precision == "c64" and args.workload == "sliced":
+        c.contract()
+        plain = c.amps.cpu().numpy().copy()
+        c.close()
+        out["split_precision"] = split_compare(w, args, plain, refs, stream)
+    else:
+        c.close()
     print(json.dumps(out), flush=True)
 
 
