@@ -82,6 +82,51 @@ def slice_errors(c, refs) -> float:
     return worst
 
 
+def head_reuse(args, plain_amps, plain_amps_per_s) -> dict:
+    """The same 1024-slice workload planned for head reuse (Method, Appendix B.2): slices the
+    size bound needs are global, the other sliced bonds are local labels on the low slice-id
+    bits, and every step above global labels only runs once per batch of 64 slices.  Timed
+    over the same step (contract + sample) in complex64 and BF16x3; the amplitudes are
+    compared with the plain plan's complex64 sum (the same full sum over all slices)."""
+    import torch
+    from paper_2111_03011_amd.contractor import Contraction
+    from paper_2111_03011_amd.workload import config_workload
+    w = config_workload("sliced", mode="reuse")
+    res = {"sliced_labels_local_then_global": [int(x) for x in w.plan.sliced_labels],
+           "peak_log2": w.plan.cost.peak_log2}
+    for name, prec in (("c64", 0), ("bf16x3", 2)):
+        c = Contraction(w.net, w.plan.path, sliced_labels=w.plan.sliced_labels,
+                        slice_ids=w.slice_ids, open_qubits=w.open_qubits,
+                        closed_bits=w.closed_bits, max_batch_slices=args.batch, precision=prec)
+        if args.autotune:
+            c.autotune(reps=2)
+        n_samp = args.samples if len(w.closed_bits) == 1 else len(w.closed_bits)
+        c.contract(norm=True)
+        c.sample(2004, n_samp)
+        steps = max(1, min(args.steps, 3))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            c.contract(norm=True)
+            c.sample(2004, n_samp)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        amps = c.amps.cpu().numpy().copy()
+        work = c.work()
+        shared = sum(l.flops for l in c.launches() if l.invariant == 2)
+        c.close()
+        aps = w.n_amplitudes / (ms * 1e-3)
+        res[name] = {"amplitudes_per_s": aps, "ms_per_step": ms,
+                     "tflops": work / (ms * 1e-3) / 1e12, "flops_per_step": work,
+                     "shared_flops_per_batch": shared,
+                     "speedup_vs_plain_c64": aps / plain_amps_per_s,
+                     "rel_err_vs_plain_c64_sum": rel_error(amps, plain_amps),
+                     "infidelity_vs_plain_c64_sum": infidelity(amps, plain_amps)}
+        print(f"[bench] head reuse {name}: {aps:.0f} amplitudes/s "
+              f"({aps / plain_amps_per_s:.2f}x plain c64)", file=sys.stderr, flush=True)
+    return res
+
+
 def split_compare(w, args, plain_amps, refs, stream) -> dict:
     """The split-precision forms on the same workload: throughput over the same timed
     step (contract + sample) and their amplitude error against the complex64 sum and,
@@ -290,6 +335,8 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="slices per launch (hipGraph per batch)")
     ap.add_argument("--autotune", type=int, default=1, help="time tile choices per GEMM first (1/0)")
     ap.add_argument("--precision", default="c64", choices=["c64", "bf16x3", "fp16x3"])
+    ap.add_argument("--head-reuse", type=int, default=1,
+                    help="sliced, c64: also time the head-reuse plan of the same workload (1/0)")
     ap.add_argument("--split-compare", type=int, default=1,
                     help="sliced, c64: also time the split-precision forms and report their "
                          "amplitude errors (1/0)")
@@ -330,8 +377,7 @@ def main():
                     max_batch_slices=args.batch,
                     precision={"c64": 0, "fp16x3": 1, "bf16x3": 2}[args.precision])
     flops_slice, bytes_slice, n_steps = c.stats()
-    flops_inv = sum(l.flops for l in c.launches() if l.invariant)
-    flops_step = flops_slice * len(w.slice_ids) + flops_inv
+    flops_step = c.work()     # algorithmic flops one pass executes (shared steps once per batch)
     stream = torch.cuda.current_stream()
 
     def one_step():
@@ -437,11 +483,15 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"], refs = cpu_baseline(w, flops_slice)
         out["rel_err_vs_oracle_slices"] = slice_errors(c, refs)
-    if args.split_compare and args.precision == "c64" and args.workload == "sliced":
+    extra = args.precision == "c64" and args.workload == "sliced"
+    if extra and (args.split_compare or args.head_reuse):
         c.contract()
         plain = c.amps.cpu().numpy().copy()
         c.close()
-        out["split_precision"] = split_compare(w, args, plain, refs, stream)
+        if args.split_compare:
+            out["split_precision"] = split_compare(w, args, plain, refs, stream)
+        if args.head_reuse:
+            out["head_reuse"] = head_reuse(args, plain, out["amplitudes_per_s"])
     else:
         c.close()
     print(json.dumps(out), flush=True)

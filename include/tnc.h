@@ -125,11 +125,23 @@ tnc_status tnc_plan_batch_slices(tnc_plan plan, int32_t* batch);
 /* Bytes of device workspace tnc_contract needs. */
 tnc_status tnc_plan_workspace_bytes(tnc_plan plan, uint64_t* bytes);
 
-/* Algorithmic cost of one slice: flops = 8 x complex multiply-adds (Table I caption),
- * bytes = operands read + results written by every step.  Steps that touch no sliced
- * tensor are run once per tnc_contract call and are not included. */
+/* Algorithmic cost of one slice contracted alone: flops = 8 x complex multiply-adds
+ * (Table I caption), bytes = operands read + results written by every step.  Steps that
+ * touch no sliced tensor are run once per tnc_contract call and are not included. */
 tnc_status tnc_plan_stats(tnc_plan plan, double* flops_per_slice, double* bytes_per_slice,
                           int32_t* n_steps);
+
+/* Head reuse inside a batch (the paper's reuse of the head across the slices of one
+ * subtask, Method and Appendix B.2): the slices of a launch sequence are consecutive in
+ * the slice list, and a step whose sliced labels all keep one value across them (their
+ * slice-id bits agree) is computed once per batch instead of once per slice.  Batches are
+ * runs of at most max_batch_slices consecutive ids, cut short where such a bit would
+ * change; with ids in counting order and the labels that vary fastest on the low bits,
+ * every step above only high-bit labels is shared.  (TNC_NO_SHARE=1 in the environment at
+ * plan creation turns this off.)
+ * tnc_plan_work: algorithmic flops that contracting slices [first, first + count) executes,
+ * shared steps counted once per batch and slice-invariant steps once. */
+tnc_status tnc_plan_work(tnc_plan plan, int64_t first, int64_t count, double* flops);
 
 /* Contract all slice ids and write the FP64 sum to d_amps (device, [L][2^n_open]
  * complex128, caller-owned).  h_norm (host, nullable) receives sum |amp|^2 (paper,
@@ -161,7 +173,8 @@ tnc_status tnc_net_destroy(tnc_net net);
  * GEMM (BF16 hi/lo copy, or the per-slice largest component that sets the FP16 scale)
  * (0 is reserved: operands are never permuted, the GEMM reads them in their stored
  * layouts); rows, m, n, k in
- * elements; flops and bytes algorithmic; invariant = 1 if run once per call.  For GEMMs:
+ * elements; flops and bytes algorithmic (one slice); invariant = 1 if run once per call,
+ * 2 if run once per batch (head reuse, see tnc_plan_work), 0 if run per slice.  For GEMMs:
  * tile configuration (0 = 128x64, 1 = 128x16, 2 = 64x32, 3 = 128x128 complex), split-K
  * factor, and row mode (0 = one launch row per output row, 1 = rows folded into M because
  * the N-side operand is shared, 2 = output rows sharing an N-side row stacked along M). */

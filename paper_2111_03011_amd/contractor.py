@@ -77,6 +77,12 @@ class Contraction:
     def stats(self):
         return tnc.tnc_plan_stats(self._plan)
 
+    def work(self, first: int = 0, count: int | None = None) -> float:
+        """Algorithmic flops contracting slices [first, first + count) executes (steps
+        shared by a batch counted once per batch)."""
+        n = len(self.slice_ids) - first if count is None else count
+        return tnc.tnc_plan_work(self._plan, first, n)
+
     def launches(self):
         return [tnc.tnc_plan_launch_info(self._plan, i)
                 for i in range(tnc.tnc_plan_n_launches(self._plan))]

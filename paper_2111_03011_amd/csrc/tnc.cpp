@@ -122,6 +122,7 @@ struct Launch {
   int64_t stk_off = -1, perm_off = -1;   // row-stacking tables (GEMM), same block
   int b_amax_a = -1, b_amax_b = -1;      // FP16 split: largest component of A and B per slice
   int b_amax_c = -1;                     // FP16 split: the output's, folded in by this launch
+  bool shared = false;        // slice-dependent, but the same for every slice of a batch
   int split_op = 0;                      // K_SPLIT: SPLIT_BF16, SPLIT_AMAX or SPLIT_ZERO
   int64_t n_elems = 0;        // elements per slice copy (split launches)
   bool enabled = true;        // a split-K reduction is switched off when tuning drops split-K
@@ -139,6 +140,9 @@ struct TState {
   bool dep = false;
   int buf = -1;
   int amax = -1;                // FP16 split: buffer with the largest |re|, |im| per slice
+  uint64_t dbits[2] = {0, 0};   // slice-id bits (sliced labels) the tensor depends on
+  bool shared = false;          // dep, and none of its bits varies inside a batch
+  bool per_slice() const { return dep && !shared; }
   bool alive = true;
   int64_t rows() const { return int64_t(keys.size()); }
   int64_t elems() const { return rows() << dense.size(); }
@@ -184,6 +188,11 @@ struct tnc_plan_s {
   int norm_parts = 1024;
   int b_norm = -1, b_cum = -1, b_samples = -1, b_counter = -1;
   int batch = 1;
+  // slice-id bits that vary inside some batch of the slice list (batches of `batch`
+  // consecutive ids, or shorter runs, see Exec::run_length); a dependent step whose bits
+  // avoid them is computed once per batch
+  uint64_t vary[2] = {~uint64_t(0), ~uint64_t(0)};
+  double flops_shared = 0;   // algorithmic flops of the once-per-batch steps (one copy)
   // captured program of one full batch (per workspace and amplitude buffer)
   hipGraphExec_t graph = nullptr;
   hipStream_t capture_stream = nullptr;
@@ -355,6 +364,7 @@ struct Compiler {
           e.bit[j] = int8_t(sl[j].second);
         }
         s.dep = true;
+        for (size_t j = 0; j < sl.size(); ++j) s.dbits[sl[j].second >> 6] |= uint64_t(1) << (sl[j].second & 63);
         s.buf = new_buf(uint64_t(e.elems_out) * 8, false, true);
         e.dst_off = s.buf;    // resolved after packing
         plan.sl_table.push_back(e);
@@ -386,6 +396,7 @@ struct Compiler {
     } else {
       plan.flops_slice += L.info.flops;
       plan.bytes_slice += L.info.bytes;
+      if (L.shared) plan.flops_shared += L.info.flops;
     }
   }
 
@@ -482,7 +493,7 @@ struct Compiler {
     L.kind = K_SPLIT;
     L.inv = !T.dep;
     L.b_in0 = T.buf;
-    L.b_out = new_buf(uint64_t(T.elems()) * 8, false, T.dep);
+    L.b_out = new_buf(uint64_t(T.elems()) * 8, false, T.per_slice());
     L.n_elems = T.elems();
     L.bufs = {L.b_in0, L.b_out};
     L.info = tnc_step_info{K_SPLIT, L.inv, T.rows(), int64_t(1) << T.dense.size(), 0, 0, 0.0,
@@ -500,7 +511,7 @@ struct Compiler {
     L.split_op = SPLIT_AMAX;
     L.inv = !T.dep;
     L.b_in0 = T.buf;
-    L.b_out = new_buf(8, false, T.dep);
+    L.b_out = new_buf(8, false, T.per_slice());
     L.n_elems = T.elems();
     L.bufs = {L.b_in0, L.b_out};
     L.info = tnc_step_info{K_SPLIT, L.inv, T.rows(), int64_t(1) << T.dense.size(), 0, 0, 0.0,
@@ -517,6 +528,7 @@ struct Compiler {
     L.kind = K_SPLIT;
     L.split_op = SPLIT_ZERO;
     L.inv = inv;
+    L.shared = !inv && !per_slice;
     L.b_out = new_buf(8, false, per_slice);
     L.bufs = {L.b_out};
     L.info = tnc_step_info{K_SPLIT, inv, 1, 1, 0, 0, 0.0, 8.0};
@@ -529,6 +541,10 @@ struct Compiler {
     TState C;
     C.dep = A.dep || B.dep;
     const bool inv = !C.dep;
+    C.dbits[0] = A.dbits[0] | B.dbits[0];
+    C.dbits[1] = A.dbits[1] | B.dbits[1];
+    C.shared = C.dep && !(C.dbits[0] & plan.vary[0]) && !(C.dbits[1] & plan.vary[1]);
+    const bool ps = C.per_slice();
     C.q = A.q | B.q;
     C.keys = row_keys(net.closed, C.q);
     std::set<int32_t> sa(A.dense.begin(), A.dense.end()), sb(B.dense.begin(), B.dense.end());
@@ -555,6 +571,7 @@ struct Compiler {
       Launch L;
       L.kind = K_STREAM;
       L.inv = inv;
+      L.shared = C.shared;
       StreamArgs& a = L.st;
       a.rows = C.rows();
       a.x_rows = X.rows();
@@ -576,7 +593,7 @@ struct Compiler {
       for (int j = 0; j < a.nn; ++j) a.s_npos[j] = int8_t(pos_of(S.dense, NS[NS.size() - 1 - j]));
       C.dense = MX;
       C.dense.insert(C.dense.end(), NS.begin(), NS.end());
-      C.buf = new_buf(uint64_t(C.elems()) * 8, false, C.dep);
+      C.buf = new_buf(uint64_t(C.elems()) * 8, false, ps);
       a.x_slice_stride = sstride(X.buf);
       a.s_slice_stride = sstride(S.buf);
       a.c_slice_stride = sstride(C.buf);
@@ -630,6 +647,7 @@ struct Compiler {
     Launch L;
     L.kind = K_GEMM;
     L.inv = inv;
+    L.shared = C.shared;
     GemmArgs& g = L.gm;
     const int nm = int(MP.size()), nn = int(NQ.size());
     int64_t M = int64_t(1) << nm, N = int64_t(1) << nn, Kd = int64_t(1) << nk;
@@ -701,7 +719,7 @@ struct Compiler {
       if (Q.amax < 0) Q.amax = emit_amax(Q);
       amax_a = P.amax;
       amax_b = Q.amax;
-      C.amax = emit_amax_slot(inv, C.dep);
+      C.amax = emit_amax_slot(inv, ps);
     }
     if (plan.precision == TNC_BF16X3) {
       // fat products split each operand once (every output tile re-reads its panels);
@@ -714,7 +732,7 @@ struct Compiler {
       }
     }
     C.dense = cat(MP, NQ);
-    C.buf = new_buf(uint64_t(C.elems()) * 8, false, C.dep);
+    C.buf = new_buf(uint64_t(C.elems()) * 8, false, ps);
     g.a_slice_stride = sstride(pbuf);
     g.b_slice_stride = sstride(qbuf);
     g.c_slice_stride = sstride(C.buf);
@@ -734,7 +752,7 @@ struct Compiler {
     L.max_splits = g.k_splits;
     if (g.k_splits > 1) {
       part = new_buf(uint64_t(g.k_splits) * uint64_t(rows) * uint64_t(M) * uint64_t(N) * 8, false,
-                     C.dep);
+                     ps);
       L.b_tmp = part;
       L.bufs.push_back(part);
     }
@@ -746,6 +764,7 @@ struct Compiler {
       Launch R;
       R.kind = K_REDUCE;
       R.inv = inv;
+      R.shared = C.shared;
       R.rd.elems = rows * M * N;
       R.rd.splits = g.k_splits;
       R.b_in0 = part;
@@ -883,6 +902,29 @@ void pack(tnc_plan_s& plan) {
 
 // ------------------------------------------------------------------------------------
 // execution
+
+// Slices [pos, pos + n) of the list form batches of at most p.batch consecutive ids whose
+// bits outside p.vary agree, so that the once-per-batch steps are right for every slice.
+int64_t run_length(const tnc_plan_s& p, int64_t pos, int64_t n) {
+  const int64_t nb = std::min<int64_t>(p.batch, n);
+  const uint64_t* id = p.slice_ids.data() + 2 * pos;
+  for (int64_t i = 1; i < nb; ++i)
+    if (((id[2 * i] ^ id[0]) & ~p.vary[0]) || ((id[2 * i + 1] ^ id[1]) & ~p.vary[1])) return i;
+  return nb;
+}
+
+// Algorithmic flops that contracting slices [first, first + count) executes.
+double plan_work(const tnc_plan_s& p, int64_t first, int64_t count) {
+  if (count <= 0) return 0.0;
+  double f = p.flops_inv;
+  for (int64_t pos = 0; pos < count;) {
+    const int64_t nb = run_length(p, first + pos, count - pos);
+    f += (p.flops_slice - p.flops_shared) * double(nb) + p.flops_shared;
+    pos += nb;
+  }
+  return f;
+}
+
 struct Exec {
   tnc_plan_s& p;
   uint8_t* ws;
@@ -912,8 +954,9 @@ struct Exec {
   }
 
   // one launch of the program for nb slices (nb = 1 for the invariant phase)
-  void launch(const Launch& L, int64_t nb, double* amps, hipStream_t st, bool timed) {
+  void launch(const Launch& L, int64_t nb_batch, double* amps, hipStream_t st, bool timed) {
     if (!L.enabled) return;
+    const int64_t nb = L.shared ? 1 : nb_batch;   // a shared step runs for one copy
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
       e0 = ev();
@@ -1066,25 +1109,28 @@ struct Exec {
       for (auto& L : p.inv) launch(L, 1, amps, s, p.timing);
     check(launch_set_i64(counter(), first, s));
     const int64_t S = p.batch;
-    const int64_t full = count / S, rest = count % S;
     static const bool no_graph = std::getenv("TNC_NO_GRAPH") != nullptr;
     // Full batches replay the captured graph.  With timing on, a bounded sample of batches
     // (about 4096 launches per call) is launched eagerly with an event pair per launch.
-    const int64_t nbat = full + (rest ? 1 : 0);
+    const int64_t nbat = (count + S - 1) / S;
     int64_t stride = nbat + 1;
     if (p.timing) {
       const int64_t per = std::max<int64_t>(1, int64_t(p.dep.size()));
       const int64_t n_timed = std::max<int64_t>(1, 4096 / per);
       stride = std::max<int64_t>(1, nbat / n_timed);
     }
-    if (full > 0 && !no_graph) capture(amps);
-    for (int64_t b = 0; b < nbat; ++b) {
-      const int64_t nb = b < full ? S : rest;
+    bool captured = false;
+    for (int64_t pos = 0, b = 0; pos < count; ++b) {
+      const int64_t nb = run_length(p, first + pos, count - pos);
       const bool timed = p.timing && (b % stride == 0);
-      if (timed || no_graph || nb < S)
+      if (timed || no_graph || nb < S) {
         batch(nb, amps, s, timed);
-      else
+      } else {
+        if (!captured) capture(amps);
+        captured = true;
         HIPCHK(hipGraphLaunch(p.graph, s));
+      }
+      pos += nb;
     }
   }
 };
@@ -1221,6 +1267,17 @@ tnc_plan_s* compile_plan(tnc_net_s& net, tnc_precision precision, int32_t max_ba
     p->slice_ids = net.slice_ids;
     p->batch = std::max<int32_t>(
         1, int32_t(std::min<int64_t>(max_batch, int64_t(net.slice_ids.size() / 2))));
+    // bits that vary inside the batches of a full pass; TNC_NO_SHARE turns sharing off
+    if (std::getenv("TNC_NO_SHARE") == nullptr) {
+      p->vary[0] = p->vary[1] = 0;
+      const int64_t n = p->n_slices();
+      const uint64_t* id = p->slice_ids.data();
+      for (int64_t b0 = 0; b0 < n; b0 += p->batch)
+        for (int64_t i = b0 + 1; i < std::min<int64_t>(n, b0 + p->batch); ++i) {
+          p->vary[0] |= id[2 * i] ^ id[2 * b0];
+          p->vary[1] |= id[2 * i + 1] ^ id[2 * b0 + 1];
+        }
+    }
     Compiler c(net, *p);
     c.run();
     pack(*p);
@@ -1283,10 +1340,10 @@ int autotune(tnc_plan_s& p, uint8_t* ws, hipStream_t st, int reps) {
   HIPCHK(hipEventCreate(&t1));
   for (int phase = 0; phase < 2; ++phase) {
     std::vector<Launch>& lst = phase == 0 ? p.inv : p.dep;
-    const int64_t nb = phase == 0 ? 1 : p.batch;
     for (size_t i = 0; i < lst.size(); ++i) {
       Launch& L = lst[i];
       if (L.kind != K_GEMM) continue;
+      const int64_t nb = (phase == 0 || L.shared) ? 1 : p.batch;
       Launch* R = (i + 1 < lst.size() && lst[i + 1].kind == K_REDUCE && lst[i + 1].b_in0 == L.b_tmp)
                       ? &lst[i + 1] : nullptr;
       GemmArgs probe = L.gm;
@@ -1750,6 +1807,15 @@ tnc_status tnc_plan_stats(tnc_plan p, double* flops, double* bytes, int32_t* n_s
   });
 }
 
+tnc_status tnc_plan_work(tnc_plan p, int64_t first, int64_t count, double* flops) {
+  return guard([&] {
+    if (!p || !flops) fail(TNC_E_INVALID, "null argument");
+    if (first < 0 || count < 0 || first + count > p->n_slices())
+      fail(TNC_E_INVALID, "slice range out of bounds");
+    *flops = plan_work(*p, first, count);
+  });
+}
+
 static void check_ws(tnc_plan p, void* ws, uint64_t bytes) {
   if (!ws) fail(TNC_E_INVALID, "null workspace");
   if (bytes < p->ws_bytes)
@@ -1823,7 +1889,7 @@ tnc_status tnc_plan_launch_info(tnc_plan p, int32_t i, tnc_step_info* info) {
     const Launch& L = i < P ? p->inv[i] : p->dep[i - P];
     *info = L.info;
     info->kind = L.kind;
-    info->invariant = L.inv ? 1 : 0;
+    info->invariant = L.inv ? 1 : (L.shared ? 2 : 0);
     info->config = info->k_splits = info->row_mode = info->reserved = 0;
     if (L.kind == K_GEMM) {
       info->config = L.gm.config;

@@ -20,6 +20,13 @@ when asked, an exact count) is met; the path is then searched again on the slice
 network.  Steps that touch no sliced leaf are the same in every slice; the objective
 counts them once.
 
+Head reuse (Method; Appendix B.2: the head is contracted once per subtask and reused by
+all of its slices).  With `reuse_batch` = B > 1 the bonds the size bound needs are sliced
+first (global labels); the remaining ones are local labels, chosen one at a time to
+minimise the per-slice work when every step that depends on global labels only is
+computed once per batch of B slices.  Local labels take the low bits of the slice id, so
+consecutive slice ids differ only in them and the library shares those steps.
+
 Path format (Appendix E): pairs (i, j); the result is stored at position i.
 """
 
@@ -106,9 +113,13 @@ class PathCost:
     flops_invariant: float = 0.0     # 8 T_c of steps shared by all slices
     peak_log2: float = 0.0
     steps: list = field(default_factory=list)   # (i, j, rows, log2 dense A, B, C, macs, dep)
+    flops_shared: float = 0.0        # part of flops_per_slice computed once per batch
+    batch: int = 1                   # slices per batch the shared part is counted for
 
     def total(self, n_slices: int) -> float:
-        return self.flops_invariant + n_slices * self.flops_per_slice
+        n_batches = -(-n_slices // max(1, self.batch))
+        return (self.flops_invariant + n_slices * (self.flops_per_slice - self.flops_shared)
+                + n_batches * self.flops_shared)
 
 
 def greedy_path(prob: Problem, temperature: float = 0.0, seed: int = 0):
@@ -292,6 +303,79 @@ def choose_slices(prob: Problem, path, max_log2: float, exact: int | None = None
     return chosen, cur_peak
 
 
+def _subtree_labels(prob: Problem, path):
+    """Per step: OR of the dense bitsets of the leaves under it (with sliced labels, when
+    `prob` is the unsliced problem)."""
+    acc = list(prob.dense)
+    out = []
+    for i, j in path:
+        acc[i] |= acc[j]
+        out.append(acc[i])
+    return out
+
+
+def choose_local_slices(prob: Problem, path, global_bits: int, n_local: int, batch: int,
+                        max_log2: float, forbidden: int = 0):
+    """Add n_local bonds (local labels) to the globally sliced set, one at a time, each the
+    one that minimises the per-slice work when steps above global labels only are shared by
+    a batch of min(batch, 2^(local labels so far)) slices, under the size bound.
+    Returns the list of chosen bond bits in order, or None when the bound cannot be met."""
+    ops = _step_operands(prob, path)
+    sub = _subtree_labels(prob, path)
+    counts = {}
+    for d in prob.dense:
+        x = d
+        while x:
+            b = x & -x
+            counts[b] = counts.get(b, 0) + 1
+            x ^= b
+    cands = [b for b, c in counts.items() if c == 2 and not (b & forbidden) and not (b & global_bits)]
+    if len(cands) < n_local:
+        return None
+    inter = list(zip(prob.dense, prob.qmask)) + [(out, q) for _, q, out in ops]
+    O = np.array([[bool(d & b) for b in cands] for d, _ in inter], dtype=np.float64)
+    U = np.array([[bool(u & b) for b in cands] for u, _, _ in ops], dtype=np.float64)
+    Dl = np.array([[bool(t & b) for b in cands] for t in sub], dtype=bool)
+    g_of = lambda x: _popcount(x & global_bits)
+    ls = np.array([math.log2(prob.rows(q)) + _popcount(d) - g_of(d) for d, q in inter])
+    lc = np.array([math.log2(prob.rows(q)) + _popcount(u) - g_of(u) for u, q, _ in ops])
+    dep_g = np.array([bool(t & global_bits) for t in sub])
+    local_dep = np.zeros(len(ops), dtype=bool)
+    chosen = []
+    taken = np.zeros(len(cands), dtype=bool)
+    for k in range(n_local):
+        share = float(min(batch, 2 ** (k + 1)))
+        best = None
+        macs_all = np.exp2(lc[:, None] - U)          # step cost with each candidate sliced
+        peak_all = (ls[:, None] - O).max(axis=0)
+        ldep = local_dep[:, None] | Dl                # steps that depend on a local label
+        shared = (~ldep) & dep_g[:, None]
+        eff = (macs_all * ldep).sum(axis=0) + (macs_all * shared).sum(axis=0) / share
+        eff = np.where(taken | (peak_all > max_log2 + 1e-9), np.inf, eff)
+        c = int(np.argmin(eff))
+        if not np.isfinite(eff[c]):
+            return None
+        chosen.append(cands[c])
+        taken[c] = True
+        ls = ls - O[:, c]
+        lc = lc - U[:, c]
+        local_dep |= Dl[:, c]
+    return chosen
+
+
+def reuse_cost(prob_sliced: Problem, path, leaf_local, leaf_global, batch: int) -> PathCost:
+    """PathCost with the steps that depend on global sliced leaves only marked as shared by
+    a batch (leaf_local / leaf_global: leaves holding a local / global sliced label)."""
+    cost = path_cost(prob_sliced, path, leaf_local | leaf_global)
+    loc = [k in leaf_local for k in range(len(prob_sliced.dense))]
+    for (i, j), st in zip(path, cost.steps):
+        loc[i] = loc[i] or loc[j]
+        if st[7] and not loc[i]:
+            cost.flops_shared += 8.0 * st[6]
+    cost.batch = batch
+    return cost
+
+
 @dataclass
 class Plan:
     path: list
@@ -306,12 +390,14 @@ class Plan:
 
 def find_plan(net, open_qubits, closed_bits, max_log2: float = 26.0,
               n_sliced: int | None = None, trials: int = 16, seed: int = 0,
-              temperature: float = 0.05, rounds: int = 2) -> Plan:
+              temperature: float = 0.05, rounds: int = 2, reuse_batch: int = 1) -> Plan:
     """Random-greedy search of (path, sliced bonds) under the size bound.
 
     n_sliced=None slices as few bonds as the bound needs; an int asks for exactly that
-    many.  Returns the plan with the lowest total flop count over the slices (steps
-    shared by all slices counted once)."""
+    many.  reuse_batch > 1 (with n_sliced) also tries head reuse: bound-driven global
+    slices plus local ones (low slice-id bits), steps above global labels counted once per
+    batch of reuse_batch slices.  Returns the plan with the lowest total flop count over
+    the slices (steps shared by all slices counted once)."""
     n = net.n_qubits
     base = make_problem(net.labels, net.out_label, n, open_qubits, closed_bits)
     bond_bits = 0
@@ -325,6 +411,7 @@ def find_plan(net, open_qubits, closed_bits, max_log2: float = 26.0,
     for t in range(trials):
         temp = 0.0 if t == 0 else temperature
         path = greedy_path(base, temperature=temp, seed=seed + 7919 * t)
+        path0 = path
         sl = 0
         for _ in range(rounds):
             need_exact = n_sliced
@@ -349,9 +436,39 @@ def find_plan(net, open_qubits, closed_bits, max_log2: float = 26.0,
         cand = Plan(path=path, sliced_labels=sliced, cost=cost, n_slices=1 << len(sliced))
         if best is None or cand.total_flops < best.total_flops:
             best = cand
+        if reuse_batch > 1 and n_sliced:
+            for p in (path0, path):
+                rc = _reuse_candidate(net, base, p, open_qubits, closed_bits, max_log2, n_sliced,
+                                      reuse_batch, forbidden)
+                if rc is not None and rc.total_flops < best.total_flops:
+                    best = rc
     if best is None:
         raise RuntimeError("no plan met the size bound; raise trials or the bound")
     return best
+
+
+def _reuse_candidate(net, base, path, open_qubits, closed_bits, max_log2, n_sliced, batch,
+                     forbidden):
+    g_bits, _ = choose_slices(base, path, max_log2, forbidden=forbidden)
+    n_glob = _popcount(g_bits)
+    # the low log2(batch) id bits vary inside every batch: they must all be local labels
+    if n_sliced - n_glob < max(1, int(batch).bit_length() - 1):
+        return None
+    local = choose_local_slices(base, path, g_bits, n_sliced - n_glob, batch, max_log2, forbidden)
+    if local is None:
+        return None
+    ids = lambda bits: [base.label_ids[i] for i in range(len(base.label_ids)) if (bits >> i) & 1]
+    loc_labels = [ids(b)[0] for b in local]
+    glob_labels = ids(g_bits)
+    sliced = loc_labels + glob_labels                 # local labels on the low id bits
+    n = net.n_qubits
+    sp = make_problem(net.labels, net.out_label, n, open_qubits, closed_bits, sliced=sliced)
+    leaf_loc = {k for k, l in enumerate(net.labels) if any(x in loc_labels for x in l)}
+    leaf_glob = {k for k, l in enumerate(net.labels) if any(x in glob_labels for x in l)}
+    cost = reuse_cost(sp, path, leaf_loc, leaf_glob, batch)
+    if cost.peak_log2 > max_log2 + 1e-9:
+        return None
+    return Plan(path=path, sliced_labels=sliced, cost=cost, n_slices=1 << len(sliced))
 
 
 def validate_path(n_tensors: int, pairs):

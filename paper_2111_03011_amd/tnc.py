@@ -32,7 +32,7 @@ KIND_NAMES = ("permute", "gemm", "stream", "slice_leaves", "slice_sum", "splitk_
 
 EXPORTS = (
     "tnc_last_error", "tnc_net_create", "tnc_net_set_path", "tnc_net_set_slices",
-    "tnc_net_set_slices_wide", "tnc_net_set_targets", "tnc_plan_create", "tnc_plan_workspace_bytes", "tnc_plan_stats",
+    "tnc_net_set_slices_wide", "tnc_net_set_targets", "tnc_plan_create", "tnc_plan_workspace_bytes", "tnc_plan_stats", "tnc_plan_work",
     "tnc_contract", "tnc_contract_range", "tnc_sample", "tnc_plan_destroy", "tnc_net_destroy",
     "tnc_plan_autotune", "tnc_plan_batch_slices", "tnc_plan_n_launches", "tnc_plan_launch_info", "tnc_plan_set_timing", "tnc_plan_timing",
     "tnc_plan_launch_timing",
@@ -89,6 +89,7 @@ def lib() -> ctypes.CDLL:
             "tnc_plan_create": (_I32, [_P, ctypes.c_int, _I32, ctypes.POINTER(_P)]),
             "tnc_plan_workspace_bytes": (_I32, [_P, ctypes.POINTER(_U64)]),
             "tnc_plan_stats": (_I32, [_P, ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_I32)]),
+            "tnc_plan_work": (_I32, [_P, _I64, _I64, ctypes.POINTER(_D)]),
             "tnc_contract": (_I32, [_P, _P, _U64, _P, _P, ctypes.POINTER(_D)]),
             "tnc_contract_range": (_I32, [_P, _P, _U64, _P, _P, _I64, _I64, _I32]),
             "tnc_sample": (_I32, [_P, _P, _U64, _P, _U64, _I64, _P, _P]),
@@ -187,6 +188,12 @@ def tnc_plan_stats(plan: int):
     f, b, n = _D(), _D(), _I32()
     _check(lib().tnc_plan_stats(plan, ctypes.byref(f), ctypes.byref(b), ctypes.byref(n)))
     return f.value, b.value, n.value
+
+
+def tnc_plan_work(plan: int, first: int, count: int) -> float:
+    f = _D()
+    _check(lib().tnc_plan_work(plan, first, count, ctypes.byref(f)))
+    return f.value
 
 
 def tnc_contract(plan: int, ws: int, ws_bytes: int, stream: int, amps: int, want_norm: bool = False):

@@ -35,10 +35,10 @@ class Workload:
 
 def make_workload(circuit: dict, open_qubits, closed_bits, max_log2: float = 26,
                   n_sliced=None, slice_ids=None, trials: int = 4, seed: int = 0,
-                  name: str = "custom") -> Workload:
+                  name: str = "custom", reuse_batch: int = 1) -> Workload:
     net = circuit_network(circuit)
     plan = find_plan(net, open_qubits, closed_bits, max_log2=max_log2, n_sliced=n_sliced,
-                     trials=trials, seed=seed)
+                     trials=trials, seed=seed, reuse_batch=reuse_batch)
     if slice_ids is None:
         if len(plan.sliced_labels) > 24:
             raise ValueError("too many slices to enumerate; pass a slice subset")
@@ -54,8 +54,11 @@ _CACHE = {}
 
 def config_workload(name: str, mode: str = "default", trials: int | None = None) -> Workload:
     """name: small | sliced | large.  For small, mode 'amplitudes' (64 bitstrings, no open
-    qubit) or 'samples' (all 12 qubits open, one group).  trials defaults to the
-    configuration's plan_trials.  Plans are deterministic and memoised per process."""
+    qubit) or 'samples' (all 12 qubits open, one group).  For sliced, mode 'reuse' plans
+    for head reuse (bound-driven global slices, cheap local ones on the low slice-id bits,
+    steps above global labels once per batch of the configuration's reuse_batch).  trials
+    defaults to the configuration's plan_trials.  Plans are deterministic and memoised per
+    process."""
     key = (name, mode, trials)
     if key not in _CACHE:
         _CACHE[key] = _config_workload(name, mode, trials)
@@ -81,7 +84,8 @@ def _config_workload(name: str, mode: str, trials: int | None) -> Workload:
     closed = synth.group_targets(n, open_q, g["L"], g["seed"])
     net = circuit_network(circuit)
     plan = find_plan(net, open_q, closed, max_log2=cfg["max_log2_size"],
-                     n_sliced=cfg.get("sliced_labels"), trials=trials, seed=cfg["path_seed"])
+                     n_sliced=cfg.get("sliced_labels"), trials=trials, seed=cfg["path_seed"],
+                     reuse_batch=cfg.get("reuse_batch", 1) if mode == "reuse" else 1)
     k = len(plan.sliced_labels)
     if "slice_subset" in cfg:
         sub = cfg["slice_subset"]

@@ -36,6 +36,7 @@ CONFIGS = {
         "samples": {"count": 1000, "seed": 2004},
         "path_seed": 2005,
         "plan_trials": 64,
+        "reuse_batch": 64,        # head-reuse plan: steps above global labels once per 64
     },
     "precision": {
         "name": "precision",

@@ -326,3 +326,58 @@ def test_plan_log_lists_gemms():
     n = int(out.stdout.strip().splitlines()[-1])
     lines = [l for l in out.stderr.splitlines() if l.startswith("[tnc plan]")]
     assert len(lines) == n and n > 0
+
+
+def _reuse_case(reuse_batch):
+    circ = synth.make_circuit(4, 4, 14, 44)
+    open_q = list(range(10, 16))
+    closed = synth.group_targets(16, open_q, 4, 45)
+    return make_workload(circ, open_q, closed, max_log2=14, n_sliced=6, trials=8, seed=44,
+                         reuse_batch=reuse_batch)
+
+
+def _plan_of(w, batch):
+    h = tnc.tnc_net_create(0, w.net.n_qubits, w.net.ranks(), w.net.flat_labels(),
+                           w.net.flat_data(), w.net.out_label)
+    tnc.tnc_net_set_path(h, w.plan.path)
+    tnc.tnc_net_set_slices(h, w.plan.sliced_labels, w.slice_ids)
+    tnc.tnc_net_set_targets(h, w.open_qubits, w.closed_bits)
+    p = tnc.tnc_plan_create(h, tnc.TNC_C64, batch)
+    tnc.tnc_net_destroy(h)
+    return p
+
+
+def test_head_reuse_plan_and_its_work():
+    """Head reuse (Method, Appendix B.2): with reuse_batch = 8 the planner slices the bonds
+    the size bound needs, adds local bonds on the low slice-id bits, and counts the steps
+    above global labels once per batch; the library shares exactly those steps, so its
+    executed work equals the planner's total, also over a range that does not start on a
+    batch boundary (runs are cut where a shared bit changes)."""
+    import os
+    w = _reuse_case(8)
+    plain = _reuse_case(1)
+    assert w.plan.cost.flops_shared > 0
+    assert w.plan.total_flops < plain.plan.total_flops
+    n = len(w.slice_ids)
+    inv, ps, sh = w.plan.cost.flops_invariant, w.plan.cost.flops_per_slice, w.plan.cost.flops_shared
+    p = _plan_of(w, 8)
+    infos = [tnc.tnc_plan_launch_info(p, i) for i in range(tnc.tnc_plan_n_launches(p))]
+    assert any(i.invariant == 2 for i in infos)
+    assert math.isclose(tnc.tnc_plan_stats(p)[0], ps, rel_tol=1e-12)
+    assert math.isclose(tnc.tnc_plan_work(p, 0, n), w.plan.total_flops, rel_tol=1e-12)
+    # ids 3..15: runs 3..7 and 8..15
+    want = inv + ((ps - sh) * 5 + sh) + ((ps - sh) * 8 + sh)
+    assert math.isclose(tnc.tnc_plan_work(p, 3, 13), want, rel_tol=1e-12)
+    assert tnc.tnc_plan_work(p, 0, 0) == 0.0
+    with pytest.raises(tnc.TncError):
+        tnc.tnc_plan_work(p, 60, 8)
+    tnc.tnc_plan_destroy(p)
+    os.environ["TNC_NO_SHARE"] = "1"
+    try:
+        q = _plan_of(w, 8)
+    finally:
+        os.environ.pop("TNC_NO_SHARE")
+    infos = [tnc.tnc_plan_launch_info(q, i) for i in range(tnc.tnc_plan_n_launches(q))]
+    assert not any(i.invariant == 2 for i in infos)
+    assert math.isclose(tnc.tnc_plan_work(q, 0, n), inv + n * ps, rel_tol=1e-12)
+    tnc.tnc_plan_destroy(q)
