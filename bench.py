@@ -127,6 +127,23 @@ def head_reuse(args, plain_amps, plain_amps_per_s) -> dict:
     return res
 
 
+def time_samplers(c, w, args) -> dict:
+    """Wall time of the three in-group samplers on the contracted amplitudes (inverse CDF,
+    the paper's Metropolis chains, frugal rejection sampling), one call each after a warm-up
+    call; the bitstrings are copied to the host inside the timed call."""
+    n = args.samples if len(w.closed_bits) == 1 else len(w.closed_bits)
+    runs = {"inverse_cdf": lambda: c.sample(2004, n),
+            "metropolis_100_steps": lambda: c.sample_metropolis(2004, n, 100),
+            "frugal_m10_64_trials": lambda: c.sample_frugal(2004, n, 10.0, 64)}
+    res = {"draws": n, "group_size": 1 << len(w.open_qubits)}
+    for name, fn in runs.items():
+        fn()
+        t0 = time.perf_counter()
+        fn()
+        res[name + "_ms"] = 1e3 * (time.perf_counter() - t0)
+    return res
+
+
 def split_compare(w, args, plain_amps, refs, stream) -> dict:
     """The split-precision forms on the same workload: throughput over the same timed
     step (contract + sample) and their amplitude error against the complex64 sum and,
@@ -479,6 +496,7 @@ def main():
         "time_share": {k: v / tot for k, v in share.items()},
         "roofline": roof,
     }
+    out["samplers"] = time_samplers(c, w, args)
     refs = {}
     if not args.no_cpu_baseline:
         out["cpu_baseline"], refs = cpu_baseline(w, flops_slice)

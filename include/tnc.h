@@ -165,6 +165,27 @@ tnc_status tnc_contract_range(tnc_plan plan, void* d_workspace, uint64_t ws_byte
 tnc_status tnc_sample(tnc_plan plan, void* d_workspace, uint64_t ws_bytes, const double* d_amps,
                       uint64_t seed, int64_t n_samples, uint64_t* h_bitstrings, void* hip_stream);
 
+/* The paper's in-group samplers (main text, sampling paragraph), with the same draw
+ * convention as tnc_sample (L == 1: n_samples independent draws from the one group;
+ * L > 1: n_samples == L, draw d from group d), w_mu = re^2 + im^2 rounded as in
+ * tnc_sample, u_k = (SplitMix64 output k+1 from state `seed`) >> 11 times 2^-53 and
+ * floor(u l) for a uniform index.  Synchronous on the stream; the workspace is the one
+ * tnc_contract uses.
+ * tnc_sample_metropolis: draw d runs a Metropolis chain over its group: with
+ * k0 = d (2 steps + 1) it starts at floor(u_k0 l), and step t = 1..steps proposes
+ * nu = floor(u_(k0+2t-1) l) and moves iff w_nu >= u_(k0+2t) w_mu; the draw is the last
+ * state.  steps >= 0.
+ * tnc_sample_frugal: frugal rejection sampling: with k0 = 2 d max_trials, proposal t is
+ * nu = floor(u_(k0+2t) l), accepted iff u_(k0+2t+1) (m S) < w_nu l (S = sum of w over the
+ * group in mu order), i.e. with probability min(1, w_nu / (m mean w)); after max_trials
+ * rejections the last proposal is the draw.  m > 0 finite, max_trials >= 1. */
+tnc_status tnc_sample_metropolis(tnc_plan plan, void* d_workspace, uint64_t ws_bytes,
+                                 const double* d_amps, uint64_t seed, int64_t n_samples,
+                                 int32_t steps, uint64_t* h_bitstrings, void* hip_stream);
+tnc_status tnc_sample_frugal(tnc_plan plan, void* d_workspace, uint64_t ws_bytes,
+                             const double* d_amps, uint64_t seed, int64_t n_samples, double m,
+                             int32_t max_trials, uint64_t* h_bitstrings, void* hip_stream);
+
 tnc_status tnc_plan_destroy(tnc_plan plan);
 tnc_status tnc_net_destroy(tnc_net net);
 

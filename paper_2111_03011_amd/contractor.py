@@ -68,6 +68,19 @@ class Contraction:
         return tnc.tnc_sample(self._plan, self.ws.data_ptr(), self.ws_bytes,
                               self.amps.data_ptr(), seed, n_samples, self._stream(stream))
 
+    def sample_metropolis(self, seed: int, n_samples: int, steps: int, stream=None) -> np.ndarray:
+        """In-group Metropolis chains of `steps` moves (one draw per chain)."""
+        return tnc.tnc_sample_metropolis(self._plan, self.ws.data_ptr(), self.ws_bytes,
+                                         self.amps.data_ptr(), seed, n_samples, steps,
+                                         self._stream(stream))
+
+    def sample_frugal(self, seed: int, n_samples: int, m: float = 10.0, max_trials: int = 64,
+                      stream=None) -> np.ndarray:
+        """Frugal rejection sampling with bound m and at most max_trials proposals."""
+        return tnc.tnc_sample_frugal(self._plan, self.ws.data_ptr(), self.ws_bytes,
+                                     self.amps.data_ptr(), seed, n_samples, m, max_trials,
+                                     self._stream(stream))
+
     def autotune(self, reps: int = 3, stream=None) -> int:
         """Pick tile configurations and split-K per GEMM by timing them; returns how many
         launches changed."""

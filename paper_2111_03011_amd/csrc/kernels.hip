@@ -1284,6 +1284,76 @@ __global__ __launch_bounds__(kThreads) void k_sample_groups(
   }
 }
 
+__device__ __forceinline__ double unif(uint64_t seed, uint64_t k) {
+  return double(splitmix64(seed, k) >> 11) * 0x1.0p-53;
+}
+
+__device__ __forceinline__ int64_t index_of(double u, int64_t l) {
+  const int64_t i = int64_t(__dmul_rn(u, double(l)));
+  return i < l - 1 ? i : l - 1;
+}
+
+// In-group Metropolis chains, one thread per draw d (draws d0 + 0..n-1; group d for several
+// groups, else group 0): start floor(u_k0 l), k0 = d (2 steps + 1); step t proposes
+// floor(u_(k0+2t-1) l) and moves iff w_nu >= u_(k0+2t) w_mu.
+__global__ __launch_bounds__(kThreads) void k_sample_metropolis(
+    const double* amps, int64_t L, int n_open, const uint64_t* closed, const int32_t* open_q,
+    int n, uint64_t seed, int64_t d0, int64_t n_draws, int steps, uint64_t* out) {
+  const int64_t l = int64_t(1) << n_open;
+  for (int64_t j = int64_t(blockIdx.x) * kThreads + threadIdx.x; j < n_draws;
+       j += int64_t(gridDim.x) * kThreads) {
+    const int64_t d = d0 + j, g = L > 1 ? d : 0;
+    const double* a = amps + 2 * g * l;
+    const uint64_t k0 = uint64_t(d) * uint64_t(2 * steps + 1);
+    int64_t mu = index_of(unif(seed, k0), l);
+    double wmu = weight(a, mu);
+    for (int t = 1; t <= steps; ++t) {
+      const int64_t nu = index_of(unif(seed, k0 + 2 * t - 1), l);
+      const double wnu = weight(a, nu);
+      if (wnu >= __dmul_rn(unif(seed, k0 + 2 * t), wmu)) {
+        mu = nu;
+        wmu = wnu;
+      }
+    }
+    out[j] = compose(closed[g], mu, n_open, open_q, n);
+  }
+}
+
+// Frugal rejection sampling, one thread per draw: k0 = 2 d trials; proposal t is
+// floor(u_(k0+2t) l), accepted iff u_(k0+2t+1) (m S) < w_nu l with S the group's weight sum
+// in mu order (totals[g]); after `trials` rejections the last proposal is kept.
+__global__ __launch_bounds__(kThreads) void k_sample_frugal(
+    const double* amps, const double* totals, int64_t L, int n_open, const uint64_t* closed,
+    const int32_t* open_q, int n, uint64_t seed, int64_t d0, int64_t n_draws, double m,
+    int trials, uint64_t* out) {
+  const int64_t l = int64_t(1) << n_open;
+  for (int64_t j = int64_t(blockIdx.x) * kThreads + threadIdx.x; j < n_draws;
+       j += int64_t(gridDim.x) * kThreads) {
+    const int64_t d = d0 + j, g = L > 1 ? d : 0;
+    const double* a = amps + 2 * g * l;
+    const double ms = __dmul_rn(m, totals[g]);
+    const uint64_t k0 = uint64_t(d) * uint64_t(2 * trials);
+    int64_t nu = 0;
+    for (int t = 0; t < trials; ++t) {
+      nu = index_of(unif(seed, k0 + 2 * t), l);
+      if (__dmul_rn(unif(seed, k0 + 2 * t + 1), ms) < __dmul_rn(weight(a, nu), double(l))) break;
+    }
+    out[j] = compose(closed[g], nu, n_open, open_q, n);
+  }
+}
+
+// Weight sum of each group in mu order (one thread per group).
+__global__ __launch_bounds__(kThreads) void k_group_totals(const double* amps, int64_t L,
+                                                           int64_t l, double* totals) {
+  for (int64_t g = int64_t(blockIdx.x) * kThreads + threadIdx.x; g < L;
+       g += int64_t(gridDim.x) * kThreads) {
+    const double* a = amps + 2 * g * l;
+    double c = 0.0;
+    for (int64_t i = 0; i < l; ++i) c = __dadd_rn(c, weight(a, i));
+    totals[g] = c;
+  }
+}
+
 int grid_for(int64_t work, int64_t per_block, int64_t cap = 8192) {
   int64_t g = (work + per_block - 1) / per_block;
   if (g < 1) g = 1;
@@ -1481,6 +1551,32 @@ hipError_t launch_norm(const double* amps, int64_t n, double* partials, int n_pa
                        double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_norm_partial, dim3(n_partials), dim3(kThreads), 0, s, amps, n, partials);
   hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(kThreads), 0, s, partials, n_partials, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_metropolis(const double* amps, int64_t L, int n_open, const uint64_t* closed,
+                                    const int32_t* open_qubits, int n_qubits, uint64_t seed,
+                                    int64_t d0, int64_t n_draws, int steps, uint64_t* out,
+                                    hipStream_t s) {
+  hipLaunchKernelGGL(k_sample_metropolis, dim3(grid_for(n_draws, kThreads)), dim3(kThreads), 0, s,
+                     amps, L, n_open, closed, open_qubits, n_qubits, seed, d0, n_draws, steps, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_totals(const double* amps, int64_t L, int n_open, double* totals,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_group_totals, dim3(grid_for(L, kThreads)), dim3(kThreads), 0, s, amps, L,
+                     int64_t(1) << n_open, totals);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_frugal(const double* amps, const double* totals, int64_t L, int n_open,
+                                const uint64_t* closed, const int32_t* open_qubits, int n_qubits,
+                                uint64_t seed, int64_t d0, int64_t n_draws, double m, int trials,
+                                uint64_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sample_frugal, dim3(grid_for(n_draws, kThreads)), dim3(kThreads), 0, s,
+                     amps, totals, L, n_open, closed, open_qubits, n_qubits, seed, d0, n_draws, m,
+                     trials, out);
   return hipGetLastError();
 }
 

@@ -186,7 +186,7 @@ struct tnc_plan_s {
   // sampling and norm scratch
   int64_t closed_off = 0, open_off = 0;
   int norm_parts = 1024;
-  int b_norm = -1, b_cum = -1, b_samples = -1, b_counter = -1;
+  int b_norm = -1, b_cum = -1, b_samples = -1, b_counter = -1, b_totals = -1;
   int batch = 1;
   // slice-id bits that vary inside some batch of the slice list (batches of `batch`
   // consecutive ids, or shorter runs, see Exec::run_length); a dependent step whose bits
@@ -839,6 +839,7 @@ struct Compiler {
     plan.b_norm = new_buf(uint64_t(plan.norm_parts + 1) * 8);
     const int64_t l = int64_t(1) << net.open.size();
     plan.b_cum = new_buf(uint64_t(l) * 8);
+    plan.b_totals = new_buf(uint64_t(plan.L) * 8);
     plan.sample_chunk = std::max<int64_t>(plan.L, 65536);
     plan.b_samples = new_buf(uint64_t(plan.sample_chunk) * 8);
     plan.b_counter = new_buf(8);
@@ -1186,6 +1187,35 @@ void sample_into(tnc_plan_s& p, uint8_t* ws, const double* amps, uint64_t seed, 
     hipError_t err = launch_sample(amps, 1, p.n_open, closed, openq, p.n_qubits, seed_c, c, cum,
                                    dout, st);
     if (err != hipSuccess) fail(TNC_E_HIP, hipGetErrorString(err));
+    HIPCHK(hipMemcpyAsync(h_bits + done, dout, uint64_t(c) * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+}
+
+// In-group Metropolis chains (steps >= 0) or frugal rejection sampling (trials >= 1, m > 0);
+// synchronous on `st`.  Draw d keeps counting across chunks of one group's draws.
+void sample_chain_into(tnc_plan_s& p, uint8_t* ws, const double* amps, uint64_t seed,
+                       int64_t n_samples, bool frugal, int32_t steps_or_trials, double m,
+                       uint64_t* h_bits, hipStream_t st) {
+  if (n_samples < 0) fail(TNC_E_INVALID, "negative sample count");
+  if (p.L > 1 && n_samples != p.L)
+    fail(TNC_E_INVALID, "with several groups, n_samples must equal the number of groups");
+  if (frugal && (steps_or_trials < 1 || !(m > 0.0) || !std::isfinite(m)))
+    fail(TNC_E_INVALID, "frugal sampling needs trials >= 1 and a finite m > 0");
+  if (!frugal && steps_or_trials < 0) fail(TNC_E_INVALID, "negative chain length");
+  Exec e{p, ws, st};
+  e.upload();
+  uint64_t* dout = reinterpret_cast<uint64_t*>(ws + p.bufs[p.b_samples].off);
+  double* totals = reinterpret_cast<double*>(ws + p.bufs[p.b_totals].off);
+  const uint64_t* closed = reinterpret_cast<const uint64_t*>(ws + p.closed_off);
+  const int32_t* openq = reinterpret_cast<const int32_t*>(ws + p.open_off);
+  if (frugal && n_samples > 0) e.check(launch_group_totals(amps, p.L, p.n_open, totals, st));
+  for (int64_t done = 0; done < n_samples; done += p.sample_chunk) {
+    const int64_t c = std::min(p.sample_chunk, n_samples - done);
+    e.check(frugal ? launch_sample_frugal(amps, totals, p.L, p.n_open, closed, openq, p.n_qubits,
+                                          seed, done, c, m, steps_or_trials, dout, st)
+                   : launch_sample_metropolis(amps, p.L, p.n_open, closed, openq, p.n_qubits,
+                                              seed, done, c, steps_or_trials, dout, st));
     HIPCHK(hipMemcpyAsync(h_bits + done, dout, uint64_t(c) * 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
   }
@@ -1863,6 +1893,30 @@ tnc_status tnc_sample(tnc_plan p, void* ws, uint64_t ws_bytes, const double* amp
     DeviceGuard dg(p->device);
     sample_into(*p, static_cast<uint8_t*>(ws), amps, seed, n_samples, h_bits,
                 static_cast<hipStream_t>(stream));
+  });
+}
+
+tnc_status tnc_sample_metropolis(tnc_plan p, void* ws, uint64_t ws_bytes, const double* amps,
+                                 uint64_t seed, int64_t n_samples, int32_t steps,
+                                 uint64_t* h_bits, void* stream) {
+  return guard([&] {
+    if (!p || !amps || (n_samples > 0 && !h_bits)) fail(TNC_E_INVALID, "null argument");
+    check_ws(p, ws, ws_bytes);
+    DeviceGuard dg(p->device);
+    sample_chain_into(*p, static_cast<uint8_t*>(ws), amps, seed, n_samples, false, steps, 0.0,
+                      h_bits, static_cast<hipStream_t>(stream));
+  });
+}
+
+tnc_status tnc_sample_frugal(tnc_plan p, void* ws, uint64_t ws_bytes, const double* amps,
+                             uint64_t seed, int64_t n_samples, double m, int32_t max_trials,
+                             uint64_t* h_bits, void* stream) {
+  return guard([&] {
+    if (!p || !amps || (n_samples > 0 && !h_bits)) fail(TNC_E_INVALID, "null argument");
+    check_ws(p, ws, ws_bytes);
+    DeviceGuard dg(p->device);
+    sample_chain_into(*p, static_cast<uint8_t*>(ws), amps, seed, n_samples, true, max_trials, m,
+                      h_bits, static_cast<hipStream_t>(stream));
   });
 }
 

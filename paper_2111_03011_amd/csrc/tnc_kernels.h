@@ -152,6 +152,19 @@ hipError_t launch_add_i64(int64_t* p, int64_t v, hipStream_t s);
 // Sum of |amp|^2 over n complex128 values into *out (device double), deterministic.
 hipError_t launch_norm(const double* amps, int64_t n, double* partials, int n_partials,
                        double* out, hipStream_t s);
+// In-group Metropolis chains and frugal rejection sampling (see tnc.h): draws d0 ..
+// d0 + n_draws - 1, bitstrings to out[n_draws] (device).  totals: per-group weight sums
+// from launch_group_totals.
+hipError_t launch_sample_metropolis(const double* amps, int64_t L, int n_open, const uint64_t* closed,
+                                    const int32_t* open_qubits, int n_qubits, uint64_t seed,
+                                    int64_t d0, int64_t n_draws, int steps, uint64_t* out,
+                                    hipStream_t s);
+hipError_t launch_group_totals(const double* amps, int64_t L, int n_open, double* totals,
+                               hipStream_t s);
+hipError_t launch_sample_frugal(const double* amps, const double* totals, int64_t L, int n_open,
+                                const uint64_t* closed, const int32_t* open_qubits, int n_qubits,
+                                uint64_t seed, int64_t d0, int64_t n_draws, double m, int trials,
+                                uint64_t* out, hipStream_t s);
 // Inverse-CDF sampler (see tnc.h): writes bitstrings to out[n_samples] (device).
 hipError_t launch_sample(const double* amps, int64_t L, int n_open, const uint64_t* closed,
                          const int32_t* open_qubits, int n_qubits, uint64_t seed,
