@@ -10,6 +10,13 @@ Slicing (Appendix B.2) fixes a bond of the network to one value.  A bond here is
 from 0).  Fixing it to v is the same as inserting the projector |v><v| on that wire, so
 `simulate(..., projectors={(q, j): v})` returns the unnormalised state of one slice,
 <s|U_sigma|0^n> for every s.
+
+Hole drilling (Method): a circuit may list `holes`, indices of two-qubit gates in circuit
+order (cycle by cycle, coupler order).  Drilling gate g breaks its two input edges by
+inserting E = |0><0| on each, right before the gate; since fSim|00> = |00>, the drilled
+gate with both inputs projected is |00><00|, so the simulator applies the projector
+|0><0| to both qubits in place of the gate.  The result is the unnormalised approximate
+state psi_hat of the perturbed network.
 """
 
 from __future__ import annotations
@@ -43,12 +50,18 @@ def simulate(circuit: dict, projectors: dict | None = None) -> np.ndarray:
     psi = np.zeros((2,) * n, dtype=np.complex128)
     psi[(0,) * n] = 1.0
     g = fsim_tensor(circuit["fsim"]["theta"], circuit["fsim"]["phi"])
+    holes = set(int(h) for h in circuit.get("holes", ()))
     n2q = [0] * n
+    gate = 0
     for layer in circuit["layers"]:
         for q, name in enumerate(layer["oneq"]):
             psi = apply_1q(psi, ONEQ[name], q)
         for qa, qb in layer["couplers"]:
-            psi = apply_2q(psi, g, qa, qb)
+            if gate in holes:
+                psi = project(project(psi, qa, 0), qb, 0)
+            else:
+                psi = apply_2q(psi, g, qa, qb)
+            gate += 1
             for q in (qa, qb):
                 key = (q, n2q[q])
                 if key in projectors:

@@ -102,3 +102,48 @@ def test_sparse_from_state_bit_order():
     out = statevector.sparse_from_state(psi, n, [2, 0], [0b010])
     # mu = (s2, s0): (0,0)->x=010=2, (0,1)->110=6, (1,0)->011=3, (1,1)->111=7
     assert list(out[0]) == [2, 6, 3, 7]
+
+
+def test_drilled_gate_is_the_input_projector_pair():
+    """Hole drilling (Method): both input edges of a drilled fSim get E = |0><0|.  Eq. (1)
+    has e0 as its first row and column, so fSim (P0 x P0) = (P0 x P0) fSim = |00><00| and
+    the gate can be dropped; the simulator's drilled state equals the brute-force product
+    with the projector pair in the gate's place (3 qubits, the middle gate drilled)."""
+    for theta, phi in ((math.pi / 2, math.pi / 6), (0.7, 1.9)):
+        f = gates.fsim(theta, phi)
+        p00 = np.zeros((4, 4), dtype=complex)
+        p00[0, 0] = 1.0
+        assert np.allclose(f @ p00, p00) and np.allclose(p00 @ f, p00)
+    layers = [(["sqrt_y", "sqrt_w", "sqrt_x"], [(0, 1)]), (["sqrt_x", "sqrt_y", "sqrt_w"], [(1, 2)]),
+              (["sqrt_w", "sqrt_x", "sqrt_y"], [(0, 2)])]
+    c = _circuit(3, layers)
+    c["holes"] = [1]
+    f = gates.fsim(c["fsim"]["theta"], c["fsim"]["phi"])
+    proj = np.zeros((4, 4), dtype=complex)
+    proj[0, 0] = 1.0
+    u = np.eye(8, dtype=complex)
+    gate = 0
+    for oneq, couplers in layers:
+        u = _full_oneq_layer(oneq) @ u
+        for qa, qb in couplers:
+            u = _full_two_qubit(3, qa, qb, proj if gate == 1 else f) @ u
+            gate += 1
+    assert np.allclose(statevector.simulate(c), u[:, 0], atol=1e-14)
+
+
+def test_drilled_fidelity_follows_two_to_the_minus_k():
+    """Each broken edge halves the fidelity (Method, F_K ~ 2^-K with K = 2 per hole): on a
+    4x5-qubit, 14-cycle random circuit the mean of F / 2^-K over six random hole positions
+    in the middle half of the gates is within 25% of 1 for one to three holes."""
+    from oracle.metrics import fidelity
+    circ = synth.make_circuit(4, 5, 14, 72)
+    psi = statevector.simulate(circ)
+    n2 = sum(len(l["couplers"]) for l in circ["layers"])
+    rng = np.random.default_rng(72)
+    for h in (1, 2, 3):
+        ratios = []
+        for _ in range(6):
+            c = dict(circ)
+            c["holes"] = sorted(rng.choice(range(n2 // 4, 3 * n2 // 4), size=h, replace=False).tolist())
+            ratios.append(fidelity(statevector.simulate(c), psi) / 2.0 ** (-2 * h))
+        assert 0.8 < np.mean(ratios) < 1.25, (h, ratios)
