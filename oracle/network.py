@@ -11,6 +11,10 @@ for every j except the last two-qubit gate on q, and `bond_label[(q, j)]` maps s
 name to its wire label.  A qubit's last wire is
 its output leg `out_label[q]`.  The right boundary attaches a basis vector e_{s_q} to
 the output leg of every closed qubit and leaves the open qubits' legs open.
+
+Hole drilling (Method): a gate listed in `circuit["holes"]` (index in circuit order) has
+both input edges broken by E = |0><0|, which turns the fSim tensor into |00><00|; here
+that four-way tensor takes the gate's place (the wires stay connected).
 """
 
 from __future__ import annotations
@@ -54,6 +58,10 @@ def build_network(circuit: dict, closed_values: dict | None = None) -> Network:
     n = circuit["n_qubits"]
     closed_values = dict(closed_values or {})
     g = fsim_tensor(circuit["fsim"]["theta"], circuit["fsim"]["phi"])
+    holes = set(int(h) for h in circuit.get("holes", ()))
+    p00 = np.zeros((2, 2, 2, 2), dtype=np.complex128)
+    p00[0, 0, 0, 0] = 1.0
+    gate = 0
     net = Network()
     k = [0] * n
     n2q = [0] * n
@@ -65,8 +73,9 @@ def build_network(circuit: dict, closed_values: dict | None = None) -> Network:
             net.add(ONEQ[name], [("w", q, k[q] + 1), ("w", q, k[q])])
             k[q] += 1
         for qa, qb in layer["couplers"]:
-            net.add(g, [("w", qa, k[qa] + 1), ("w", qb, k[qb] + 1),
-                        ("w", qa, k[qa]), ("w", qb, k[qb])])
+            net.add(p00 if gate in holes else g, [("w", qa, k[qa] + 1), ("w", qb, k[qb] + 1),
+                                                  ("w", qa, k[qa]), ("w", qb, k[qb])])
+            gate += 1
             for q in (qa, qb):
                 k[q] += 1
                 net.bond_label[(q, n2q[q])] = ("w", q, k[q])

@@ -147,3 +147,20 @@ def test_drilled_fidelity_follows_two_to_the_minus_k():
             c["holes"] = sorted(rng.choice(range(n2 // 4, 3 * n2 // 4), size=h, replace=False).tolist())
             ratios.append(fidelity(statevector.simulate(c), psi) / 2.0 ** (-2 * h))
         assert 0.8 < np.mean(ratios) < 1.25, (h, ratios)
+
+
+def test_drilled_network_contraction_equals_drilled_state():
+    """The oracle's contractor on its drilled network (the |00><00| tensor in the gate's
+    place) gives the simulator's drilled state, per group and summed over slices."""
+    from oracle import contract as ocontract
+    circ = synth.make_circuit(3, 3, 8, 5)
+    circ["holes"] = [2, 9, 15]
+    n = circ["n_qubits"]
+    psi = statevector.simulate(circ)
+    got = ocontract.sparse_amplitudes(circ, list(range(n)), [0])
+    assert np.allclose(got.reshape(-1), psi, atol=1e-13)
+    bonds = [(1, 1), (4, 2)]
+    part = ocontract.sparse_amplitudes(circ, [0, 4, 8], [0b000110000], sliced_bonds=bonds,
+                                       slice_ids=[0, 1, 2, 3])
+    ref = statevector.sparse_from_state(psi, n, [0, 4, 8], [0b000110000])
+    assert np.allclose(part, ref, atol=1e-13)
