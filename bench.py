@@ -144,6 +144,45 @@ def time_samplers(c, w, args) -> dict:
     return res
 
 
+def perturbed(args, plain_amps, plain_amps_per_s) -> dict:
+    """The same workload with holes drilled into the circuit (Method): K = 2 per hole broken
+    edges, fidelity estimate 2^-K.  Timed over the same step; the fidelity of its 4096
+    amplitudes to the plain (exact) sum is reported beside the estimate."""
+    import torch
+    from paper_2111_03011_amd.contractor import Contraction
+    from paper_2111_03011_amd.workload import config_workload
+    w = config_workload("sliced", mode="holes")
+    c = Contraction(w.net, w.plan.path, sliced_labels=w.plan.sliced_labels,
+                    slice_ids=w.slice_ids, open_qubits=w.open_qubits, closed_bits=w.closed_bits,
+                    max_batch_slices=args.batch)
+    if args.autotune:
+        c.autotune(reps=2)
+    n_samp = args.samples if len(w.closed_bits) == 1 else len(w.closed_bits)
+    c.contract(norm=True)
+    c.sample(2004, n_samp)
+    steps = max(1, min(args.steps, 3))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        c.contract(norm=True)
+        c.sample(2004, n_samp)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    amps = c.amps.cpu().numpy().copy()
+    work = c.work()
+    c.close()
+    K = 2 * len(w.circuit["holes"])
+    aps = w.n_amplitudes / (ms * 1e-3)
+    print(f"[bench] perturbed network ({K} broken edges): {aps:.0f} amplitudes/s",
+          file=sys.stderr, flush=True)
+    return {"holes": [int(h) for h in w.circuit["holes"]], "broken_edges": K,
+            "fidelity_estimate": 2.0 ** -K,
+            "fidelity_vs_exact_4096_amplitudes": 1.0 - infidelity(amps, plain_amps),
+            "amplitudes_per_s": aps, "ms_per_step": ms, "flops_per_step": work,
+            "tflops": work / (ms * 1e-3) / 1e12,
+            "speedup_vs_plain_c64": aps / plain_amps_per_s}
+
+
 def split_compare(w, args, plain_amps, refs, stream) -> dict:
     """The split-precision forms on the same workload: throughput over the same timed
     step (contract + sample) and their amplitude error against the complex64 sum and,
@@ -352,6 +391,8 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="slices per launch (hipGraph per batch)")
     ap.add_argument("--autotune", type=int, default=1, help="time tile choices per GEMM first (1/0)")
     ap.add_argument("--precision", default="c64", choices=["c64", "bf16x3", "fp16x3"])
+    ap.add_argument("--perturbed", type=int, default=1,
+                    help="sliced, c64: also time the workload with holes drilled (1/0)")
     ap.add_argument("--head-reuse", type=int, default=1,
                     help="sliced, c64: also time the head-reuse plan of the same workload (1/0)")
     ap.add_argument("--split-compare", type=int, default=1,
@@ -502,7 +543,7 @@ def main():
         out["cpu_baseline"], refs = cpu_baseline(w, flops_slice)
         out["rel_err_vs_oracle_slices"] = slice_errors(c, refs)
     extra = args.precision == "c64" and args.workload == "sliced"
-    if extra and (args.split_compare or args.head_reuse):
+    if extra and (args.split_compare or args.head_reuse or args.perturbed):
         c.contract()
         plain = c.amps.cpu().numpy().copy()
         c.close()
@@ -510,6 +551,8 @@ def main():
             out["split_precision"] = split_compare(w, args, plain, refs, stream)
         if args.head_reuse:
             out["head_reuse"] = head_reuse(args, plain, out["amplitudes_per_s"])
+        if args.perturbed:
+            out["perturbed_network"] = perturbed(args, plain, out["amplitudes_per_s"])
     else:
         c.close()
     print(json.dumps(out), flush=True)

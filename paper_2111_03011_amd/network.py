@@ -78,8 +78,20 @@ def _apply_matrix(t: np.ndarray, labels: list, lab: int, m: np.ndarray, side: st
 
 
 def circuit_network(circuit: dict, simplify: bool = True) -> TensorNetwork:
+    """Tensor network of a circuit (Method).  `circuit["holes"]` (optional) lists two-qubit
+    gates, by index in circuit order, whose two input edges are broken (hole drilling,
+    Method): E = |0><0| on each input wire makes the fSim gate |00><00|, so the gate is
+    dropped, the incoming wire is closed with <0| (after its pending single-qubit gates)
+    and the outgoing wire starts again from |0>.  The perturbed network's amplitudes are
+    those of psi_hat, with fidelity about 2^-K for K = 2 per hole."""
     n = circuit["n_qubits"]
     g = _fsim4(circuit["fsim"]["theta"], circuit["fsim"]["phi"])
+    holes = set(int(h) for h in circuit.get("holes", ()))
+    n2 = sum(len(layer["couplers"]) for layer in circuit["layers"])
+    if any(h < 0 or h >= n2 for h in holes):
+        raise ValueError(f"hole indices must name one of the {n2} two-qubit gates")
+    gate = 0
+    scale = complex(1.0)
     next_label = [0]
 
     def new_label():
@@ -100,6 +112,23 @@ def circuit_network(circuit: dict, simplify: bool = True) -> TensorNetwork:
             else:
                 pending[q] = u @ pending[q]
         for qa, qb in layer["couplers"]:
+            drilled = gate in holes
+            gate += 1
+            if drilled:
+                for q in (qa, qb):
+                    if last[q] is None:            # wire still a vector: <0|v is a number
+                        scale *= complex(head[q][0])
+                    else:                          # close the last fSim's output with <0|P
+                        idx, o = last[q]
+                        ax = labels[idx].index(o)
+                        tensors[idx] = np.tensordot(tensors[idx], pending[q][0, :], axes=([ax], [0]))
+                        labels[idx].remove(o)
+                        bond_of.pop(o, None)
+                    head[q] = np.array([1.0, 0.0], dtype=np.complex128)
+                    pending[q] = np.eye(2, dtype=np.complex128)
+                    last[q] = None
+                    n2q[q] += 1
+                continue
             t = g.copy()
             oa, ob = new_label(), new_label()
             labs = [oa, ob, -1, -2]
@@ -133,6 +162,15 @@ def circuit_network(circuit: dict, simplify: bool = True) -> TensorNetwork:
             tensors[idx] = _apply_matrix(tensors[idx], labels[idx], o, pending[q], "out")
             out_label[q] = o
             bond_of.pop(o, None)          # last output of a qubit is its leg, not a bond
+    # tensors left without legs by closed wires are numbers: fold them into one tensor
+    keep = [k for k in range(len(tensors)) if labels[k]]
+    for k in range(len(tensors)):
+        if not labels[k]:
+            scale *= complex(np.asarray(tensors[k]).reshape(()))
+    tensors = [tensors[k] for k in keep]
+    labels = [labels[k] for k in keep]
+    if scale != 1.0:
+        tensors[0] = tensors[0] * scale
     net = TensorNetwork(n_qubits=n, tensors=tensors, labels=labels, out_label=out_label,
                         bond_label={v: k for k, v in bond_of.items()})
     if simplify:

@@ -49,6 +49,41 @@ def make_workload(circuit: dict, open_qubits, closed_bits, max_log2: float = 26,
                     plan, ids)
 
 
+def choose_holes(circuit: dict, n_holes: int, open_qubits, closed_bits, max_log2: float = 26,
+                 n_sliced=None, first_cycle: int | None = None, last_cycle: int | None = None,
+                 seed: int = 0) -> list:
+    """Hole positions for the perturbed network (Method: holes are placed so that the
+    perturbed network is much cheaper to contract).  Greedy: each round drills the
+    two-qubit gate, among those of cycles [first_cycle, last_cycle) (default: the middle
+    third), whose network has the lowest planned total flops (one greedy path per
+    candidate, same size bound and slice count)."""
+    layers = circuit["layers"]
+    m = len(layers)
+    c0 = m // 3 if first_cycle is None else first_cycle
+    c1 = (2 * m) // 3 if last_cycle is None else last_cycle
+    starts = np.cumsum([0] + [len(l["couplers"]) for l in layers])
+    cands = [g for c in range(c0, c1) for g in range(int(starts[c]), int(starts[c + 1]))]
+    holes = []
+    for _ in range(n_holes):
+        best = None
+        for g in cands:
+            if g in holes:
+                continue
+            c = dict(circuit)
+            c["holes"] = sorted(holes + [g])
+            try:
+                plan = find_plan(circuit_network(c), open_qubits, closed_bits, max_log2=max_log2,
+                                 n_sliced=n_sliced, trials=1, seed=seed)
+            except RuntimeError:
+                continue
+            if best is None or plan.total_flops < best[0]:
+                best = (plan.total_flops, g)
+        if best is None:
+            break
+        holes.append(best[1])
+    return sorted(holes)
+
+
 _CACHE = {}
 
 
@@ -56,7 +91,9 @@ def config_workload(name: str, mode: str = "default", trials: int | None = None)
     """name: small | sliced | large.  For small, mode 'amplitudes' (64 bitstrings, no open
     qubit) or 'samples' (all 12 qubits open, one group).  For sliced, mode 'reuse' plans
     for head reuse (bound-driven global slices, cheap local ones on the low slice-id bits,
-    steps above global labels once per batch of the configuration's reuse_batch).  trials
+    steps above global labels once per batch of the configuration's reuse_batch), and mode
+    'holes' drills the configuration's number of holes (chosen by choose_holes) into the
+    circuit, a perturbed network with fidelity about 2^-K (K = 2 per hole).  trials
     defaults to the configuration's plan_trials.  Plans are deterministic and memoised per
     process."""
     key = (name, mode, trials)
@@ -82,6 +119,11 @@ def _config_workload(name: str, mode: str, trials: int | None) -> Workload:
     open_q = cfg["open_qubits"]
     g = cfg["groups"]
     closed = synth.group_targets(n, open_q, g["L"], g["seed"])
+    if mode == "holes":
+        circuit = dict(circuit)
+        circuit["holes"] = choose_holes(circuit, cfg["holes"], open_q, closed,
+                                        max_log2=cfg["max_log2_size"],
+                                        n_sliced=cfg.get("sliced_labels"), seed=cfg["path_seed"])
     net = circuit_network(circuit)
     plan = find_plan(net, open_q, closed, max_log2=cfg["max_log2_size"],
                      n_sliced=cfg.get("sliced_labels"), trials=trials, seed=cfg["path_seed"],

@@ -37,6 +37,7 @@ CONFIGS = {
         "path_seed": 2005,
         "plan_trials": 64,
         "reuse_batch": 64,        # head-reuse plan: steps above global labels once per 64
+        "holes": 2,               # perturbed-network mode: drilled two-qubit gates (K = 4)
     },
     "precision": {
         "name": "precision",

@@ -381,3 +381,38 @@ def test_head_reuse_plan_and_its_work():
     assert not any(i.invariant == 2 for i in infos)
     assert math.isclose(tnc.tnc_plan_work(q, 0, n), inv + n * ps, rel_tol=1e-12)
     tnc.tnc_plan_destroy(q)
+
+
+def test_drilled_network_builder_matches_oracle():
+    """Hole drilling in the network builder (Method): the drilled gate is dropped, its
+    incoming wires closed with <0| and its outgoing wires restarted from |0>.  The built
+    network, contracted by the oracle's contractor, equals the oracle's drilled state
+    (holes in the first cycle, adjacent ones, and one on the last gate of a qubit)."""
+    circ = synth.make_circuit(3, 4, 8, 1001)
+    n = circ["n_qubits"]
+    n2 = sum(len(l["couplers"]) for l in circ["layers"])
+    for holes in ([5], [0, 1, 2], [3, 4, 17], [n2 - 1, n2 - 2]):
+        c = dict(circ)
+        c["holes"] = holes
+        net = circuit_network(c)
+        plan = planner.find_plan(net, list(range(n)), np.zeros(1, np.uint64), trials=2)
+        got = ocontract.contract_path(net.tensors, net.labels, plan.path, net.out_label)
+        assert np.allclose(got.reshape(-1), statevector.simulate(c), atol=1e-12), holes
+    bad = dict(circ)
+    bad["holes"] = [n2]
+    with pytest.raises(ValueError):
+        circuit_network(bad)
+
+
+def test_chosen_holes_lower_the_planned_cost():
+    from paper_2111_03011_amd.workload import choose_holes
+    circ = synth.make_circuit(4, 4, 10, 61)
+    open_q = list(range(10, 16))
+    closed = np.zeros(1, np.uint64)
+    holes = choose_holes(circ, 2, open_q, closed, max_log2=26)
+    assert len(holes) == 2
+    plain = planner.find_plan(circuit_network(circ), open_q, closed, trials=1)
+    c = dict(circ)
+    c["holes"] = holes
+    drilled = planner.find_plan(circuit_network(c), open_q, closed, trials=1)
+    assert drilled.total_flops < plain.total_flops
