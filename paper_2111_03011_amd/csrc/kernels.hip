@@ -789,8 +789,11 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
   constexpr int BN = WAVES_N * UN * 16;
   using Tile = GemmTile<BM, BN, BK, A_MFAST, B_NFAST, false>;
   constexpr int A_LD = Tile::A_LD, B_LD = Tile::B_LD;
-  constexpr int RS = 2 * BK + 8;               // bf16 per LDS row (32 real k + 16 B pad)
+  constexpr int RS = 2 * BK;                   // bf16 per LDS row (32 real k, 64 bytes)
   constexpr int A_PLANE = BM * RS, B_PLANE = 2 * BN * RS;
+  // chunk rotation of row r: c ^ ((r >> 1) ^ (r >> S2) ^ (r >> S3)), shifts per tile width
+  constexpr int LBN = BN >= 128 ? 7 : BN >= 64 ? 6 : BN >= 32 ? 5 : 4;
+  constexpr int S2 = BN <= 16 ? 3 : 2, S3 = BN <= 16 ? 4 : LBN - 1;
   constexpr int STAGE = 2 * A_PLANE + 2 * B_PLANE;   // hi and lo planes of A and B
   __shared__ __attribute__((aligned(16))) __bf16 lds[2 * STAGE];
 
@@ -827,21 +830,24 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
 
   float2 ra[A_LD], rb[B_LD];
   uint32_t valid = 0;
-  // LDS rows hold 32 bf16 of k in four 16-byte chunks; chunk c of row r is stored at
-  // position c ^ ((r >> 3) & 3), so that 16-byte writes to every other row (the embedded
-  // B columns 2n) and fragment reads of eight consecutive rows are free of bank conflicts
+  // LDS rows hold 32 bf16 of k in four 16-byte chunks, unpadded; chunk c of row r is stored
+  // at position c ^ ((r >> 1) ^ (r >> S2) ^ (r >> S3)) & 3.  The embedded B column 2n + c
+  // (c = 0: (re, -im), c = 1: (im, re)) is LDS row n + BN c.  With this layout the 16-byte
+  // staging writes and fragment reads of the tile shapes in use are free of bank conflicts
+  // on a 64-bank LDS (16 lanes per 16-byte access) and nearly so on a 32-bank one.
   auto lds_off = [](int row, int kq) {
-    return row * RS + ((((kq >> 3) ^ (row >> 3)) & 3) << 3) + (kq & 7);
+    const int rot = (row >> 1) ^ (row >> S2) ^ (row >> S3);
+    return row * RS + ((((kq >> 3) ^ rot) & 3) << 3) + (kq & 7);
   };
   // LDS element offsets of this thread's load slots (A: row-major k pairs; B: the two
-  // embedded columns 2n and 2n + 1 of its (k, n) value)
+  // embedded columns 2n and 2n + 1 of its (k, n) value, LDS rows n and BN + n)
   int a_so[A_LD], b_so0[B_LD], b_so1[B_LD];
 #pragma unroll
   for (int i = 0; i < A_LD; ++i) a_so[i] = lds_off(Tile::a_row(i), 2 * Tile::a_col(i));
 #pragma unroll
   for (int i = 0; i < B_LD; ++i) {
-    b_so0[i] = lds_off(2 * Tile::b_n(i), 2 * Tile::b_kr(i));
-    b_so1[i] = lds_off(2 * Tile::b_n(i) + 1, 2 * Tile::b_kr(i));
+    b_so0[i] = lds_off(Tile::b_n(i), 2 * Tile::b_kr(i));
+    b_so1[i] = lds_off(BN + Tile::b_n(i), 2 * Tile::b_kr(i));
   }
   auto store = [&](int stage) {
     if (valid != t.full_bits) Tile::apply(valid, ra, rb);
@@ -924,7 +930,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
 #pragma unroll
     for (int i = 0; i < UM; ++i) a_rd[ks][i] = lds_off(wm * UM * 32 + i * 32 + j32, 8 * (half + 2 * ks));
 #pragma unroll
-    for (int j = 0; j < UN; ++j) b_rd[ks][j] = lds_off(2 * (wn * UN * 16 + j * 16) + j32, 8 * (half + 2 * ks));
+    for (int j = 0; j < UN; ++j)
+      b_rd[ks][j] = lds_off(wn * UN * 16 + j * 16 + (j32 >> 1) + BN * (j32 & 1), 8 * (half + 2 * ks));
   }
 
   int stage = 0;
