@@ -161,3 +161,36 @@ def test_fp16_scale_of_a_produced_operand(blocks):
     err = metrics.rel_error(got, ref)
     log(f"fp16x3 chain, split-K {[l.k_splits for l in g]}: rel err {err:.3e}")
     assert np.all(np.isfinite(got)) and err <= 1e-5
+
+
+@pytest.mark.parametrize("form", FORMS, ids=[f[0] for f in FORMS])
+@pytest.mark.parametrize("config", [0, 1, 3, 4])
+@pytest.mark.parametrize("free_a", [7, 6])
+def test_split_m_fast_operand_paired_loads(config, free_a, form):
+    """An M-side operand whose fastest label is an m label is loaded two rows per 16-byte
+    access in the 128-row tiles; full (M = 128) and partial (M = 64) tiles, split-K off and
+    on, against the oracle."""
+    import os
+    name, prec, tol = form
+    shared, free_b = 9, 5
+    k = list(range(shared))
+    fa = list(range(shared, shared + free_a))
+    order_a = k + fa                                   # m labels last: m is A's fastest index
+    net = random_pair_network(free_a + shared, free_b + shared, shared, 700 + free_a, order_a, None)
+    ref = ocontract.contract_path(net.tensors, net.labels, [(0, 1)], net.out_label).reshape(-1)
+    for blocks in ("1", "1000000"):
+        os.environ["TNC_GEMM_CONFIG"] = str(config)
+        os.environ["TNC_SPLITK_BLOCKS"] = blocks
+        try:
+            c = _contraction(net, [(0, 1)], open_qubits=list(range(net.n_qubits)),
+                             closed_bits=[0], precision=prec)
+        finally:
+            os.environ.pop("TNC_GEMM_CONFIG", None)
+            os.environ.pop("TNC_SPLITK_BLOCKS", None)
+        g = [l for l in c.launches() if l.kind == 1]
+        assert len(g) == 1 and g[0].m == 1 << free_a and g[0].config == config
+        c.contract()
+        err = metrics.rel_error(c.amps.cpu().numpy()[0], ref)
+        c.close()
+        log(f"{name} m-fast A, M {1 << free_a}, config {config}, split-K {g[0].k_splits}: rel err {err:.3e}")
+        assert err <= tol
