@@ -393,6 +393,9 @@ def main():
     ap.add_argument("--precision", default="c64", choices=["c64", "bf16x3", "fp16x3"])
     ap.add_argument("--perturbed", type=int, default=1,
                     help="sliced, c64: also time the workload with holes drilled (1/0)")
+    ap.add_argument("--reuse", action="store_true",
+                    help="large: the head-reuse mode (subtasks of 4 consecutive slices; use "
+                         "--batch 4)")
     ap.add_argument("--head-reuse", type=int, default=1,
                     help="sliced, c64: also time the head-reuse plan of the same workload (1/0)")
     ap.add_argument("--split-compare", type=int, default=1,
@@ -425,7 +428,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     t_plan = time.perf_counter()
-    w = config_workload(args.workload, mode="samples" if args.workload == "small" else "default")
+    mode = "samples" if args.workload == "small" else ("reuse" if args.reuse else "default")
+    w = config_workload(args.workload, mode=mode)
     t_plan = time.perf_counter() - t_plan
     print(f"[bench] planned {args.workload}: {len(w.plan.path)} steps, "
           f"{len(w.plan.sliced_labels)} sliced bonds, {len(w.slice_ids)} slices, "
@@ -522,7 +526,8 @@ def main():
                           "(1024 slices), largest intermediate <= 2^26, 12 open qubits x 1 group "
                           "(4096 amplitudes), 1000 samples",
                 "small": "3x4 grid, 8 cycles, all 12 qubits open, 1000 samples",
-                "large": "6x9 grid minus (0,4), 20 cycles, 256-slice subset, 2^14 groups x 6 open",
+                "large": "6x9 grid minus (0,4), 20 cycles, 256-slice subset, 2^14 groups x 6 open"
+                         + (" (head reuse: 64 subtasks x 4 local slices)" if args.reuse else ""),
             }[args.workload],
             "slices": int(len(w.slice_ids)),
             "amplitudes": int(w.n_amplitudes),

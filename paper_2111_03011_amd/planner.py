@@ -471,6 +471,38 @@ def _reuse_candidate(net, base, path, open_qubits, closed_bits, max_log2, n_slic
     return Plan(path=path, sliced_labels=sliced, cost=cost, n_slices=1 << len(sliced))
 
 
+def order_for_reuse(net, plan: Plan, open_qubits, closed_bits, batch: int) -> Plan:
+    """Head reuse without extra slicing: of the plan's sliced labels, log2(batch) become
+    local labels on the low slice-id bits, chosen one at a time to minimise the work of the
+    steps that depend on them (every other slice-dependent step is then shared by a batch
+    of `batch` consecutive ids); the path and the sliced set are unchanged."""
+    n_loc = max(1, int(batch).bit_length() - 1)
+    sl = list(plan.sliced_labels)
+    deps = [set(x for x in lab if x in sl) for lab in net.labels]
+    sets = []
+    for i, j in plan.path:
+        deps[i] = deps[i] | deps[j]
+        sets.append(deps[i])
+    macs = [st[6] for st in plan.cost.steps]
+    local = []
+    for _ in range(min(n_loc, len(sl))):
+        best = None
+        for x in sl:
+            if x in local:
+                continue
+            chosen = set(local + [x])
+            w = sum(m for m, st in zip(macs, sets) if st & chosen)
+            if best is None or w < best[0]:
+                best = (w, x)
+        local.append(best[1])
+    order = local + [x for x in sl if x not in local]
+    sp = make_problem(net.labels, net.out_label, net.n_qubits, open_qubits, closed_bits, sliced=order)
+    leaf_loc = {k for k, l in enumerate(net.labels) if any(x in local for x in l)}
+    leaf_glob = {k for k, l in enumerate(net.labels) if any(x in sl and x not in local for x in l)}
+    cost = reuse_cost(sp, plan.path, leaf_loc, leaf_glob, batch)
+    return Plan(path=plan.path, sliced_labels=order, cost=cost, n_slices=plan.n_slices)
+
+
 def validate_path(n_tensors: int, pairs):
     """Check a path in the (i, j) -> i format (Appendix E) against n_tensors leaves: every
     pair names two distinct live tensors.  Returns the ids still alive at the end."""

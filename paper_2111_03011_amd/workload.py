@@ -9,7 +9,7 @@ import numpy as np
 import synth
 
 from .network import TensorNetwork, circuit_network
-from .planner import Plan, find_plan
+from .planner import Plan, find_plan, order_for_reuse
 
 
 @dataclass
@@ -89,7 +89,9 @@ _CACHE = {}
 
 def config_workload(name: str, mode: str = "default", trials: int | None = None) -> Workload:
     """name: small | sliced | large.  For small, mode 'amplitudes' (64 bitstrings, no open
-    qubit) or 'samples' (all 12 qubits open, one group).  For sliced, mode 'reuse' plans
+    qubit) or 'samples' (all 12 qubits open, one group).  For large, mode 'reuse' keeps the
+    plan's sliced bonds, puts the log2(reuse_batch) cheapest on the low id bits and draws
+    the slice subset as subtasks of reuse_batch consecutive ids.  For sliced, mode 'reuse' plans
     for head reuse (bound-driven global slices, cheap local ones on the low slice-id bits,
     steps above global labels once per batch of the configuration's reuse_batch), and mode
     'holes' drills the configuration's number of holes (chosen by choose_holes) into the
@@ -129,7 +131,16 @@ def _config_workload(name: str, mode: str, trials: int | None) -> Workload:
                      n_sliced=cfg.get("sliced_labels"), trials=trials, seed=cfg["path_seed"],
                      reuse_batch=cfg.get("reuse_batch", 1) if mode == "reuse" else 1)
     k = len(plan.sliced_labels)
-    if "slice_subset" in cfg:
+    if "slice_subset" in cfg and mode == "reuse":
+        # subtasks (Method): count / B random assignments of the global labels, each with all
+        # B values of the local labels, which sit on the low id bits
+        b = cfg["reuse_batch"]
+        plan = order_for_reuse(net, plan, open_q, closed, b)
+        n_loc = b.bit_length() - 1
+        sub = cfg["slice_subset"]
+        glob = synth.slice_subset(k - n_loc, sub["count"] // b, sub["seed"])
+        ids = [(int(g) << n_loc) | loc for g in glob for loc in range(b)]
+    elif "slice_subset" in cfg:
         sub = cfg["slice_subset"]
         ids = synth.slice_subset(k, sub["count"], sub["seed"])
     else:

@@ -45,3 +45,39 @@ def test_large_sparse_state_equals_single_groups():
         err = metrics.rel_error(amps[g], got)
         log(f"  group {g}: sparse state vs alone rel diff {err:.2e}")
         assert err <= 1e-5
+
+
+def test_large_head_reuse_equals_plain_plan():
+    """Head reuse on the 53-qubit share: the reuse mode keeps the 98 sliced bonds, puts the
+    two cheapest on the low slice-id bits and draws the subset as 64 subtasks x 4 local
+    slices; with batches of 4, the steps above the other 96 labels run once per subtask.
+    Its sparse state over 32 of those slices equals the plain plan's over the same slices
+    (ids translated to the plain label order), contracted one slice at a time."""
+    from paper_2111_03011_amd.contractor import Contraction
+    from paper_2111_03011_amd.workload import config_workload
+    plain = config_workload("large")
+    reuse = config_workload("large", mode="reuse")
+    assert sorted(reuse.plan.sliced_labels) == sorted(plain.plan.sliced_labels)
+    ids = [int(x) for x in reuse.slice_ids[:32]]
+    pos = [plain.plan.sliced_labels.index(x) for x in reuse.plan.sliced_labels]
+    plain_ids = [sum(((i >> b) & 1) << pos[b] for b in range(len(pos))) for i in ids]
+    r = Contraction(reuse.net, reuse.plan.path, sliced_labels=reuse.plan.sliced_labels,
+                    slice_ids=ids, open_qubits=reuse.open_qubits, closed_bits=reuse.closed_bits,
+                    max_batch_slices=4)
+    shared = sum(l.flops for l in r.launches() if l.invariant == 2)
+    r.contract()
+    got = r.amps.cpu().numpy().copy()
+    work = r.work()
+    r.close()
+    p = Contraction(plain.net, plain.plan.path, sliced_labels=plain.plan.sliced_labels,
+                    slice_ids=plain_ids, open_qubits=plain.open_qubits,
+                    closed_bits=plain.closed_bits, max_batch_slices=1)
+    p.contract()
+    ref = p.amps.cpu().numpy()
+    plain_work = p.work()
+    p.close()
+    err = metrics.rel_error(got, ref)
+    log(f"large head reuse: shared {shared:.3e} flops per batch, work {work:.3e} vs plain "
+        f"{plain_work:.3e}; rel diff {err:.3e}")
+    assert shared > 0 and work < 0.6 * plain_work
+    assert err <= 1e-5
