@@ -394,8 +394,8 @@ def main():
     ap.add_argument("--perturbed", type=int, default=1,
                     help="sliced, c64: also time the workload with holes drilled (1/0)")
     ap.add_argument("--reuse", action="store_true",
-                    help="large: the head-reuse mode (subtasks of 4 consecutive slices; use "
-                         "--batch 4)")
+                    help="large: the head-reuse mode (subtasks of 8 consecutive slices; use "
+                         "--batch 8)")
     ap.add_argument("--head-reuse", type=int, default=1,
                     help="sliced, c64: also time the head-reuse plan of the same workload (1/0)")
     ap.add_argument("--split-compare", type=int, default=1,
@@ -527,7 +527,7 @@ def main():
                           "(4096 amplitudes), 1000 samples",
                 "small": "3x4 grid, 8 cycles, all 12 qubits open, 1000 samples",
                 "large": "6x9 grid minus (0,4), 20 cycles, 256-slice subset, 2^14 groups x 6 open"
-                         + (" (head reuse: 64 subtasks x 4 local slices)" if args.reuse else ""),
+                         + (" (head reuse: 32 subtasks x 8 local slices)" if args.reuse else ""),
             }[args.workload],
             "slices": int(len(w.slice_ids)),
             "amplitudes": int(w.n_amplitudes),

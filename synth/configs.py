@@ -63,7 +63,7 @@ CONFIGS = {
         "slice_subset": {"count": 256, "seed": 5003},
         "path_seed": 5004,
         "plan_trials": 1,
-        "reuse_batch": 4,         # head-reuse mode: 64 subtasks x 4 local slices
+        "reuse_batch": 8,         # head-reuse mode: 32 subtasks x 8 local slices
     },
 }
 

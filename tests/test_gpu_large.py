@@ -49,8 +49,8 @@ def test_large_sparse_state_equals_single_groups():
 
 def test_large_head_reuse_equals_plain_plan():
     """Head reuse on the 53-qubit share: the reuse mode keeps the 98 sliced bonds, puts the
-    two cheapest on the low slice-id bits and draws the subset as 64 subtasks x 4 local
-    slices; with batches of 4, the steps above the other 96 labels run once per subtask.
+    log2(B) cheapest on the low slice-id bits and draws the subset as subtasks of B local
+    slices; with batches of B, the steps above the other labels run once per subtask.
     Its sparse state over 32 of those slices equals the plain plan's over the same slices
     (ids translated to the plain label order), contracted one slice at a time."""
     from paper_2111_03011_amd.contractor import Contraction
@@ -61,9 +61,11 @@ def test_large_head_reuse_equals_plain_plan():
     ids = [int(x) for x in reuse.slice_ids[:32]]
     pos = [plain.plan.sliced_labels.index(x) for x in reuse.plan.sliced_labels]
     plain_ids = [sum(((i >> b) & 1) << pos[b] for b in range(len(pos))) for i in ids]
+    import synth
+    b = synth.config("large")["reuse_batch"]
     r = Contraction(reuse.net, reuse.plan.path, sliced_labels=reuse.plan.sliced_labels,
                     slice_ids=ids, open_qubits=reuse.open_qubits, closed_bits=reuse.closed_bits,
-                    max_batch_slices=4)
+                    max_batch_slices=b)
     shared = sum(l.flops for l in r.launches() if l.invariant == 2)
     r.contract()
     got = r.amps.cpu().numpy().copy()
