@@ -83,3 +83,27 @@ def test_large_head_reuse_equals_plain_plan():
         f"{plain_work:.3e}; rel diff {err:.3e}")
     assert shared > 0 and work < 0.6 * plain_work
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("precision,tol", [(2, 1e-3), (1, 1e-5)])
+def test_large_head_reuse_split_precision(precision, tol):
+    """The split-precision forms on the 53-qubit share with head reuse, against the complex64
+    result of the same plan and slices (within each form's stated bound, 1 - F <= 1e-6)."""
+    import synth
+    from paper_2111_03011_amd.contractor import Contraction
+    from paper_2111_03011_amd.workload import config_workload
+    w = config_workload("large", mode="reuse")
+    b = synth.config("large")["reuse_batch"]
+    ids = [int(x) for x in w.slice_ids[:16]]
+    out = {}
+    for prec in (0, precision):
+        c = Contraction(w.net, w.plan.path, sliced_labels=w.plan.sliced_labels, slice_ids=ids,
+                        open_qubits=w.open_qubits, closed_bits=w.closed_bits,
+                        max_batch_slices=b, precision=prec)
+        c.contract()
+        out[prec] = c.amps.cpu().numpy().copy()
+        c.close()
+    err = metrics.rel_error(out[precision], out[0])
+    fid = metrics.fidelity(out[precision], out[0])
+    log(f"large head reuse, precision {precision}: rel diff {err:.3e}, 1-F {1 - fid:.3e}")
+    assert err <= tol and 1 - fid <= 1e-6
