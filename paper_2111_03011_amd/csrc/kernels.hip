@@ -728,11 +728,14 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
 
 typedef float f32x2v __attribute__((ext_vector_type(2)));
 
-// Fold per-lane maxima m >= 0 into amax[slice * step] with atomic maxima on the float bits
-// (non-negative floats order like their bits).  Every lane of the wave calls this; a lane
-// without an element passes slice = -1.  When the lanes with an element share one slice the
-// wave reduces first and issues one atomic.
+// Fold per-lane maxima m >= 0 into the slice's kAmaxSlots slots amax[slice * step + j] with
+// atomic maxima on the float bits (non-negative floats order like their bits); the slot is
+// the workgroup index modulo kAmaxSlots, which spreads the atomics of a large output over
+// many addresses, and readers take the maximum over the slots (amax_read).  Every lane of
+// the wave calls this; a lane without an element passes slice = -1.  When the lanes with an
+// element share one slice the wave reduces first and issues one atomic.
 __device__ __forceinline__ void amax_commit(float m, int64_t slice, uint32_t* amax, int step) {
+  amax += blockIdx.x & (kAmaxSlots - 1);
   int64_t s0 = slice;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -747,6 +750,17 @@ __device__ __forceinline__ void amax_commit(float m, int64_t slice, uint32_t* am
   } else if (slice >= 0 && m > 0.f) {
     atomicMax(amax + slice * step, __float_as_uint(m));
   }
+}
+
+// maximum over a slice's kAmaxSlots slots (lane j reads slot j; every lane gets the result)
+__device__ __forceinline__ uint32_t amax_read(const uint32_t* slots) {
+  uint32_t v = slots[threadIdx.x & (kAmaxSlots - 1)];
+#pragma unroll
+  for (int off = kAmaxSlots / 2; off > 0; off >>= 1) {
+    const uint32_t o = __shfl_xor(v, off);
+    v = v > o ? v : o;
+  }
+  return v;
 }
 
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
@@ -812,8 +826,8 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
       return e < -110 ? -110 : (e > 127 ? 127 : e);
     };
     auto pow2 = [](int k) { return __uint_as_float(uint32_t(127 + k) << 23); };
-    const int ea = expo(a.amax_a[t.sl * a.amax_a_step]);
-    const int eb = expo(a.amax_b[t.sl * a.amax_b_step]);
+    const int ea = expo(amax_read(a.amax_a + t.sl * a.amax_a_step));
+    const int eb = expo(amax_read(a.amax_b + t.sl * a.amax_b_step));
     sc_a = pow2(13 - ea);
     sc_b = pow2(13 - eb);
     us_a = pow2(ea - 13);
@@ -1009,12 +1023,13 @@ __global__ __launch_bounds__(kThreads) void k_absmax(const float2* X, int64_t el
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
-  if ((threadIdx.x & 63) == 0) atomicMax(out + s * out_step, __float_as_uint(m));
+  if ((threadIdx.x & 63) == 0)
+    atomicMax(out + s * out_step + (blockIdx.x & (kAmaxSlots - 1)), __float_as_uint(m));
 }
 
-__global__ __launch_bounds__(kThreads) void k_zero_u32(uint32_t* p, int64_t n, int step) {
+__global__ __launch_bounds__(kThreads) void k_zero_u32(uint32_t* p, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-  if (i < n) p[i * step] = 0u;
+  if (i < n) p[i] = 0u;
 }
 
 __global__ __launch_bounds__(kThreads) void k_reduce(ReduceArgs a) {
@@ -1502,15 +1517,15 @@ hipError_t launch_split_bf16(const float2* in, void* out, int64_t n, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_zero_u32(uint32_t* p, int64_t n, int step, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, p, n, step);
+hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, p, n);
   return hipGetLastError();
 }
 
 hipError_t launch_absmax(const float2* X, int64_t elems, int64_t slice_stride, int64_t copies,
                          uint32_t* out, int out_step, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(copies, kThreads)), dim3(kThreads), 0, s, out, copies,
-                     out_step);
+  hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(copies * out_step, kThreads)), dim3(kThreads), 0, s,
+                     out, copies * out_step);
   int64_t bx = (elems + 4 * kThreads - 1) / (4 * kThreads);
   bx = bx < 1 ? 1 : (bx > 1024 ? 1024 : bx);
   hipLaunchKernelGGL(k_absmax, dim3(unsigned(bx), unsigned(copies)), dim3(kThreads), 0, s, X, elems,

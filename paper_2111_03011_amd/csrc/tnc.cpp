@@ -511,7 +511,7 @@ struct Compiler {
     L.split_op = SPLIT_AMAX;
     L.inv = !T.dep;
     L.b_in0 = T.buf;
-    L.b_out = new_buf(8, false, T.per_slice());
+    L.b_out = new_buf(4 * kAmaxSlots, false, T.per_slice());
     L.n_elems = T.elems();
     L.bufs = {L.b_in0, L.b_out};
     L.info = tnc_step_info{K_SPLIT, L.inv, T.rows(), int64_t(1) << T.dense.size(), 0, 0, 0.0,
@@ -529,7 +529,7 @@ struct Compiler {
     L.split_op = SPLIT_ZERO;
     L.inv = inv;
     L.shared = !inv && !per_slice;
-    L.b_out = new_buf(8, false, per_slice);
+    L.b_out = new_buf(4 * kAmaxSlots, false, per_slice);
     L.bufs = {L.b_out};
     L.info = tnc_step_info{K_SPLIT, inv, 1, 1, 0, 0, 0.0, 8.0};
     account(L);
@@ -989,10 +989,10 @@ struct Exec {
         if (L.b_amax_a >= 0) {
           a.amax_a = reinterpret_cast<const uint32_t*>(ptr(L.b_amax_a));
           a.amax_b = reinterpret_cast<const uint32_t*>(ptr(L.b_amax_b));
-          a.amax_a_step = p.bufs[L.b_amax_a].per_slice ? 2 : 0;
-          a.amax_b_step = p.bufs[L.b_amax_b].per_slice ? 2 : 0;
+          a.amax_a_step = p.bufs[L.b_amax_a].per_slice ? kAmaxSlots : 0;
+          a.amax_b_step = p.bufs[L.b_amax_b].per_slice ? kAmaxSlots : 0;
           a.amax_c = reinterpret_cast<uint32_t*>(ptr(L.b_amax_c));
-          a.amax_c_step = p.bufs[L.b_amax_c].per_slice ? 2 : 0;
+          a.amax_c_step = p.bufs[L.b_amax_c].per_slice ? kAmaxSlots : 0;
         }
         a.partial = L.b_tmp >= 0 ? ptr(L.b_tmp) : nullptr;
         a.nb = nb;
@@ -1002,11 +1002,11 @@ struct Exec {
       case K_SPLIT: {
         const int64_t copies = plan_copies(L, nb);
         if (L.split_op == SPLIT_ZERO) {
-          err = launch_zero_u32(reinterpret_cast<uint32_t*>(ptr(L.b_out)), copies, 2, st);
+          err = launch_zero_u32(reinterpret_cast<uint32_t*>(ptr(L.b_out)), copies * kAmaxSlots, st);
         } else if (L.split_op == SPLIT_AMAX) {
           const int64_t sstride = p.bufs[L.b_in0].per_slice ? int64_t(p.bufs[L.b_in0].elems) : 0;
           err = launch_absmax(ptr(L.b_in0), L.n_elems, sstride, copies,
-                              reinterpret_cast<uint32_t*>(ptr(L.b_out)), 2, st);
+                              reinterpret_cast<uint32_t*>(ptr(L.b_out)), kAmaxSlots, st);
         } else {
           err = launch_split_bf16(ptr(L.b_in0), ptr(L.b_out), L.n_elems * copies, st);
         }
@@ -1019,7 +1019,7 @@ struct Exec {
         a.elems = L.rd.elems * nb;
         if (L.b_amax_c >= 0) {
           a.amax = reinterpret_cast<uint32_t*>(ptr(L.b_amax_c));
-          a.amax_step = p.bufs[L.b_amax_c].per_slice ? 2 : 0;
+          a.amax_step = p.bufs[L.b_amax_c].per_slice ? kAmaxSlots : 0;
         }
         err = launch_reduce(a, st);
         break;

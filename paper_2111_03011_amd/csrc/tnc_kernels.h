@@ -70,14 +70,15 @@ struct GemmArgs {
   const int32_t* stk;
   const int32_t* perm;
   int group_m;                // tiles are numbered in groups of group_m tile rows (L2 reuse)
-  // precision 3 (FP16 hi+lo): largest |re|, |im| of A and B per slice, as float bits, at
-  // amax_a[slice * amax_a_step] (step 0: operand shared by every slice)
+  // precision 3 (FP16 hi+lo): largest |re|, |im| of A and B per slice, as float bits, the
+  // maximum over the kAmaxSlots slots amax_a[slice * amax_a_step + j] (step 0: operand
+  // shared by every slice, else kAmaxSlots)
   const uint32_t* amax_a;
   const uint32_t* amax_b;
   int amax_a_step, amax_b_step;
   // precision 3: when set and the launch writes C itself (k_splits == 1), the largest
-  // |re|, |im| of C per slice is folded into amax_c[slice * amax_c_step] with an atomic
-  // maximum (the slot is zero before the launch)
+  // |re|, |im| of C per slice is folded into the slots amax_c[slice * amax_c_step + j] with
+  // atomic maxima (the slots are zero before the launch)
   uint32_t* amax_c;
   int amax_c_step;
 };
@@ -137,7 +138,8 @@ hipError_t launch_stream(const StreamArgs& a, hipStream_t s);
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t s);
 // out[s * out_step] = bits of max |re|, |im| over the `elems` elements of copy s of X
 // (copies at X + s * slice_stride), for s < copies
-hipError_t launch_zero_u32(uint32_t* p, int64_t n, int step, hipStream_t s);
+constexpr int kAmaxSlots = 64;   // slots per slice of a largest-component record
+hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_absmax(const float2* X, int64_t elems, int64_t slice_stride, int64_t copies,
                          uint32_t* out, int out_step, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
