@@ -64,6 +64,55 @@ def greedy_path(labels: list[tuple], seed: int | None = None) -> list[tuple[int,
     return path
 
 
+def random_greedy_path(labels: list[tuple], seed: int, trials: int = 20,
+                       temperature: float = 0.5) -> list[tuple[int, int]]:
+    """The greedy order of greedy_path with its cost perturbed: each candidate pair's
+    memory growth gets temperature x (standard Gumbel noise) added, one pass per trial
+    (seeded), and the pass with the smallest largest intermediate (then the fewest
+    multiply-adds) is kept.  Any order gives the same contraction result; this one only
+    keeps large networks within memory."""
+    import math
+    rng = np.random.default_rng(seed)
+    best, best_key = None, None
+    for _ in range(trials):
+        labs = {i: set(l) for i, l in enumerate(labels)}
+        where: dict = {}
+        for i, l in labs.items():
+            for x in l:
+                where.setdefault(x, set()).add(i)
+        path, peak, macs = [], 0, 0.0
+        while True:
+            pick, pick_key = None, None
+            for x, holders in where.items():
+                if len(holders) != 2:
+                    continue
+                i, j = sorted(holders)
+                out = labs[i] ^ labs[j]
+                cost = _size(out) - _size(labs[i]) - _size(labs[j])
+                cost -= temperature * math.log(-math.log(rng.random()))
+                if pick_key is None or cost < pick_key:
+                    pick, pick_key = (i, j), cost
+            if pick is None:
+                break
+            i, j = pick
+            out = labs[i] ^ labs[j]
+            macs += _size(labs[i] | labs[j])
+            for x in labs[j]:
+                where[x].discard(j)
+                if x in out:
+                    where[x].add(i)
+            for x in labs[i] & labs[j]:
+                where.pop(x, None)
+            labs[i] = out
+            del labs[j]
+            peak = max(peak, len(out))
+            path.append((i, j))
+        key = (peak, macs)
+        if best_key is None or key < best_key:
+            best, best_key = path, key
+    return best
+
+
 def time_ordered_path(n_tensors: int) -> list[tuple[int, int]]:
     """Absorb the tensors one by one into tensor 0, in creation order."""
     return [(0, j) for j in range(1, n_tensors)]
@@ -136,6 +185,8 @@ def sparse_amplitudes(circuit: dict, open_qubits, closed_bits, sliced_bonds=(),
                         cached_path = greedy_path(labels)
                     elif path == "time":
                         cached_path = time_ordered_path(len(tensors))
+                    elif path.startswith("random-greedy:"):
+                        cached_path = random_greedy_path(labels, int(path.split(":")[1]))
                     else:
                         raise ValueError(path)
                 p = cached_path

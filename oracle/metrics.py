@@ -36,12 +36,6 @@ def linear_xeb(n: int, probs_of_samples) -> float:
     return float((2.0 ** n) * p.mean() - 1.0)
 
 
-def sparse_norm(amps) -> float:
-    """Results: N = sum_i sum_mu |psi_hat_i^mu|^2."""
-    a = np.asarray(amps, dtype=np.complex128)
-    return float(np.sum(np.abs(a) ** 2))
-
-
 def full_space_normalisation(n: int, L: int, l: int, norm: float) -> float:
     """Results: the 2^n-space normalisation estimated from the sparse norm; for n = 53
     and L*l = 2^26 this is 2^27 * N."""

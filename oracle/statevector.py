@@ -17,13 +17,96 @@ inserting E = |0><0| on each, right before the gate; since fSim|00> = |00>, the 
 gate with both inputs projected is |00><00|, so the simulator applies the projector
 |0><0| to both qubits in place of the gate.  The result is the unnormalised approximate
 state psi_hat of the perturbed network.
+
+The gate arithmetic has two interchangeable backends with the same pins: "numpy"
+(tensordot per gate, new arrays) and "c" (sv.c: the same updates as in-place loops over
+the amplitudes on every host core, for states of up to 30 qubits = 16 GiB).
 """
 
 from __future__ import annotations
 
+import ctypes
+import os
+import subprocess
+
 import numpy as np
 
 from .gates import ONEQ, fsim_tensor
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SV_SRC = os.path.join(_HERE, "sv.c")
+_SV_LIB = os.path.join(_HERE, "libsv.so")
+_sv = None
+
+
+def build_c(force: bool = False) -> str:
+    """Compile sv.c into libsv.so next to it (gcc, OpenMP) unless it is up to date."""
+    if force or not os.path.exists(_SV_LIB) or os.path.getmtime(_SV_LIB) < os.path.getmtime(_SV_SRC):
+        tmp = _SV_LIB + f".tmp{os.getpid()}"
+        subprocess.run(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SV_SRC], check=True)
+        os.replace(tmp, _SV_LIB)
+    return _SV_LIB
+
+
+def _c_lib():
+    global _sv
+    if _sv is None:
+        lib = ctypes.CDLL(build_c())
+        p, i = ctypes.c_void_p, ctypes.c_int
+        lib.sv_apply_1q.argtypes = [p, i, i, p]
+        lib.sv_apply_2q.argtypes = [p, i, i, i, p]
+        lib.sv_project.argtypes = [p, i, i, i]
+        for f in (lib.sv_apply_1q, lib.sv_apply_2q, lib.sv_project):
+            f.restype = None
+        _sv = lib
+    return _sv
+
+
+class _CState:
+    """Flat complex128 state updated in place by sv.c."""
+
+    def __init__(self, n: int):
+        self.n = n
+        self.psi = np.zeros(1 << n, dtype=np.complex128)
+        self.psi[0] = 1.0
+        self.lib = _c_lib()
+
+    def _ptr(self):
+        return self.psi.ctypes.data_as(ctypes.c_void_p)
+
+    def apply_1q(self, u: np.ndarray, q: int) -> None:
+        m = np.ascontiguousarray(u, dtype=np.complex128)
+        self.lib.sv_apply_1q(self._ptr(), self.n, q, m.ctypes.data_as(ctypes.c_void_p))
+
+    def apply_2q(self, g: np.ndarray, qa: int, qb: int) -> None:
+        m = np.ascontiguousarray(g, dtype=np.complex128).reshape(-1)
+        self.lib.sv_apply_2q(self._ptr(), self.n, qa, qb, m.ctypes.data_as(ctypes.c_void_p))
+
+    def project(self, q: int, v: int) -> None:
+        self.lib.sv_project(self._ptr(), self.n, q, int(v))
+
+    def flat(self) -> np.ndarray:
+        return self.psi
+
+
+class _NumpyState:
+    """State of shape (2,)*n updated by the tensordot functions below."""
+
+    def __init__(self, n: int):
+        self.psi = np.zeros((2,) * n, dtype=np.complex128)
+        self.psi[(0,) * n] = 1.0
+
+    def apply_1q(self, u, q):
+        self.psi = apply_1q(self.psi, u, q)
+
+    def apply_2q(self, g, qa, qb):
+        self.psi = apply_2q(self.psi, g, qa, qb)
+
+    def project(self, q, v):
+        self.psi = project(self.psi, q, v)
+
+    def flat(self):
+        return self.psi.reshape(-1)
 
 
 def apply_1q(psi: np.ndarray, u: np.ndarray, q: int) -> np.ndarray:
@@ -43,36 +126,36 @@ def project(psi: np.ndarray, q: int, v: int) -> np.ndarray:
     return apply_1q(psi, p, q)
 
 
-def simulate(circuit: dict, projectors: dict | None = None) -> np.ndarray:
+def simulate(circuit: dict, projectors: dict | None = None, backend: str = "numpy") -> np.ndarray:
     """Final state |psi> = U|0^n> (flattened, length 2^n), optionally one slice of it."""
     n = circuit["n_qubits"]
     projectors = dict(projectors or {})
-    psi = np.zeros((2,) * n, dtype=np.complex128)
-    psi[(0,) * n] = 1.0
+    if backend == "numpy":
+        st = _NumpyState(n)
+    elif backend == "c":
+        st = _CState(n)
+    else:
+        raise ValueError(f"unknown backend {backend!r}")
     g = fsim_tensor(circuit["fsim"]["theta"], circuit["fsim"]["phi"])
     holes = set(int(h) for h in circuit.get("holes", ()))
     n2q = [0] * n
     gate = 0
     for layer in circuit["layers"]:
         for q, name in enumerate(layer["oneq"]):
-            psi = apply_1q(psi, ONEQ[name], q)
+            st.apply_1q(ONEQ[name], q)
         for qa, qb in layer["couplers"]:
             if gate in holes:
-                psi = project(project(psi, qa, 0), qb, 0)
+                st.project(qa, 0)
+                st.project(qb, 0)
             else:
-                psi = apply_2q(psi, g, qa, qb)
+                st.apply_2q(g, qa, qb)
             gate += 1
             for q in (qa, qb):
                 key = (q, n2q[q])
                 if key in projectors:
-                    psi = project(psi, q, projectors[key])
+                    st.project(q, projectors[key])
                 n2q[q] += 1
-    return psi.reshape(-1)
-
-
-def amplitude_index(bits: int, n: int) -> int:
-    """State-vector index of a uint64 bitstring (bit n-1-q holds s_q): the same integer."""
-    return int(bits) & ((1 << n) - 1)
+    return st.flat()
 
 
 def sparse_from_state(psi: np.ndarray, n: int, open_qubits, closed_bits) -> np.ndarray:

@@ -49,7 +49,11 @@ def test_path_independence():
     t, l = net.sliced({})
     p = contract.greedy_path(l, seed=5)
     d = contract.sparse_amplitudes(c, list(range(n)), [0], path=p)
+    e = contract.sparse_amplitudes(c, list(range(n)), [0], path="random-greedy:7")
     assert np.allclose(a, b, atol=1e-13) and np.allclose(a, d, atol=1e-13)
+    assert np.allclose(a, e, atol=1e-13)
+    # the perturbed search is a different order, not a copy of the plain greedy one
+    assert contract.random_greedy_path(l, 7, trials=1, temperature=4.0) != contract.greedy_path(l)
 
 
 def test_slices_sum_to_unsliced_and_match_projected_state():

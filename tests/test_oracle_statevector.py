@@ -13,6 +13,8 @@ import synth
 from oracle import gates, statevector
 from oracle.metrics import collision_ratio
 
+BACKENDS = ("numpy", "c")
+
 
 def _circuit(n, layers, theta=math.pi / 2, phi=math.pi / 6):
     return {"n_qubits": n, "fsim": {"theta": theta, "phi": phi},
@@ -58,33 +60,64 @@ def _brute(c):
     (3, [(["sqrt_y", "sqrt_w", "sqrt_x"], [(0, 1)]), (["sqrt_x", "sqrt_y", "sqrt_w"], [(1, 2)]),
          (["sqrt_w", "sqrt_x", "sqrt_y"], [(0, 2)])]),
 ])
-def test_statevector_matches_brute_force(n, layers):
+@pytest.mark.parametrize("backend", BACKENDS)
+def test_statevector_matches_brute_force(n, layers, backend):
     c = _circuit(n, layers, theta=1.1, phi=0.7)
-    assert np.allclose(statevector.simulate(c), _brute(c), atol=1e-14)
+    assert np.allclose(statevector.simulate(c, backend=backend), _brute(c), atol=1e-14)
 
 
-def test_empty_circuit_is_all_zero_state():
+@pytest.mark.parametrize("backend", BACKENDS)
+def test_four_qubit_gates_on_every_pair_match_brute_force(backend):
+    """Two-qubit gates on every ordered pair position (adjacent, distant, the top and
+    bottom bits) and with a non-symmetric four-way tensor: a wrong bit position, operand
+    order or transposition in either backend changes the result."""
+    n = 4
+    layers = [(["sqrt_x", "sqrt_y", "sqrt_w", "sqrt_x"], [(0, 3), (1, 2)]),
+              (["sqrt_w", "sqrt_x", "sqrt_y", "sqrt_w"], [(0, 1), (2, 3)]),
+              (["sqrt_y", "sqrt_w", "sqrt_x", "sqrt_y"], [(1, 3)]),
+              (["sqrt_x", "sqrt_x", "sqrt_w", "sqrt_y"], [(0, 2)])]
+    c = _circuit(n, layers, theta=0.9, phi=1.3)
+    assert np.allclose(statevector.simulate(c, backend=backend), _brute(c), atol=1e-14)
+    # a general (non-symmetric, non-unitary) four-way tensor through the same primitive
+    rng = np.random.default_rng(3)
+    g = rng.normal(size=(2, 2, 2, 2)) + 1j * rng.normal(size=(2, 2, 2, 2))
+    psi0 = rng.normal(size=16) + 1j * rng.normal(size=16)
+    ref = _full_two_qubit(n, 1, 3, g.reshape(4, 4)) @ psi0
+    if backend == "numpy":
+        got = statevector.apply_2q(psi0.reshape((2,) * n), g, 1, 3).reshape(-1)
+    else:
+        st = statevector._CState(n)
+        st.psi[:] = psi0
+        st.apply_2q(g, 1, 3)
+        got = st.flat()
+    assert np.allclose(got, ref, atol=1e-13)
+
+
+@pytest.mark.parametrize("backend", BACKENDS)
+def test_empty_circuit_is_all_zero_state(backend):
     c = _circuit(4, [])
-    psi = statevector.simulate(c)
+    psi = statevector.simulate(c, backend=backend)
     assert psi[0] == 1 and np.count_nonzero(psi) == 1
 
 
-def test_norm_and_porter_thomas():
-    psi = statevector.simulate(synth.make_circuit(3, 4, 8, 1001))
+@pytest.mark.parametrize("backend", BACKENDS)
+def test_norm_and_porter_thomas(backend):
+    psi = statevector.simulate(synth.make_circuit(3, 4, 8, 1001), backend=backend)
     assert abs(np.sum(np.abs(psi) ** 2) - 1.0) < 1e-12
-    deep = statevector.simulate(synth.make_circuit(4, 4, 14, 11))
+    deep = statevector.simulate(synth.make_circuit(4, 4, 14, 11), backend=backend)
     # Porter-Thomas: 2^n sum p^2 -> 2 for deep random circuits
     assert abs(collision_ratio(np.abs(deep) ** 2) - 2.0) < 0.1
 
 
-def test_projector_slices_sum_to_state():
+@pytest.mark.parametrize("backend", BACKENDS)
+def test_projector_slices_sum_to_state(backend):
     c = synth.make_circuit(2, 3, 6, 5)
-    full = statevector.simulate(c)
+    full = statevector.simulate(c, backend=backend)
     bonds = [(0, 0), (2, 1), (4, 0)]
     acc = np.zeros_like(full)
     parts = []
     for vals in itertools.product((0, 1), repeat=len(bonds)):
-        part = statevector.simulate(c, projectors=dict(zip(bonds, vals)))
+        part = statevector.simulate(c, projectors=dict(zip(bonds, vals)), backend=backend)
         parts.append(part)
         acc += part
     assert np.allclose(acc, full, atol=1e-14)
@@ -104,7 +137,8 @@ def test_sparse_from_state_bit_order():
     assert list(out[0]) == [2, 6, 3, 7]
 
 
-def test_drilled_gate_is_the_input_projector_pair():
+@pytest.mark.parametrize("backend", BACKENDS)
+def test_drilled_gate_is_the_input_projector_pair(backend):
     """Hole drilling (Method): both input edges of a drilled fSim get E = |0><0|.  Eq. (1)
     has e0 as its first row and column, so fSim (P0 x P0) = (P0 x P0) fSim = |00><00| and
     the gate can be dropped; the simulator's drilled state equals the brute-force product
@@ -128,7 +162,7 @@ def test_drilled_gate_is_the_input_projector_pair():
         for qa, qb in couplers:
             u = _full_two_qubit(3, qa, qb, proj if gate == 1 else f) @ u
             gate += 1
-    assert np.allclose(statevector.simulate(c), u[:, 0], atol=1e-14)
+    assert np.allclose(statevector.simulate(c, backend=backend), u[:, 0], atol=1e-14)
 
 
 def test_drilled_fidelity_follows_two_to_the_minus_k():
