@@ -186,6 +186,19 @@ tnc_status tnc_sample_frugal(tnc_plan plan, void* d_workspace, uint64_t ws_bytes
                              const double* d_amps, uint64_t seed, int64_t n_samples, double m,
                              int32_t max_trials, uint64_t* h_bitstrings, void* hip_stream);
 
+/* tnc_sample for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation), and that would otherwise have
+ * to keep a plan's workspace only to sample.  Same arguments, draws and uniforms as
+ * tnc_sample, minus the workspace: the closed bits, open qubit ids, running sums and draws
+ * live in a static device buffer of 16 MiB inside the library (one per GPU, held until the
+ * process ends; nothing is allocated or freed).  A plan whose draws need more (L groups:
+ * 16 bytes per group; one group: 8 bytes per amplitude plus 8 per draw in flight) is
+ * rejected with TNC_E_INVALID.  Every call on one GPU shares that buffer and overwrites it:
+ * calls that overlap on one GPU (from several host threads or streams) race.  Synchronous
+ * on the stream. */
+tnc_status tnc_sample_noalloc(tnc_plan plan, const double* d_amps, uint64_t seed,
+                              int64_t n_samples, uint64_t* h_bitstrings, void* hip_stream);
+
 tnc_status tnc_plan_destroy(tnc_plan plan);
 tnc_status tnc_net_destroy(tnc_net net);
 

@@ -51,7 +51,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
     inc = ["-I", INCLUDE, "-I", CSRC]
     objs = []
-    for src in ("kernels.hip", "tnc.cpp"):
+    for src in ("kernels.hip", "noalloc.hip", "tnc.cpp"):
         obj = os.path.join(BUILD_DIR, src.replace(".", "_") + ".o")
         path = os.path.join(CSRC, src)
         if src.endswith(".hip"):

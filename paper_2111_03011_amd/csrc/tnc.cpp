@@ -32,6 +32,7 @@
 #include <utility>
 #include <vector>
 
+#include "tnc_internal.h"
 #include "tnc_kernels.h"
 
 using namespace tnc;
@@ -1667,6 +1668,64 @@ struct tnc_server_s {
 
 // ------------------------------------------------------------------------------------
 // C ABI
+// ---- sampling out of a caller-given scratch buffer (used by tnc_sample_noalloc) ----
+tnc_status tnc::report_error(tnc_status code, const char* msg) {
+  g_err = msg ? msg : "";
+  return code;
+}
+
+tnc_status tnc::plan_device(tnc_plan p, int* device) {
+  return guard([&] {
+    if (!p || !device) fail(TNC_E_INVALID, "null argument");
+    *device = p->device;
+  });
+}
+
+tnc_status tnc::sample_in_scratch(tnc_plan p, uint8_t* scratch, uint64_t cap, const double* amps,
+                                  uint64_t seed, int64_t n_samples, uint64_t* h_bits,
+                                  void* stream) {
+  return guard([&] {
+    if (!p || !scratch || !amps || (n_samples > 0 && !h_bits)) fail(TNC_E_INVALID, "null argument");
+    if (n_samples < 0) fail(TNC_E_INVALID, "negative sample count");
+    if (p->L > 1 && n_samples != p->L)
+      fail(TNC_E_INVALID, "with several groups, n_samples must equal the number of groups");
+    DeviceGuard dg(p->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint64_t L = uint64_t(p->L), l = uint64_t(1) << p->n_open;
+    // layout: closed bits | open qubit ids | running sums (one group only) | draws
+    const uint64_t o_open = align_up(L * 8), o_cum = o_open + align_up(4 * 64 + 4);
+    const uint64_t o_out = o_cum + (L == 1 ? align_up(l * 8) : 0);
+    const uint64_t need = o_out + 8 * (L > 1 ? L : 1);
+    if (need > cap)
+      fail(TNC_E_INVALID, "sampling this plan needs " + std::to_string(need) +
+                              " bytes of scratch, more than the " + std::to_string(cap) +
+                              " bytes of tnc_sample_noalloc's static buffer");
+    HIPCHK(hipMemcpyAsync(scratch, p->consts.data() + p->closed_off, L * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(scratch + o_open, p->consts.data() + p->open_off,
+                          4 * uint64_t(p->n_open + 1), hipMemcpyHostToDevice, st));
+    const uint64_t* closed = reinterpret_cast<const uint64_t*>(scratch);
+    const int32_t* openq = reinterpret_cast<const int32_t*>(scratch + o_open);
+    double* cum = reinterpret_cast<double*>(scratch + o_cum);
+    uint64_t* dout = reinterpret_cast<uint64_t*>(scratch + o_out);
+    if (n_samples == 0) {
+      HIPCHK(hipStreamSynchronize(st));
+      return;
+    }
+    // one group: the draws go out in chunks that fill the rest of the buffer (the draw
+    // index keeps counting across chunks, as in tnc_sample); several groups: one launch
+    const int64_t chunk = L > 1 ? int64_t(L) : int64_t((cap - o_out) / 8);
+    for (int64_t done = 0; done < n_samples; done += chunk) {
+      const int64_t c = std::min(chunk, n_samples - done);
+      const uint64_t seed_c = L > 1 ? seed : seed + uint64_t(done) * 0x9E3779B97F4A7C15ull;
+      hipError_t err = launch_sample(amps, p->L, p->n_open, closed, openq, p->n_qubits, seed_c, c,
+                                     cum, dout, st);
+      if (err != hipSuccess) fail(TNC_E_HIP, hipGetErrorString(err));
+      HIPCHK(hipMemcpyAsync(h_bits + done, dout, uint64_t(c) * 8, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+    }
+  });
+}
+
 extern "C" {
 
 const char* tnc_last_error(void) { return g_err.c_str(); }

@@ -34,7 +34,7 @@ EXPORTS = (
     "tnc_last_error", "tnc_net_create", "tnc_net_set_path", "tnc_net_set_slices",
     "tnc_net_set_slices_wide", "tnc_net_set_targets", "tnc_plan_create", "tnc_plan_workspace_bytes", "tnc_plan_stats", "tnc_plan_work",
     "tnc_contract", "tnc_contract_range", "tnc_sample", "tnc_sample_metropolis",
-    "tnc_sample_frugal", "tnc_plan_destroy", "tnc_net_destroy",
+    "tnc_sample_frugal", "tnc_sample_noalloc", "tnc_plan_destroy", "tnc_net_destroy",
     "tnc_plan_autotune", "tnc_plan_batch_slices", "tnc_plan_n_launches", "tnc_plan_launch_info", "tnc_plan_set_timing", "tnc_plan_timing",
     "tnc_plan_launch_timing",
     "tnc_server_create", "tnc_server_submit", "tnc_server_poll", "tnc_server_pending",
@@ -96,6 +96,7 @@ def lib() -> ctypes.CDLL:
             "tnc_sample": (_I32, [_P, _P, _U64, _P, _U64, _I64, _P, _P]),
             "tnc_sample_metropolis": (_I32, [_P, _P, _U64, _P, _U64, _I64, _I32, _P, _P]),
             "tnc_sample_frugal": (_I32, [_P, _P, _U64, _P, _U64, _I64, _D, _I32, _P, _P]),
+            "tnc_sample_noalloc": (_I32, [_P, _P, _U64, _I64, _P, _P]),
             "tnc_plan_destroy": (_I32, [_P]),
             "tnc_net_destroy": (_I32, [_P]),
             "tnc_plan_batch_slices": (_I32, [_P, ctypes.POINTER(_I32)]),
@@ -235,6 +236,13 @@ def tnc_sample_frugal(plan: int, ws: int, ws_bytes: int, amps: int, seed: int, n
     _check(lib().tnc_sample_frugal(plan, ws, ws_bytes, amps, seed & ((1 << 64) - 1), n_samples,
                                    float(m), max_trials, out.ctypes.data_as(ctypes.c_void_p),
                                    stream))
+    return out
+
+
+def tnc_sample_noalloc(plan: int, amps: int, seed: int, n_samples: int, stream: int) -> np.ndarray:
+    out = np.zeros(n_samples, dtype=np.uint64)
+    _check(lib().tnc_sample_noalloc(plan, amps, seed & ((1 << 64) - 1), n_samples,
+                                    out.ctypes.data_as(ctypes.c_void_p), stream))
     return out
 
 
