@@ -1,14 +1,20 @@
 """Benchmark: sliced sparse-state contraction on one MI355X.
 
-One step = the whole hot path over one batch of synthetic input: every slice of the
-network is contracted (leaf slicing, permutes, stream and GEMM steps), summed in FP64
-into psi_hat, its norm taken and 1000 bitstrings drawn.  Planning (circuit -> network ->
-path, slices) happens before the timed region.
+One step = the whole hot path over one pass of the workload's slice set, with the network,
+targets and slice ids resident in HBM: every slice is contracted (slice leaves, stream and
+GEMM steps, split-K reductions), the slices are summed in FP64 into psi_hat, its norm is
+taken and bitstrings are drawn (one per group, or 1000 from a single group).  Planning
+(circuit -> network -> path, slicing) happens before the timed region.
 
-Default workload: 5x6 grid, 14 cycles, 10 sliced bonds (1024 slices), largest
-intermediate <= 2^26 complex64, one group of 12 open qubits (4096 amplitudes).
+Default workload (the headline line): the 53-qubit share - 6x9 grid minus site (0,4),
+20 cycles, ABCDCDAB, fSim(pi/2, pi/6), 98 sliced bonds, a fixed 256-slice subset, 2^14
+groups x 6 open qubits (2^20 amplitudes), largest intermediate 2^30 complex64 (8 GiB),
+one slice per launch sequence.  `--workload sliced` runs the 5x6-grid, 14-cycle network
+(1024 slices, 4096 amplitudes) as the line instead; by default it runs as extra keys of
+the headline line together with the split-precision forms, head reuse and the perturbed
+network.
 
-Prints one JSON line (rank 0).
+Prints one JSON line.
 """
 
 from __future__ import annotations
@@ -26,44 +32,100 @@ if ROOT not in sys.path:
 PEAK_FP32_MFMA = 157.3e12
 PEAK_BF16_MFMA = 2.5e15
 PEAK_HBM = 8.0e12
+PREC = {"c64": 0, "fp16x3": 1, "bf16x3": 2}
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+WORKLOAD_TEXT = {
+    "large": "53-qubit share: 6x9 grid minus (0,4), 20 cycles, ABCDCDAB, fSim(pi/2, pi/6), "
+             "98 sliced bonds, fixed 256-slice subset, 2^14 groups x 6 open qubits "
+             "(2^20 amplitudes), one draw per group",
+    "sliced": "5x6 grid, 14 cycles, ABCDCDAB, fSim(pi/2, pi/6), 10 sliced bonds (1024 slices), "
+              "12 open qubits x 1 group (4096 amplitudes), 1000 samples",
+    "small": "3x4 grid, 8 cycles, all 12 qubits open, 1000 samples",
+}
 
 
-def cpu_baseline(w, flops_per_slice: float, budget_s: float = 20.0):
-    """The oracle, as it stands, on a bounded sample of the same workload: as many slices
-    as fit in about `budget_s` seconds (at least one), each contracted alone.  Returns the
-    baseline record and the oracle amplitudes of the sampled slices by slice index."""
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def host_info() -> dict:
+    """The CPU side of the box: cores, model, memory, BLAS library and its threads."""
     import numpy as np
-
-    from oracle import contract as ocontract
+    info = {"nproc": os.cpu_count(), "affinity_cores": len(os.sched_getaffinity(0))}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["cpu_model"] = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                info["ram_gib"] = round(int(line.split()[1]) / 2 ** 20, 1)
+                break
+    except OSError:
+        pass
+    try:
+        cfg = np.show_config(mode="dicts")
+        blas = cfg["Build Dependencies"]["blas"]
+        info["blas"] = f"{blas.get('name')} {blas.get('version')}"
+    except Exception:
+        info["blas"] = "unknown"
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
-    except Exception:  # pragma: no cover - informational only
-        threads = os.cpu_count()
-    done, t0 = 0, time.perf_counter()
-    refs = {}
-    while True:
-        idx = done % len(w.slice_ids)
-        sid = [int(w.slice_ids[idx])]
-        refs[idx] = ocontract.sparse_amplitudes(w.circuit, w.open_qubits, w.closed_bits,
-                                                sliced_bonds=w.sliced_bonds, slice_ids=sid)
-        done += 1
-        if time.perf_counter() - t0 > budget_s or done >= len(w.slice_ids):
-            break
-    dt = time.perf_counter() - t0
-    per_slice = dt / done
-    tflops = flops_per_slice / per_slice / 1e12
-    return {"value": tflops, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{done} slice(s) of the same workload, numpy complex128 tensordot "
-                      f"along the oracle's own greedy path, {per_slice:.2f} s per slice; value = "
-                      f"the library's algorithmic flops per slice / oracle seconds per slice",
-            "amplitudes_per_s": w.n_amplitudes / (per_slice * len(w.slice_ids))}, refs
+        pools = threadpool_info()
+        info["blas_threads"] = max([p.get("num_threads", 1) for p in pools] or [1])
+        info["threadpools"] = sorted({f"{p.get('internal_api')}:{p.get('num_threads')}" for p in pools})
+    except Exception:
+        info["blas_threads"] = None
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS"):
+        if k in os.environ:
+            info[k] = os.environ[k]
+    return info
+
+
+# -- stored oracle values (tests/golden, written by tests/golden/make_golden.py) -----------
+def load_sliced_golden():
+    """The oracle's 4096 exact amplitudes of the 5x6-grid workload (all 1024 slices)."""
+    import numpy as np
+    path = os.path.join(GOLDEN, "sliced_5x6_m14_full_sum.txt")
+    if not os.path.exists(path):
+        return None
+    v = np.loadtxt(path, comments="#")
+    return v[:, 0] + 1j * v[:, 1]
+
+
+def load_large_golden():
+    """The oracle's (slice position, group, 64 amplitudes) pairs of the 53-qubit share."""
+    import numpy as np
+    path = os.path.join(GOLDEN, "large_53q_m20_slice_group.txt")
+    if not os.path.exists(path):
+        return []
+    pairs, cur = [], None
+    for line in open(path):
+        if line.startswith("#"):
+            continue
+        if line.startswith("pair"):
+            f = line.split()
+            cur = {"pos": int(f[1]), "group": int(f[2]), "slice_id": int(f[3], 16),
+                   "closed": int(f[4], 16), "amps": []}
+            pairs.append(cur)
+        elif line.strip():
+            re, im = map(float, line.split())
+            cur["amps"].append(complex(re, im))
+    for p in pairs:
+        p["amps"] = np.asarray(p["amps"])
+    return pairs
 
 
 def rel_error(got, ref) -> float:
     import numpy as np
     got, ref = np.asarray(got).reshape(-1), np.asarray(ref).reshape(-1)
     return float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
+
+
+def max_err_over_rms(got, ref) -> float:
+    import numpy as np
+    got, ref = np.asarray(got).reshape(-1), np.asarray(ref).reshape(-1)
+    return float(np.max(np.abs(got - ref)) / max(np.sqrt(np.mean(np.abs(ref) ** 2)), 1e-300))
 
 
 def infidelity(got, ref) -> float:
@@ -73,65 +135,387 @@ def infidelity(got, ref) -> float:
     return float(1.0 - abs(np.vdot(ref, got)) ** 2 / den) if den > 0 else 0.0
 
 
-def slice_errors(c, refs) -> float:
-    """Largest normwise relative error of single-slice contractions against the oracle."""
-    worst = 0.0
-    for idx, ref in refs.items():
-        c.contract_range(idx, 1)
-        worst = max(worst, rel_error(c.amps.cpu().numpy(), ref))
-    return worst
+def percentiles(ms) -> dict:
+    import numpy as np
+    a = np.asarray(ms, dtype=float)
+    return {"median": float(np.median(a)), "p90": float(np.percentile(a, 90)),
+            "mean": float(a.mean()), "min": float(a.min()), "max": float(a.max())}
 
 
-def head_reuse(args, plain_amps, plain_amps_per_s) -> dict:
-    """The same 1024-slice workload planned for head reuse (Method, Appendix B.2): slices the
-    size bound needs are global, the other sliced bonds are local labels on the low slice-id
-    bits, and every step above global labels only runs once per batch of 64 slices.  Timed
-    over the same step (contract + sample) in complex64 and BF16x3; the amplitudes are
-    compared with the plain plan's complex64 sum (the same full sum over all slices)."""
-    import torch
+# -- contraction helpers ----------------------------------------------------------------
+def contraction(w, precision: str, batch: int):
     from paper_2111_03011_amd.contractor import Contraction
+    return Contraction(w.net, w.plan.path, sliced_labels=w.plan.sliced_labels,
+                       slice_ids=w.slice_ids, open_qubits=w.open_qubits,
+                       closed_bits=w.closed_bits, max_batch_slices=batch,
+                       precision=PREC[precision])
+
+
+def n_draws(w, args) -> int:
+    return args.samples if len(w.closed_bits) == 1 else len(w.closed_bits)
+
+
+def timed_steps(c, w, args, steps: int, warmup: int, tag: str):
+    """warmup + steps whole passes (contract all slices, FP64 sum, norm, draws); returns
+    the per-step milliseconds (each step ends synchronised: the draws are copied to the
+    host) and the last norm."""
+    import torch
+    nd = n_draws(w, args)
+    for i in range(warmup):
+        norm = c.contract(norm=True)
+        c.sample(2004, nd)
+        log(f"{tag} warmup {i}: norm {norm:.6e}")
+    ms = []
+    torch.cuda.synchronize()
+    for i in range(steps):
+        t0 = time.perf_counter()
+        norm = c.contract(norm=True)
+        c.sample(2004, nd)
+        ms.append(1e3 * (time.perf_counter() - t0))
+        log(f"{tag} step {i}: {ms[-1]:.1f} ms, norm {norm:.6e}")
+    return ms, norm
+
+
+def roofline(kt, precision: str, traffic):
+    """Dominant kernel by measured time: algorithmic work of its timed launches over their
+    summed durations (HIP events on the contraction stream)."""
+    dom = max(kt, key=lambda k: kt[k]["ms"])
+    d = kt[dom]
+    per = max(d["launches"], 1)
+    if dom == "gemm":
+        algo = d["flops"] / (d["ms"] * 1e-3) / 1e12
+        if precision == "c64":
+            # one v_mfma_f32_32x32x2f32 per complex k: matrix-core flops = algorithmic flops
+            r = {"kernel": "k_gemm (complex64 on v_mfma_f32_32x32x2f32)", "bound": "mfma",
+                 "achieved": algo, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
+                 "frac": algo / (PEAK_FP32_MFMA / 1e12)}
+        else:
+            # three products (hi*hi, hi*lo, lo*hi) per algorithmic flop; FP16 and BF16 share
+            # one matrix-core peak
+            mf = "f16" if precision == "fp16x3" else "bf16"
+            r = {"kernel": f"k_gemm_bf16x3 (v_mfma_f32_32x32x16_{mf}, 3 products)",
+                 "bound": "mfma", "achieved": 3 * algo, "peak": PEAK_BF16_MFMA / 1e12,
+                 "unit": "TFLOP/s", "frac": 3 * algo / (PEAK_BF16_MFMA / 1e12),
+                 "algorithmic_tflops": algo}
+    else:
+        gbs = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+        r = {"kernel": f"k_{dom}", "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM / 1e9,
+             "unit": "GB/s", "frac": gbs / (PEAK_HBM / 1e9)}
+    r.update({"traffic": traffic, "launches_timed": d["launches"],
+              "avg_launch_ms": d["ms"] / per,
+              "algorithmic_flops_per_launch": d["flops"] / per,
+              "algorithmic_bytes_per_launch": d["bytes"] / per})
+    return r
+
+
+KIND = {1: "gemm", 2: "stream", 3: "slice_leaves", 4: "slice_sum", 5: "splitk_reduce",
+        6: "split_operand"}
+TILE = {0: "128x64", 1: "128x16", 2: "64x32", 3: "128x128", 4: "128x32", 5: "128x8"}
+
+
+def step_classes(c) -> dict:
+    """Per launch of the plan (timed launches only): kind, shape, time, algorithmic
+    TFLOP/s and GB/s; summarised by class - GEMMs above the FP32 ridge (MFMA-bound by
+    their arithmetic intensity) and the rest (HBM-bound)."""
+    rows = []
+    infos = c.launches()
+    for i, (ms, n) in enumerate(c.launch_timing()):
+        if n == 0:
+            continue
+        s = infos[i]
+        t = ms / n
+        inten = s.flops / max(s.bytes, 1.0)
+        rows.append({"i": i, "kind": KIND.get(s.kind, str(s.kind)), "inv": s.invariant,
+                     "rows": s.rows, "m": s.m, "n": s.n, "k": s.k,
+                     "tile": TILE.get(s.config, "-") if s.kind == 1 else "-",
+                     "splits": s.k_splits, "row_mode": s.row_mode, "ms": t, "count": n,
+                     "tflops": s.flops / (t * 1e-3) / 1e12 if t > 0 else 0.0,
+                     "gbs": s.bytes / (t * 1e-3) / 1e9 if t > 0 else 0.0,
+                     "intensity": inten,
+                     "mfma_bound": s.kind == 1 and inten >= PEAK_FP32_MFMA / PEAK_HBM})
+    out = {}
+    for cls, sel in (("mfma_bound_gemm", lambda r: r["mfma_bound"]),
+                     ("hbm_bound", lambda r: not r["mfma_bound"])):
+        rs = [r for r in rows if sel(r)]
+        ms = sum(r["ms"] * r["count"] for r in rs)
+        fl = sum(r["tflops"] * r["ms"] * r["count"] for r in rs)
+        by = sum(r["gbs"] * r["ms"] * r["count"] for r in rs)
+        out[cls] = {"launch_types": len(rs), "ms": ms,
+                    "tflops": fl / ms if ms else 0.0, "gbs": by / ms if ms else 0.0}
+    tot = sum(v["ms"] for v in out.values()) or 1.0
+    for v in out.values():
+        v["time_share"] = v["ms"] / tot
+    out["mfma_bound_gemm"]["frac_of_fp32_peak"] = out["mfma_bound_gemm"]["tflops"] / (PEAK_FP32_MFMA / 1e12)
+    out["hbm_bound"]["frac_of_hbm_peak"] = out["hbm_bound"]["gbs"] / (PEAK_HBM / 1e9)
+    return out, rows
+
+
+def write_step_table(path: str, rows, title: str) -> None:
+    with open(path, "w") as f:
+        f.write(f"# {title}\n\n")
+        f.write("| launch | kind | inv | rows | M | N | K | tile | splits | row mode | ms | "
+                "TFLOP/s | GB/s | flop/B | bound |\n")
+        f.write("|---|---|---|---|---|---|---|---|---|---|---|---|---|---|---|\n")
+        for r in sorted(rows, key=lambda r: -r["ms"] * r["count"]):
+            f.write(f"| {r['i']} | {r['kind']} | {r['inv']} | {r['rows']} | {r['m']} | {r['n']} | "
+                    f"{r['k']} | {r['tile']} | {r['splits']} | {r['row_mode']} | {r['ms']:.4f} | "
+                    f"{r['tflops']:.1f} | {r['gbs']:.0f} | {r['intensity']:.1f} | "
+                    f"{'mfma' if r['mfma_bound'] else 'hbm'} |\n")
+
+
+# -- the CPU oracle, timed (the only place the benchmark runs oracle code) -----------------
+def cpu_baseline_sliced(w, flops_per_slice: float, budget_s: float = 20.0):
+    """The oracle, as it stands, on as many single slices of the workload as fit in about
+    `budget_s` seconds (at least one).  Returns the record and the oracle amplitudes of the
+    sampled slices by slice position."""
+    from oracle import contract as ocontract
+    done, t0, refs = 0, time.perf_counter(), {}
+    while True:
+        idx = done % len(w.slice_ids)
+        refs[idx] = ocontract.sparse_amplitudes(w.circuit, w.open_qubits, w.closed_bits,
+                                                sliced_bonds=w.sliced_bonds,
+                                                slice_ids=[int(w.slice_ids[idx])])
+        done += 1
+        if time.perf_counter() - t0 > budget_s or done >= len(w.slice_ids):
+            break
+    per_slice = (time.perf_counter() - t0) / done
+    hi = host_info()
+    return {"value": flops_per_slice / per_slice / 1e12, "unit": "TFLOP/s",
+            "cores": hi.get("blas_threads") or hi["nproc"], "kind": "oracle",
+            "sample": f"{done} slice(s) of the same workload, numpy complex128 tensordot along "
+                      f"the oracle's own greedy path, {per_slice:.2f} s per slice; value = the "
+                      "library's algorithmic flops per slice / oracle seconds per slice",
+            "amplitudes_per_s": w.n_amplitudes / (per_slice * len(w.slice_ids)),
+            "host": hi}, refs
+
+
+def cpu_baseline_large(w, flops_per_slice: float, pos: int = 0, group: int = 0):
+    """The oracle, as it stands, on one (slice, group) pair of the 53-qubit share: its own
+    network for that group (closed outputs fixed), the pair's slice fixed, its own seeded
+    random-greedy path (path search not timed), numpy complex128 tensordot.  Its measured
+    rate (oracle multiply-adds x 8 / seconds) prices the library's algorithmic flops per
+    slice: the per-slice time and the amplitudes/s are estimates."""
+    from oracle import contract as ocontract
+    from oracle import network as onetwork
+    circ, n = w.circuit, w.circuit["n_qubits"]
+    sigma, cb = int(w.slice_ids[pos]), int(w.closed_bits[group])
+    closed = [q for q in range(n) if q not in set(w.open_qubits)]
+    net = onetwork.build_network(circ, {q: (cb >> (n - 1 - q)) & 1 for q in closed})
+    fixed = {net.bond_label[tuple(b)]: (sigma >> bi) & 1 for bi, b in enumerate(w.sliced_bonds)}
+    tensors, labels = net.sliced(fixed)
+    path = ocontract.random_greedy_path(labels, 5101)
+    macs, ls = 0.0, [set(l) for l in labels]
+    for i, j in path:
+        macs += 2.0 ** len(ls[i] | ls[j])
+        ls[i] = ls[i] ^ ls[j]
+    t0 = time.perf_counter()
+    out = ocontract.contract_path(tensors, labels, path, [net.out_label[q] for q in w.open_qubits])
+    sec = time.perf_counter() - t0
+    rate = 8.0 * macs / sec
+    est = flops_per_slice / rate
+    hi = host_info()
+    return {"value": rate / 1e12, "unit": "TFLOP/s", "cores": hi.get("blas_threads") or hi["nproc"],
+            "kind": "oracle", "estimated": True,
+            "sample": f"one (slice, group) pair of the same workload (slice position {pos}, group "
+                      f"{group}): {8 * macs:.3e} oracle flops in {sec:.1f} s; value = that measured "
+                      "oracle rate, so one slice of the library's algorithmic flops would take the "
+                      f"oracle an estimated {est:.0f} s",
+            "oracle_pair_seconds": sec, "estimated_seconds_per_slice": est,
+            "estimated_amplitudes_per_s": w.n_amplitudes / (est * len(w.slice_ids)),
+            "host": hi}, {(pos, group): out.reshape(-1)}
+
+
+# -- extra keys ---------------------------------------------------------------------------
+def pair_errors(c, w, pairs) -> dict:
+    """Single (slice, group) pairs of the contraction against stored oracle values:
+    normwise relative error and max |error| / rms of the 64 amplitudes."""
+    worst, worst_max = 0.0, 0.0
+    for p in pairs:
+        assert int(w.slice_ids[p["pos"]]) == p["slice_id"], "stored pair names another slice"
+        assert int(w.closed_bits[p["group"]]) == p["closed"], "stored pair names another group"
+        c.contract_range(p["pos"], 1)
+        got = c.amps[p["group"]].cpu().numpy()
+        worst = max(worst, rel_error(got, p["amps"]))
+        worst_max = max(worst_max, max_err_over_rms(got, p["amps"]))
+    return {"pairs": len(pairs), "rel_err": worst, "max_err_over_rms": worst_max}
+
+
+def large_forms(args, c64_amps, c64_aps, pairs) -> dict:
+    """The split-precision forms of the 53-qubit share (same plan, slices, batch): one timed
+    whole pass each, amplitudes/s, difference from the complex64 sum, error against the
+    stored oracle pairs."""
+    import torch
     from paper_2111_03011_amd.workload import config_workload
-    w = config_workload("sliced", mode="reuse")
-    res = {"sliced_labels_local_then_global": [int(x) for x in w.plan.sliced_labels],
-           "peak_log2": w.plan.cost.peak_log2}
-    for name, prec in (("c64", 0), ("bf16x3", 2)):
-        c = Contraction(w.net, w.plan.path, sliced_labels=w.plan.sliced_labels,
-                        slice_ids=w.slice_ids, open_qubits=w.open_qubits,
-                        closed_bits=w.closed_bits, max_batch_slices=args.batch, precision=prec)
+    w = config_workload("large")
+    res = {}
+    for name in ("bf16x3", "fp16x3"):
+        c = contraction(w, name, 1)
+        if args.autotune:
+            c.autotune(reps=1)
+        c.contract_range(0, 1)
+        torch.cuda.synchronize()
+        ms, _ = timed_steps(c, w, args, 1, 0, f"large {name}")
+        amps = c.amps.cpu().numpy().copy()
+        r = {"amplitudes_per_s": w.n_amplitudes / (ms[0] * 1e-3), "ms_per_step": ms[0],
+             "ms_per_slice": ms[0] / len(w.slice_ids),
+             "tflops": c.work() / (ms[0] * 1e-3) / 1e12,
+             "speedup_vs_c64": (w.n_amplitudes / (ms[0] * 1e-3)) / c64_aps,
+             "rel_err_vs_c64_sum": rel_error(amps, c64_amps),
+             "infidelity_vs_c64_sum": infidelity(amps, c64_amps)}
+        if pairs:
+            r["vs_oracle_pairs"] = pair_errors(c, w, pairs)
+        c.close()
+        res[name] = r
+        log(f"large {name}: {r['amplitudes_per_s']:.0f} amplitudes/s "
+            f"({r['speedup_vs_c64']:.2f}x c64), rel diff vs c64 {r['rel_err_vs_c64_sum']:.2e}")
+    return res
+
+
+def large_reuse(args, c64_aps) -> dict:
+    """Head reuse on the 53-qubit share (Method; Appendix B.2): the plain plan's sliced
+    bonds, the three cheapest on the low slice-id bits, 256 slices as 32 subtasks x 8 local
+    values; every step above the 95 global labels runs once per batch of 8."""
+    import torch
+    from paper_2111_03011_amd.workload import config_workload
+    w = config_workload("large", mode="reuse")
+    res = {"subtasks": len(w.slice_ids) // 8, "local_slices": 8}
+    for name in ("c64", "bf16x3", "fp16x3"):
+        c = contraction(w, name, 8)
+        if args.autotune:
+            c.autotune(reps=1)
+        c.contract_range(0, 8)
+        torch.cuda.synchronize()
+        ms, _ = timed_steps(c, w, args, 1, 0, f"large reuse {name}")
+        aps = w.n_amplitudes / (ms[0] * 1e-3)
+        res[name] = {"amplitudes_per_s": aps, "ms_per_step": ms[0],
+                     "ms_per_slice": ms[0] / len(w.slice_ids),
+                     "executed_tflops": c.work() / (ms[0] * 1e-3) / 1e12,
+                     "speedup_vs_plain_c64": aps / c64_aps,
+                     "workspace_gb": c.ws_bytes / 1e9}
+        c.close()
+        log(f"large reuse {name}: {aps:.0f} amplitudes/s ({aps / c64_aps:.2f}x plain c64)")
+    return res
+
+
+def xeb_vs_exact(c, w, exact, n_samples: int, seed: int) -> float:
+    """Linear XEB (Appendix D) of n_samples draws from the contraction's amplitudes, scored
+    with the exact probabilities |psi(s)|^2 of the stored state-vector amplitudes."""
+    import numpy as np
+    bits = c.sample(seed, n_samples)
+    n, opn = w.circuit["n_qubits"], w.open_qubits
+    mu = np.zeros(len(bits), dtype=np.int64)
+    for t, q in enumerate(opn):
+        mu |= ((bits.astype(np.int64) >> (n - 1 - q)) & 1) << (len(opn) - 1 - t)
+    p = np.abs(exact[mu]) ** 2
+    return float(2.0 ** n * p.mean() - 1.0)
+
+
+def sliced_extra(args, refs=None) -> dict:
+    """The 5x6-grid, 14-cycle network (1024 slices, 4096 amplitudes) in every form: the
+    plain complex64 pass at 64 slices per launch (graph replays), BF16x3 and FP16x3 with
+    their amplitude error, infidelity and XEB change against the exact (FP64 state-vector)
+    amplitudes, the head-reuse plan and the perturbed network."""
+    import numpy as np
+    import torch
+    from paper_2111_03011_amd.workload import config_workload
+    w = config_workload("sliced")
+    exact = load_sliced_golden()
+    res = {"workload": WORKLOAD_TEXT["sliced"], "batch": 64, "peak_log2": w.plan.cost.peak_log2}
+    amps_by = {}
+    for name in ("c64", "bf16x3", "fp16x3"):
+        c = contraction(w, name, 64)
         if args.autotune:
             c.autotune(reps=2)
-        n_samp = args.samples if len(w.closed_bits) == 1 else len(w.closed_bits)
-        c.contract(norm=True)
-        c.sample(2004, n_samp)
-        steps = max(1, min(args.steps, 3))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            c.contract(norm=True)
-            c.sample(2004, n_samp)
-        torch.cuda.synchronize()
-        ms = 1e3 * (time.perf_counter() - t0) / steps
-        amps = c.amps.cpu().numpy().copy()
-        work = c.work()
-        shared = sum(l.flops for l in c.launches() if l.invariant == 2)
+        if name == "c64":
+            c.set_timing(True)
+            c.timing(reset=True)
+        ms, _ = timed_steps(c, w, args, 3, 1, f"sliced {name}")
+        r = {"ms_per_step": percentiles(ms), "amplitudes_per_s": w.n_amplitudes / (np.median(ms) * 1e-3),
+             "tflops": c.work() / (np.median(ms) * 1e-3) / 1e12}
+        if name == "c64":
+            r["roofline"] = roofline(c.timing(reset=True), "c64", None)
+            c.set_timing(False)
+        c.contract()
+        amps = c.amps.cpu().numpy()[0].copy()
+        amps_by[name] = amps
+        if exact is not None:
+            r["rel_err_vs_oracle_full_sum"] = rel_error(amps, exact)
+            r["max_err_over_rms_vs_oracle"] = max_err_over_rms(amps, exact)
+            r["infidelity_vs_oracle"] = infidelity(amps, exact)
+            r["xeb_1024_samples"] = xeb_vs_exact(c, w, exact, 1024, 3001)
+        if name != "c64":
+            r["speedup_vs_c64"] = r["amplitudes_per_s"] / res["c64"]["amplitudes_per_s"]
+            if exact is not None:
+                r["delta_xeb_vs_c64"] = r["xeb_1024_samples"] - res["c64"]["xeb_1024_samples"]
+        if exact is not None and name == "c64":
+            # draws from the exact amplitudes themselves (uploaded into the same buffer)
+            c.amps.copy_(torch.from_numpy(exact.reshape(1, -1)).to(c.amps.device))
+            res["xeb_1024_samples_exact_amplitudes"] = xeb_vs_exact(c, w, exact, 1024, 3001)
         c.close()
-        aps = w.n_amplitudes / (ms * 1e-3)
-        res[name] = {"amplitudes_per_s": aps, "ms_per_step": ms,
-                     "tflops": work / (ms * 1e-3) / 1e12, "flops_per_step": work,
-                     "shared_flops_per_batch": shared,
-                     "speedup_vs_plain_c64": aps / plain_amps_per_s,
-                     "rel_err_vs_plain_c64_sum": rel_error(amps, plain_amps),
-                     "infidelity_vs_plain_c64_sum": infidelity(amps, plain_amps)}
-        print(f"[bench] head reuse {name}: {aps:.0f} amplitudes/s "
-              f"({aps / plain_amps_per_s:.2f}x plain c64)", file=sys.stderr, flush=True)
+        res[name] = r
+        log(f"sliced {name}: {r['amplitudes_per_s']:.0f} amplitudes/s"
+            + (f", rel err vs oracle {r['rel_err_vs_oracle_full_sum']:.2e}" if exact is not None else ""))
+    if exact is not None:
+        for name in ("c64", "bf16x3", "fp16x3"):
+            res[name]["delta_xeb_vs_exact"] = (res[name]["xeb_1024_samples"]
+                                               - res["xeb_1024_samples_exact_amplitudes"])
+    plain_aps = res["c64"]["amplitudes_per_s"]
+    if args.head_reuse:
+        res["head_reuse"] = sliced_reuse(args, amps_by["c64"], plain_aps)
+    if args.perturbed:
+        res["perturbed_network"] = perturbed(args, amps_by["c64"] if exact is None else exact, plain_aps)
     return res
+
+
+def sliced_reuse(args, plain_amps, plain_aps) -> dict:
+    """The 1024-slice workload planned for head reuse: 4 global bonds (size bound) and 6
+    local ones on the low slice-id bits; steps above the global labels once per 64."""
+    import numpy as np
+    from paper_2111_03011_amd.workload import config_workload
+    w = config_workload("sliced", mode="reuse")
+    res = {"peak_log2": w.plan.cost.peak_log2}
+    for name in ("c64", "bf16x3"):
+        c = contraction(w, name, 64)
+        if args.autotune:
+            c.autotune(reps=2)
+        ms, _ = timed_steps(c, w, args, 3, 1, f"sliced reuse {name}")
+        amps = c.amps.cpu().numpy()[0].copy()
+        aps = w.n_amplitudes / (np.median(ms) * 1e-3)
+        res[name] = {"amplitudes_per_s": aps, "ms_per_step": float(np.median(ms)),
+                     "executed_tflops": c.work() / (np.median(ms) * 1e-3) / 1e12,
+                     "speedup_vs_plain_c64": aps / plain_aps,
+                     "rel_err_vs_plain_c64_sum": rel_error(amps, plain_amps)}
+        c.close()
+    return res
+
+
+def perturbed(args, exact_amps, plain_aps) -> dict:
+    """The 1024-slice workload with holes drilled into the circuit (Method): K = 2 broken
+    edges per hole, fidelity estimate 2^-K, measured against the exact amplitudes."""
+    import numpy as np
+    from paper_2111_03011_amd.workload import config_workload
+    w = config_workload("sliced", mode="holes")
+    c = contraction(w, "c64", 64)
+    if args.autotune:
+        c.autotune(reps=2)
+    ms, _ = timed_steps(c, w, args, 3, 1, "perturbed")
+    amps = c.amps.cpu().numpy()[0].copy()
+    work = c.work()
+    c.close()
+    K = 2 * len(w.circuit["holes"])
+    aps = w.n_amplitudes / (np.median(ms) * 1e-3)
+    return {"holes": [int(h) for h in w.circuit["holes"]], "broken_edges": K,
+            "fidelity_estimate": 2.0 ** -K,
+            "fidelity_vs_exact_4096_amplitudes": 1.0 - infidelity(amps, exact_amps),
+            "amplitudes_per_s": aps, "ms_per_step": float(np.median(ms)),
+            "flops_per_step": work, "speedup_vs_plain_c64": aps / plain_aps}
 
 
 def time_samplers(c, w, args) -> dict:
     """Wall time of the three in-group samplers on the contracted amplitudes (inverse CDF,
     the paper's Metropolis chains, frugal rejection sampling), one call each after a warm-up
     call; the bitstrings are copied to the host inside the timed call."""
-    n = args.samples if len(w.closed_bits) == 1 else len(w.closed_bits)
+    n = n_draws(w, args)
     runs = {"inverse_cdf": lambda: c.sample(2004, n),
             "metropolis_100_steps": lambda: c.sample_metropolis(2004, n, 100),
             "frugal_m10_64_trials": lambda: c.sample_frugal(2004, n, 10.0, 64)}
@@ -144,84 +528,10 @@ def time_samplers(c, w, args) -> dict:
     return res
 
 
-def perturbed(args, plain_amps, plain_amps_per_s) -> dict:
-    """The same workload with holes drilled into the circuit (Method): K = 2 per hole broken
-    edges, fidelity estimate 2^-K.  Timed over the same step; the fidelity of its 4096
-    amplitudes to the plain (exact) sum is reported beside the estimate."""
-    import torch
-    from paper_2111_03011_amd.contractor import Contraction
-    from paper_2111_03011_amd.workload import config_workload
-    w = config_workload("sliced", mode="holes")
-    c = Contraction(w.net, w.plan.path, sliced_labels=w.plan.sliced_labels,
-                    slice_ids=w.slice_ids, open_qubits=w.open_qubits, closed_bits=w.closed_bits,
-                    max_batch_slices=args.batch)
-    if args.autotune:
-        c.autotune(reps=2)
-    n_samp = args.samples if len(w.closed_bits) == 1 else len(w.closed_bits)
-    c.contract(norm=True)
-    c.sample(2004, n_samp)
-    steps = max(1, min(args.steps, 3))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        c.contract(norm=True)
-        c.sample(2004, n_samp)
-    torch.cuda.synchronize()
-    ms = 1e3 * (time.perf_counter() - t0) / steps
-    amps = c.amps.cpu().numpy().copy()
-    work = c.work()
-    c.close()
-    K = 2 * len(w.circuit["holes"])
-    aps = w.n_amplitudes / (ms * 1e-3)
-    print(f"[bench] perturbed network ({K} broken edges): {aps:.0f} amplitudes/s",
-          file=sys.stderr, flush=True)
-    return {"holes": [int(h) for h in w.circuit["holes"]], "broken_edges": K,
-            "fidelity_estimate": 2.0 ** -K,
-            "fidelity_vs_exact_4096_amplitudes": 1.0 - infidelity(amps, plain_amps),
-            "amplitudes_per_s": aps, "ms_per_step": ms, "flops_per_step": work,
-            "tflops": work / (ms * 1e-3) / 1e12,
-            "speedup_vs_plain_c64": aps / plain_amps_per_s}
-
-
-def split_compare(w, args, plain_amps, refs, stream) -> dict:
-    """The split-precision forms on the same workload: throughput over the same timed
-    step (contract + sample) and their amplitude error against the complex64 sum and,
-    slice by slice, against the oracle."""
-    import torch
-    from paper_2111_03011_amd.contractor import Contraction
-    res = {}
-    for name, prec in (("bf16x3", 2), ("fp16x3", 1)):
-        c = Contraction(w.net, w.plan.path, sliced_labels=w.plan.sliced_labels,
-                        slice_ids=w.slice_ids, open_qubits=w.open_qubits,
-                        closed_bits=w.closed_bits, max_batch_slices=args.batch, precision=prec)
-        if args.autotune:
-            c.autotune(reps=2)
-        n_samp = args.samples if len(w.closed_bits) == 1 else len(w.closed_bits)
-        c.contract(norm=True)
-        c.sample(2004, n_samp)
-        steps = max(1, min(args.steps, 3))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            c.contract(norm=True)
-            c.sample(2004, n_samp)
-        torch.cuda.synchronize()
-        ms = 1e3 * (time.perf_counter() - t0) / steps
-        amps = c.amps.cpu().numpy().copy()
-        r = {"amplitudes_per_s": w.n_amplitudes / (ms * 1e-3), "ms_per_step": ms,
-             "tflops": c.stats()[0] * len(w.slice_ids) / (ms * 1e-3) / 1e12,
-             "rel_err_vs_c64_sum": rel_error(amps, plain_amps),
-             "infidelity_vs_c64_sum": infidelity(amps, plain_amps)}
-        if refs:
-            r["rel_err_vs_oracle_slices"] = slice_errors(c, refs)
-        c.close()
-        res[name] = r
-        print(f"[bench] {name}: {r['amplitudes_per_s']:.0f} amplitudes/s, rel err vs c64 "
-              f"{r['rel_err_vs_c64_sum']:.2e}", file=sys.stderr, flush=True)
-    return res
-
-
-TRAFFIC_JSON = os.path.join(ROOT, "profiles", "k_gemm_sliced_5x6_m14_traffic.json")
+# -- HBM traffic of the dominant kernel (rocprofv3 counter passes, summarised offline) -----
+def traffic_json(workload: str, precision: str) -> str:
+    name = {"large": "large_53q_m20", "sliced": "sliced_5x6_m14", "small": "small_3x4_m8"}[workload]
+    return os.path.join(ROOT, "profiles", f"k_gemm_{name}_{precision}_traffic.json")
 
 
 def kernels_sha256():
@@ -230,23 +540,24 @@ def kernels_sha256():
     return hashlib.sha256(src).hexdigest()
 
 
-def measured_traffic(args):
-    """HBM bytes per k_gemm launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    passes (calibrated against a plain 1 GiB copy), or None when they do not describe the
-    kernel that runs now (different source, precision, workload or batch)."""
+def measured_traffic(args, batch: int):
+    """HBM bytes per launch of the dominant GEMM kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE passes (calibrated against a plain device copy), or None when
+    they do not describe the kernel that runs now (other source, precision, workload or
+    batch)."""
     try:
-        rec = json.load(open(TRAFFIC_JSON))
+        rec = json.load(open(traffic_json(args.workload, args.precision)))
         sha = kernels_sha256()
     except OSError:
         return None
     if (rec.get("kernels_hip_sha256") != sha or rec.get("workload") != args.workload or
-            rec.get("precision") != args.precision or rec.get("batch") != args.batch):
+            rec.get("precision") != args.precision or rec.get("batch") != batch):
         return None
     return rec["traffic_bytes_per_launch"]
 
 
-def write_traffic(args, fetch_csv, write_csv):
-    """Summarise two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE; one step of this
+def write_traffic(args, batch: int, fetch_csv, write_csv):
+    """Summarise two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE; a short run of this
     bench with --copy-calibration) into the traffic record bench.py reads: KiB per dispatch
     of the dominant GEMM kernel, each counter scaled by what it reads for the plain device
     copy of known size."""
@@ -272,8 +583,8 @@ def write_traffic(args, fetch_csv, write_csv):
     f_fac, w_fac = kib / f_copy, kib / w_copy
     rec = {
         "kernel": name.strip(":<"), "workload": args.workload, "precision": args.precision,
-        "batch": args.batch, "kernels_hip_sha256": kernels_sha256(),
-        "dispatches": [n_f, n_w],
+        "batch": batch, "kernels_hip_sha256": kernels_sha256(),
+        "slices_profiled": args.max_slices or "all", "dispatches": [n_f, n_w],
         "fetch_kib_per_launch_raw": round(f_kib, 2), "write_kib_per_launch_raw": round(w_kib, 2),
         "copy_calibration": {"bytes": args.copy_calibration, "fetch_kib": f_copy,
                              "write_kib": w_copy, "fetch_factor": round(f_fac, 4),
@@ -282,7 +593,7 @@ def write_traffic(args, fetch_csv, write_csv):
         "write_bytes_per_launch": round(w_kib * w_fac * 1024.0),
     }
     rec["traffic_bytes_per_launch"] = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
-    with open(TRAFFIC_JSON, "w") as fh:
+    with open(traffic_json(args.workload, args.precision), "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))
 
@@ -373,45 +684,50 @@ def serving_main(args):
     print(json.dumps(out), flush=True)
 
 
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="sliced", choices=["sliced", "small", "large", "serving"])
-    ap.add_argument("--requests", type=int, default=120, help="serving: requests in the stream")
+    ap.add_argument("--workload", default="large", choices=["large", "sliced", "small", "serving"])
+    ap.add_argument("--precision", default="c64", choices=["c64", "bf16x3", "fp16x3"])
+    ap.add_argument("--batch", type=int, default=0,
+                    help="slices per launch sequence (0 = the workload's own: 1 for large, "
+                         "8 for large --reuse, 64 for sliced)")
+    ap.add_argument("--reuse", action="store_true",
+                    help="large: the head-reuse mode (32 subtasks x 8 local slices)")
+    ap.add_argument("--samples", type=int, default=1000)
+    ap.add_argument("--autotune", type=int, default=1, help="time tile choices per GEMM first (1/0)")
+    ap.add_argument("--extras", type=int, default=1,
+                    help="large, c64: also the split-precision forms and head reuse of the same "
+                         "share, and the 5x6-grid network in every form (1/0)")
+    ap.add_argument("--head-reuse", type=int, default=1, help="5x6 network: also the reuse plan")
+    ap.add_argument("--perturbed", type=int, default=1, help="5x6 network: also the drilled one")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--step-table", metavar="PATH", help="write the per-launch timing table")
+    ap.add_argument("--max-slices", type=int, default=0,
+                    help="profiling runs only: contract the first N slices of the subset")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="run one plain device copy of BYTES before the timed region (a known "
+                         "reference for HBM traffic counters)")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE counter files of a run "
+                         "with --copy-calibration into the traffic record, then exit")
+    ap.add_argument("--requests", type=int, default=400, help="serving: requests in the stream")
     ap.add_argument("--templates", type=int, default=16, help="serving: distinct request templates")
     ap.add_argument("--slots", type=int, default=8, help="serving: concurrent requests")
     ap.add_argument("--arena-gb", type=int, default=64, help="serving: device arena")
     ap.add_argument("--serving-timeout", type=float, default=150.0)
     ap.add_argument("--serving-batch", type=int, default=0,
                     help="serving: slices per launch sequence (0 = chosen per request)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--samples", type=int, default=1000)
-    ap.add_argument("--batch", type=int, default=64, help="slices per launch (hipGraph per batch)")
-    ap.add_argument("--autotune", type=int, default=1, help="time tile choices per GEMM first (1/0)")
-    ap.add_argument("--precision", default="c64", choices=["c64", "bf16x3", "fp16x3"])
-    ap.add_argument("--perturbed", type=int, default=1,
-                    help="sliced, c64: also time the workload with holes drilled (1/0)")
-    ap.add_argument("--reuse", action="store_true",
-                    help="large: the head-reuse mode (subtasks of 8 consecutive slices; use "
-                         "--batch 8)")
-    ap.add_argument("--head-reuse", type=int, default=1,
-                    help="sliced, c64: also time the head-reuse plan of the same workload (1/0)")
-    ap.add_argument("--split-compare", type=int, default=1,
-                    help="sliced, c64: also time the split-precision forms and report their "
-                         "amplitude errors (1/0)")
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
-                    help="run one plain device copy of BYTES before the timed region (a known "
-                         "reference for HBM traffic counters)")
-    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE counter files of one step "
-                         "(run with --copy-calibration) into the traffic record, then exit")
     args = ap.parse_args()
+    batch = args.batch or {"large": 8 if args.reuse else 1, "sliced": 64, "small": 1}.get(args.workload, 1)
     if args.write_traffic:
         if not args.copy_calibration:
             sys.exit("--write-traffic needs the --copy-calibration size the passes used")
-        return write_traffic(args, *args.write_traffic)
+        return write_traffic(args, batch, *args.write_traffic)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); slices would shard "
               "across GPUs as independent blocks, which this program does not launch.",
@@ -420,33 +736,26 @@ def main():
     if args.workload == "serving":
         return serving_main(args)
 
+    import dataclasses
+
     import numpy as np
     import torch
 
-    from paper_2111_03011_amd.contractor import Contraction
     from paper_2111_03011_amd.workload import config_workload
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     t_plan = time.perf_counter()
     mode = "samples" if args.workload == "small" else ("reuse" if args.reuse else "default")
     w = config_workload(args.workload, mode=mode)
+    if args.max_slices:
+        w = dataclasses.replace(w, slice_ids=w.slice_ids[:args.max_slices])
     t_plan = time.perf_counter() - t_plan
-    print(f"[bench] planned {args.workload}: {len(w.plan.path)} steps, "
-          f"{len(w.plan.sliced_labels)} sliced bonds, {len(w.slice_ids)} slices, "
-          f"peak 2^{w.plan.cost.peak_log2:.0f}, {t_plan:.1f} s", file=sys.stderr, flush=True)
-    c = Contraction(w.net, w.plan.path, sliced_labels=w.plan.sliced_labels,
-                    slice_ids=w.slice_ids, open_qubits=w.open_qubits, closed_bits=w.closed_bits,
-                    max_batch_slices=args.batch,
-                    precision={"c64": 0, "fp16x3": 1, "bf16x3": 2}[args.precision])
+    log(f"planned {args.workload}: {len(w.plan.path)} steps, {len(w.plan.sliced_labels)} sliced "
+        f"bonds, {len(w.slice_ids)} slices, peak 2^{w.plan.cost.peak_log2:.0f}, {t_plan:.1f} s")
+    c = contraction(w, args.precision, batch)
     flops_slice, bytes_slice, n_steps = c.stats()
     flops_step = c.work()     # algorithmic flops one pass executes (shared steps once per batch)
-    stream = torch.cuda.current_stream()
-
-    def one_step():
-        norm = c.contract(norm=True)
-        bits = c.sample(2004, args.samples if len(w.closed_bits) == 1 else len(w.closed_bits))
-        return norm, bits
-
+    log(f"workspace {c.ws_bytes / 1e9:.1f} GB, {flops_step / 1e12:.1f} TFLOP per pass")
     if args.copy_calibration:
         src = torch.ones(args.copy_calibration, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -454,62 +763,34 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    tuned = c.autotune(reps=2) if args.autotune else 0
-    if args.autotune:
-        print(f"[bench] autotuner changed {tuned} GEMM launches", file=sys.stderr, flush=True)
+    tuned = c.autotune(reps=1 if args.workload == "large" else 2) if args.autotune else 0
+    log(f"autotuner changed {tuned} GEMM launches")
     for i in range(args.warmup):
-        norm, _ = one_step()
-        print(f"[bench] warmup {i}: norm {norm:.6e}", file=sys.stderr, flush=True)
+        norm = c.contract(norm=True)
+        c.sample(2004, n_draws(w, args))
+        log(f"warmup {i}: norm {norm:.6e}")
     c.set_timing(True)
     c.timing(reset=True)
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        norm, bits = one_step()
-        print(f"[bench] step {i}: norm {norm:.6e}", file=sys.stderr, flush=True)
-    e1.record(stream)
+    ms, norm = timed_steps(c, w, args, args.steps, 0, "timed")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = 1e3 * wall / args.steps
-    kt = c.timing(reset=True)
+    kt = c.timing(reset=False)
+    classes, table = step_classes(c)
+    c.timing(reset=True)
     c.set_timing(False)
-
-    # dominant kernel by measured time
-    dom = max(kt, key=lambda k: kt[k]["ms"])
-    d = kt[dom]
-    if dom in ("gemm",):
-        algo = d["flops"] / (d["ms"] * 1e-3) / 1e12
-        if args.precision == "c64":
-            # one v_mfma_f32_32x32x2f32 per complex k: matrix-core flops = algorithmic flops
-            roof = {"kernel": "k_gemm (complex64 on v_mfma_f32_32x32x2f32)", "bound": "mfma",
-                    "achieved": algo, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
-                    "frac": algo / (PEAK_FP32_MFMA / 1e12)}
-        else:
-            # three products (hi*hi, hi*lo, lo*hi) per algorithmic flop; the FP16 and BF16
-            # matrix instructions share one peak
-            mfma = "f16" if args.precision == "fp16x3" else "bf16"
-            roof = {"kernel": f"k_gemm_bf16x3 (v_mfma_f32_32x32x16_{mfma}, 3 products)",
-                    "bound": "mfma", "achieved": 3 * algo, "peak": PEAK_BF16_MFMA / 1e12,
-                    "unit": "TFLOP/s", "frac": 3 * algo / (PEAK_BF16_MFMA / 1e12),
-                    "algorithmic_tflops": algo}
-        roof.update({"traffic": measured_traffic(args), "launches_timed": d["launches"],
-                     "avg_launch_ms": d["ms"] / max(d["launches"], 1),
-                     "algorithmic_bytes_per_launch": d["bytes"] / max(d["launches"], 1)})
-    else:
-        achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
-        roof = {"kernel": f"k_{dom}", "bound": "hbm", "achieved": achieved,
-                "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": achieved / (PEAK_HBM / 1e9),
-                "traffic": None, "launches_timed": d["launches"],
-                "avg_launch_ms": d["ms"] / max(d["launches"], 1)}
+    if args.step_table:
+        write_step_table(args.step_table, table,
+                         f"per-launch times, {args.workload} workload, {args.precision}, batch {batch}")
+    roof = roofline(kt, args.precision, measured_traffic(args, batch))
     share = {k: v["ms"] for k, v in kt.items() if v["launches"]}
     tot = sum(share.values()) or 1.0
-    value = flops_step / (ms_step * 1e-3) / 1e12
+    aps = w.n_amplitudes / (ms_step * 1e-3)
     out = {
         "metric": "contraction TFLOP/s & MFMA util; amplitudes/s; p50/p99 request latency",
-        "value": value,
+        "value": flops_step / (ms_step * 1e-3) / 1e12,
         "unit": "TFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -521,45 +802,64 @@ def main():
         "dtype": args.precision,
         "data": "synthetic (seeded Sycamore-like circuit; random gates, no dataset)",
         "config": {
-            "workload": {
-                "sliced": "5x6 grid, 14 cycles, ABCDCDAB, fSim(pi/2, pi/6), 10 sliced bonds "
-                          "(1024 slices), largest intermediate <= 2^26, 12 open qubits x 1 group "
-                          "(4096 amplitudes), 1000 samples",
-                "small": "3x4 grid, 8 cycles, all 12 qubits open, 1000 samples",
-                "large": "6x9 grid minus (0,4), 20 cycles, 256-slice subset, 2^14 groups x 6 open"
-                         + (" (head reuse: 32 subtasks x 8 local slices)" if args.reuse else ""),
-            }[args.workload],
+            "workload": WORKLOAD_TEXT[args.workload]
+                        + (" (head reuse: 32 subtasks x 8 local slices)" if args.reuse else ""),
             "slices": int(len(w.slice_ids)),
             "amplitudes": int(w.n_amplitudes),
+            "largest_intermediate_log2": float(w.plan.cost.peak_log2),
+            "slices_per_launch": int(c.batch_slices),
             "path_steps": int(n_steps),
             "flops_per_slice": flops_slice,
             "flops_per_step": flops_step,
+            "workspace_gb": c.ws_bytes / 1e9,
         },
-        "amplitudes_per_s": w.n_amplitudes / (ms_step * 1e-3),
+        "step_ms": percentiles(ms),
+        "amplitudes_per_s": aps,
         "slices_per_s": len(w.slice_ids) / (ms_step * 1e-3),
+        "ms_per_slice": ms_step / len(w.slice_ids),
         "autotuned_launches": tuned,
         "mfma_util_gemm": roof["frac"] if roof["bound"] == "mfma" else None,
         "time_share": {k: v / tot for k, v in share.items()},
+        "step_classes": classes,
         "roofline": roof,
+        "samplers": time_samplers(c, w, args),
     }
-    out["samplers"] = time_samplers(c, w, args)
-    refs = {}
+    c.contract()
+    main_amps = c.amps.cpu().numpy().copy()
+    if args.workload == "large" and not args.max_slices:
+        pairs = load_large_golden()
+        if pairs:
+            out["vs_oracle_pairs"] = pair_errors(c, w, pairs)
+    if args.workload == "sliced" and not args.max_slices:
+        exact = load_sliced_golden()
+        if exact is not None:
+            out["rel_err_vs_oracle_full_sum"] = rel_error(main_amps[0], exact)
+            out["max_err_over_rms_vs_oracle"] = max_err_over_rms(main_amps[0], exact)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"], refs = cpu_baseline(w, flops_slice)
-        out["rel_err_vs_oracle_slices"] = slice_errors(c, refs)
-    extra = args.precision == "c64" and args.workload == "sliced"
-    if extra and (args.split_compare or args.head_reuse or args.perturbed):
-        c.contract()
-        plain = c.amps.cpu().numpy().copy()
-        c.close()
-        if args.split_compare:
-            out["split_precision"] = split_compare(w, args, plain, refs, stream)
+        if args.workload == "large":
+            out["cpu_baseline"], refs = cpu_baseline_large(w, flops_slice)
+            (pos, grp), ref = next(iter(refs.items()))
+            c.contract_range(pos, 1)
+            out["rel_err_vs_oracle_pair_live"] = rel_error(c.amps[grp].cpu().numpy(), ref)
+        else:
+            out["cpu_baseline"], refs = cpu_baseline_sliced(w, flops_slice)
+            worst = 0.0
+            for idx, ref in refs.items():
+                c.contract_range(idx, 1)
+                worst = max(worst, rel_error(c.amps.cpu().numpy(), ref))
+            out["rel_err_vs_oracle_slices"] = worst
+    c.close()
+    del c
+    torch.cuda.empty_cache()
+    if args.extras and args.workload == "large" and args.precision == "c64" and not args.reuse \
+            and not args.max_slices:
+        pairs = load_large_golden()
+        out["split_precision"] = large_forms(args, main_amps, aps, pairs)
+        torch.cuda.empty_cache()
         if args.head_reuse:
-            out["head_reuse"] = head_reuse(args, plain, out["amplitudes_per_s"])
-        if args.perturbed:
-            out["perturbed_network"] = perturbed(args, plain, out["amplitudes_per_s"])
-    else:
-        c.close()
+            out["head_reuse"] = large_reuse(args, aps)
+            torch.cuda.empty_cache()
+        out["sliced_5x6_m14"] = sliced_extra(args)
     print(json.dumps(out), flush=True)
 
 
