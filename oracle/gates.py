@@ -48,3 +48,12 @@ def fsim(theta: float, phi: float) -> np.ndarray:
 def fsim_tensor(theta: float, phi: float) -> np.ndarray:
     """fSim as a four-way tensor G[out_a, out_b, in_a, in_b] (q_a = lower qubit id)."""
     return fsim(theta, phi).reshape(2, 2, 2, 2)
+
+
+def gate_thetas(circuit: dict) -> list:
+    """The angle of every two-qubit gate in circuit order: the per-gate list
+    circuit["fsim"]["thetas"] when present (calibrated gates: angles near, not at, one
+    value), else the one angle circuit["fsim"]["theta"]."""
+    f = circuit["fsim"]
+    n2 = sum(len(l["couplers"]) for l in circuit["layers"])
+    return list(f["thetas"]) if "thetas" in f else [f["theta"]] * n2

@@ -21,7 +21,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .gates import ONEQ, fsim_tensor
+from .gates import ONEQ, fsim_tensor, gate_thetas
 
 
 class Network:
@@ -57,7 +57,8 @@ def build_network(circuit: dict, closed_values: dict | None = None) -> Network:
     """
     n = circuit["n_qubits"]
     closed_values = dict(closed_values or {})
-    g = fsim_tensor(circuit["fsim"]["theta"], circuit["fsim"]["phi"])
+    thetas = gate_thetas(circuit)
+    phi = circuit["fsim"]["phi"]
     holes = set(int(h) for h in circuit.get("holes", ()))
     p00 = np.zeros((2, 2, 2, 2), dtype=np.complex128)
     p00[0, 0, 0, 0] = 1.0
@@ -73,7 +74,8 @@ def build_network(circuit: dict, closed_values: dict | None = None) -> Network:
             net.add(ONEQ[name], [("w", q, k[q] + 1), ("w", q, k[q])])
             k[q] += 1
         for qa, qb in layer["couplers"]:
-            net.add(p00 if gate in holes else g, [("w", qa, k[qa] + 1), ("w", qb, k[qb] + 1),
+            g = p00 if gate in holes else fsim_tensor(thetas[gate], phi)
+            net.add(g, [("w", qa, k[qa] + 1), ("w", qb, k[qb] + 1),
                                                   ("w", qa, k[qa]), ("w", qb, k[qb])])
             gate += 1
             for q in (qa, qb):

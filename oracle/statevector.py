@@ -31,7 +31,7 @@ import subprocess
 
 import numpy as np
 
-from .gates import ONEQ, fsim_tensor
+from .gates import ONEQ, fsim_tensor, gate_thetas
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SV_SRC = os.path.join(_HERE, "sv.c")
@@ -136,7 +136,8 @@ def simulate(circuit: dict, projectors: dict | None = None, backend: str = "nump
         st = _CState(n)
     else:
         raise ValueError(f"unknown backend {backend!r}")
-    g = fsim_tensor(circuit["fsim"]["theta"], circuit["fsim"]["phi"])
+    thetas = gate_thetas(circuit)
+    phi = circuit["fsim"]["phi"]
     holes = set(int(h) for h in circuit.get("holes", ()))
     n2q = [0] * n
     gate = 0
@@ -148,7 +149,7 @@ def simulate(circuit: dict, projectors: dict | None = None, backend: str = "nump
                 st.project(qa, 0)
                 st.project(qb, 0)
             else:
-                st.apply_2q(g, qa, qb)
+                st.apply_2q(fsim_tensor(thetas[gate], phi), qa, qb)
             gate += 1
             for q in (qa, qb):
                 key = (q, n2q[q])

@@ -85,9 +85,13 @@ def circuit_network(circuit: dict, simplify: bool = True) -> TensorNetwork:
     and the outgoing wire starts again from |0>.  The perturbed network's amplitudes are
     those of psi_hat, with fidelity about 2^-K for K = 2 per hole."""
     n = circuit["n_qubits"]
-    g = _fsim4(circuit["fsim"]["theta"], circuit["fsim"]["phi"])
     holes = set(int(h) for h in circuit.get("holes", ()))
     n2 = sum(len(layer["couplers"]) for layer in circuit["layers"])
+    # one angle for every gate, or calibrated per-gate angles ("thetas", circuit order)
+    thetas = circuit["fsim"].get("thetas", [circuit["fsim"]["theta"]] * n2)
+    if len(thetas) != n2:
+        raise ValueError(f"fsim thetas lists {len(thetas)} angles for {n2} two-qubit gates")
+    phi = circuit["fsim"]["phi"]
     if any(h < 0 or h >= n2 for h in holes):
         raise ValueError(f"hole indices must name one of the {n2} two-qubit gates")
     gate = 0
@@ -113,6 +117,7 @@ def circuit_network(circuit: dict, simplify: bool = True) -> TensorNetwork:
                 pending[q] = u @ pending[q]
         for qa, qb in layer["couplers"]:
             drilled = gate in holes
+            theta = thetas[gate]
             gate += 1
             if drilled:
                 for q in (qa, qb):
@@ -129,7 +134,7 @@ def circuit_network(circuit: dict, simplify: bool = True) -> TensorNetwork:
                     last[q] = None
                     n2q[q] += 1
                 continue
-            t = g.copy()
+            t = _fsim4(theta, phi)
             oa, ob = new_label(), new_label()
             labs = [oa, ob, -1, -2]
             # fold the inputs: initial vectors or the pending gates of each wire

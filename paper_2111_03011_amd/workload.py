@@ -149,6 +149,18 @@ def _config_workload(name: str, mode: str, trials: int | None) -> Workload:
     return Workload(name, circuit, net, list(open_q), np.asarray(closed, np.uint64), plan, ids)
 
 
+def jittered_twin(w: Workload, theta_jitter: float, jitter_seed: int) -> Workload:
+    """The same workload with one fSim angle per gate drawn around the circuit's angle (see
+    synth.make_circuit): same network structure, hence the same path, slicing, slice ids
+    and targets; only the gate entries differ."""
+    import dataclasses
+    c = synth.with_theta_jitter(w.circuit, theta_jitter, jitter_seed)
+    net = circuit_network(c)
+    if net.labels != w.net.labels:
+        raise RuntimeError("the jittered network's structure differs from the workload's")
+    return dataclasses.replace(w, circuit=c, net=net)
+
+
 def serving_template(seed: int, max_log2: float = 26, work_cap: float = 2e13,
                      max_tries: int = 50):
     """One request of the serving stream, planned by the client ahead of time.

@@ -11,6 +11,7 @@ from .circuits import (  # noqa: F401
     grid_sites,
     pattern_couplers,
     make_circuit,
+    with_theta_jitter,
     circuit_from_config,
     ONEQ_NAMES,
 )

@@ -56,8 +56,15 @@ def pattern_couplers(sites, pattern: str) -> list[tuple[int, int]]:
 
 def make_circuit(rows: int, cols: int, cycles: int, seed: int, removed=(),
                  theta: float = math.pi / 2, phi: float = math.pi / 6,
-                 sequence: str = "ABCDCDAB") -> dict:
-    """A seeded Sycamore-like circuit description (JSON-serialisable)."""
+                 sequence: str = "ABCDCDAB", theta_jitter: float = 0.0,
+                 jitter_seed: int | None = None) -> dict:
+    """A seeded Sycamore-like circuit description (JSON-serialisable).
+
+    theta_jitter > 0 gives every two-qubit gate its own angle theta + theta_jitter * z,
+    z standard normal from PCG64(jitter_seed) in circuit order (cycle by cycle, coupler
+    order), listed as circuit["fsim"]["thetas"]; the single-qubit draw is unchanged.  (The
+    paper's gates have calibrated angles near, not at, pi/2; at pi/2 exactly fSim maps basis
+    states to basis states, which makes heavily sliced networks mostly exact zeros.)"""
     sites = grid_sites(rows, cols, removed)
     n = len(sites)
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -77,7 +84,7 @@ def make_circuit(rows: int, cols: int, cycles: int, seed: int, removed=(),
         pat = sequence[t % len(sequence)]
         layers.append({"oneq": names, "pattern": pat,
                        "couplers": [list(c) for c in pattern_couplers(sites, pat)]})
-    return {
+    circ = {
         "kind": "sycamore_like_grid",
         "rows": rows, "cols": cols, "removed": [list(s) for s in removed],
         "n_qubits": n, "sites": [list(s) for s in sites],
@@ -85,6 +92,22 @@ def make_circuit(rows: int, cols: int, cycles: int, seed: int, removed=(),
         "fsim": {"theta": float(theta), "phi": float(phi)},
         "layers": layers,
     }
+    if theta_jitter > 0:
+        circ = with_theta_jitter(circ, theta_jitter, seed if jitter_seed is None else jitter_seed)
+    return circ
+
+
+def with_theta_jitter(circuit: dict, theta_jitter: float, jitter_seed: int) -> dict:
+    """Copy of a circuit whose two-qubit gates each get the angle theta + theta_jitter * z,
+    z standard normal from PCG64(jitter_seed), in circuit order (cycle by cycle, coupler
+    order), listed as circuit["fsim"]["thetas"]."""
+    n2 = sum(len(l["couplers"]) for l in circuit["layers"])
+    rng = np.random.Generator(np.random.PCG64(jitter_seed))
+    theta = circuit["fsim"]["theta"]
+    out = dict(circuit)
+    out["fsim"] = dict(circuit["fsim"], theta_jitter=float(theta_jitter),
+                       thetas=[float(theta + theta_jitter * z) for z in rng.standard_normal(n2)])
+    return out
 
 
 def circuit_from_config(cfg: dict) -> dict:
@@ -92,4 +115,5 @@ def circuit_from_config(cfg: dict) -> dict:
     return make_circuit(c["rows"], c["cols"], c["cycles"], c["seed"],
                         removed=c.get("removed", ()),
                         theta=c.get("theta", math.pi / 2), phi=c.get("phi", math.pi / 6),
-                        sequence=c.get("sequence", "ABCDCDAB"))
+                        sequence=c.get("sequence", "ABCDCDAB"),
+                        theta_jitter=c.get("theta_jitter", 0.0), jitter_seed=c.get("jitter_seed"))

@@ -64,6 +64,10 @@ CONFIGS = {
         "path_seed": 5004,
         "plan_trials": 1,
         "reuse_batch": 8,         # head-reuse mode: 32 subtasks x 8 local slices
+        # parity twin: the same circuit with calibrated-like angles (theta ~ pi/2 +- 0.02 per
+        # gate).  At pi/2 exactly fSim maps basis states to basis states and a slice that
+        # fixes 98 bonds is mostly an exact zero (computed as rounding noise on any path).
+        "parity_jitter": {"theta_jitter": 0.02, "jitter_seed": 5005},
     },
 }
 

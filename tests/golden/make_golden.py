@@ -7,7 +7,10 @@ Every stored amplitude comes from `oracle/` (complex128): the state-vector simul
 the whole 1024-slice sum of the 5x6-grid, 14-cycle workload (the full slice set of a
 sliced network is the exact amplitude <s|U|0^n>, Appendix B.2), and the pairwise
 tensordot contractor for single (slice, group) pairs of the 53-qubit, 20-cycle share
-(Appendix A groups, Appendix B.2 slices).
+(Appendix A groups, Appendix B.2 slices), on the circuit with per-gate angles jittered
+around pi/2: at pi/2 exactly fSim maps basis states to basis states, and most slices that
+fix 98 bonds are exact zeros, computed by any contraction order as rounding noise.  Each
+pair is contracted along two orders, which must agree to rounding.
 
 Inputs: circuits, targets and slice subsets come from `synth/` (seeded generators).  For
 the 53-qubit share the sliced bonds and the slice ids are those of the package's seeded
@@ -68,39 +71,56 @@ def make_sliced() -> None:
     print(f"wrote {SLICED_FILE} ({dt:.0f} s, norm {norm:.15f})", flush=True)
 
 
+def _pair(circ, w, bonds, sigma, cb, path_seed):
+    n = circ["n_qubits"]
+    closed = [q for q in range(n) if q not in set(w.open_qubits)]
+    net = network.build_network(circ, {q: (cb >> (n - 1 - q)) & 1 for q in closed})
+    fixed = {net.bond_label[tuple(b)]: (sigma >> bi) & 1 for bi, b in enumerate(bonds)}
+    _, labels = net.sliced(fixed)
+    path = contract.random_greedy_path(labels, path_seed)
+    amps = contract.sparse_amplitudes(circ, w.open_qubits, [cb], sliced_bonds=bonds,
+                                      slice_ids=[sigma], path=path)
+    return amps[0], contract.peak_size(labels, path)
+
+
 def make_large() -> None:
     from paper_2111_03011_amd.workload import config_workload
     w = config_workload("large")
-    circ = w.circuit
-    n = circ["n_qubits"]
+    jit = synth.config("large")["parity_jitter"]
+    # the same circuit with one angle per gate near pi/2 (at pi/2 exactly most slices of this
+    # slicing are exact zeros, which any contraction order returns as rounding noise)
+    circ = synth.with_theta_jitter(w.circuit, jit["theta_jitter"], jit["jitter_seed"])
     bonds = w.sliced_bonds
     lines = []
     for pos, grp in LARGE_PAIRS:
         sigma = int(w.slice_ids[pos])
         cb = int(w.closed_bits[grp])
         t0 = time.time()
-        closed = [q for q in range(n) if q not in set(w.open_qubits)]
-        net = network.build_network(circ, {q: (cb >> (n - 1 - q)) & 1 for q in closed})
-        fixed = {net.bond_label[tuple(b)]: (sigma >> bi) & 1 for bi, b in enumerate(bonds)}
-        _, labels = net.sliced(fixed)
-        path = contract.random_greedy_path(labels, LARGE_PATH_SEED)
-        peak = contract.peak_size(labels, path)
-        amps = contract.sparse_amplitudes(circ, w.open_qubits, [cb], sliced_bonds=bonds,
-                                          slice_ids=[sigma], path=path)
+        amps, peak = _pair(circ, w, bonds, sigma, cb, LARGE_PATH_SEED)
         dt = time.time() - t0
-        print(f"pair (slice {pos}, group {grp}): peak 2^{int(np.log2(peak))}, {dt:.0f} s", flush=True)
-        lines.append((pos, grp, sigma, cb, int(np.log2(peak)), dt, amps[0]))
+        # conditioning: a second contraction order must agree to rounding
+        other, _ = _pair(circ, w, bonds, sigma, cb, LARGE_PATH_SEED + 1)
+        cond = float(np.linalg.norm(amps - other) / np.linalg.norm(amps))
+        print(f"pair (slice {pos}, group {grp}): peak 2^{int(np.log2(peak))}, {dt:.0f} s, "
+              f"second path differs by {cond:.1e}", flush=True)
+        if not cond < 1e-11:
+            raise RuntimeError("the pair's amplitudes depend on the contraction order")
+        lines.append((pos, grp, sigma, cb, int(np.log2(peak)), dt, cond, amps))
     with open(LARGE_FILE, "w") as f:
         f.write("# oracle amplitudes of single (slice, group) pairs of the 53-qubit, 20-cycle share\n")
         f.write("# (6x9 grid minus site (0,4), circuit seed %d; 2^14 groups x open qubits %s;\n"
                 % (synth.config("large")["circuit"]["seed"], " ".join(map(str, w.open_qubits))))
-        f.write("# 256-slice subset of %d sliced bonds).  oracle.contract.sparse_amplitudes along\n"
-                % len(bonds))
-        f.write("# oracle.contract.random_greedy_path(seed %d), complex128.\n" % LARGE_PATH_SEED)
+        f.write("# 256-slice subset of %d sliced bonds), with the fSim angles jittered: theta_jitter "
+                "%g, jitter_seed %d.\n" % (len(bonds), jit["theta_jitter"], jit["jitter_seed"]))
+        f.write("# oracle.contract.sparse_amplitudes along oracle.contract.random_greedy_path(seed %d),\n"
+                % LARGE_PATH_SEED)
+        f.write("# complex128; 'path_diff' = relative difference from the order of seed %d.\n"
+                % (LARGE_PATH_SEED + 1))
         f.write("# sliced bonds (q,j) in slice-bit order: %s\n"
                 % " ".join(f"{q},{j}" for q, j in bonds))
-        for pos, grp, sigma, cb, pk, dt, amps in lines:
-            f.write(f"pair {pos} {grp} {sigma:x} {cb:x} peak_log2 {pk} seconds {dt:.0f}\n")
+        for pos, grp, sigma, cb, pk, dt, cond, amps in lines:
+            f.write(f"pair {pos} {grp} {sigma:x} {cb:x} peak_log2 {pk} seconds {dt:.0f} "
+                    f"path_diff {cond:.1e}\n")
             _write_amps(f, amps)
     print(f"wrote {LARGE_FILE}", flush=True)
 

@@ -48,12 +48,15 @@ def sliced_full_sum() -> SlicedSum:
 
 
 def large_pairs():
-    """(pairs, sliced bonds in slice-bit order)."""
+    """(pairs, sliced bonds in slice-bit order, (theta_jitter, jitter_seed) of the circuit)."""
     p = _path("large_53q_m20_slice_group.txt")
-    pairs, bonds, cur = [], None, None
+    pairs, bonds, cur, jitter = [], None, None, None
     for line in open(p):
         if line.startswith("# sliced bonds"):
             bonds = [tuple(int(x) for x in b.split(",")) for b in line.split(":", 1)[1].split()]
+        elif "theta_jitter" in line and line.startswith("#"):
+            f = line.replace(",", " ").replace(".\n", " ").split()
+            jitter = (float(f[f.index("theta_jitter") + 1]), int(f[f.index("jitter_seed") + 1].rstrip(".")))
         elif line.startswith("#"):
             continue
         elif line.startswith("pair"):
@@ -65,4 +68,4 @@ def large_pairs():
             cur.amps.append(complex(re, im))
     for q in pairs:
         q.amps = np.asarray(q.amps)
-    return pairs, bonds
+    return pairs, bonds, jitter

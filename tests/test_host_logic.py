@@ -59,6 +59,17 @@ def test_network_builder_matches_oracle_state_vector():
     assert np.allclose(res, statevector.simulate(c), atol=1e-13)
 
 
+def test_network_builder_reads_per_gate_angles():
+    """A jittered circuit (one angle per two-qubit gate) builds a network with the same
+    labels as the plain one and the oracle's state vector."""
+    c = synth.make_circuit(3, 3, 9, 4, theta_jitter=0.05, jitter_seed=2)
+    net = circuit_network(c)
+    assert net.labels == circuit_network(synth.make_circuit(3, 3, 9, 4)).labels
+    p = ocontract.greedy_path(net.labels)
+    res = ocontract.contract_path(net.tensors, net.labels, p, net.out_label).reshape(-1)
+    assert np.allclose(res, statevector.simulate(c), atol=1e-13)
+
+
 def _brute_macs(labels, out_set, closed_rows, path, sliced):
     """Recount complex multiply-adds step by step from plain label sets."""
     cur = [set(l) - set(sliced) for l in labels]

@@ -100,3 +100,16 @@ def test_peak_size_counts_elements():
     labels = [("a", "b"), ("b", "c"), ("c", "d")]
     assert contract.peak_size(labels, [(0, 1), (0, 2)]) == 4
     assert contract.peak_size([("a",), ("b",)], [(0, 1)]) == 4
+
+
+def test_jittered_angles_contractor_equals_state_vector():
+    """Per-gate angles reach the contractor's network as they reach the simulator: the
+    two routes agree on a jittered circuit, sliced and summed."""
+    c = synth.make_circuit(3, 3, 8, 23, theta_jitter=0.03, jitter_seed=4)
+    n = c["n_qubits"]
+    open_q = [1, 5, 7]
+    closed = synth.group_targets(n, open_q, 3, 8)
+    bonds = [(1, 1), (4, 2), (3, 0)]
+    amps = contract.sparse_amplitudes(c, open_q, closed, sliced_bonds=bonds)
+    ref = statevector.sparse_from_state(statevector.simulate(c), n, open_q, closed)
+    assert np.allclose(amps, ref, atol=1e-13)

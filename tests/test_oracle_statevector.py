@@ -45,12 +45,16 @@ def _full_two_qubit(n, qa, qb, f):
 
 def _brute(c):
     n = c["n_qubits"]
-    f = gates.fsim(c["fsim"]["theta"], c["fsim"]["phi"])
+    n2 = sum(len(l["couplers"]) for l in c["layers"])
+    thetas = c["fsim"].get("thetas", [c["fsim"]["theta"]] * n2)
     u = np.eye(1 << n, dtype=complex)
+    gate = 0
     for layer in c["layers"]:
         u = _full_oneq_layer(layer["oneq"]) @ u
         for qa, qb in layer["couplers"]:
+            f = gates.fsim(thetas[gate], c["fsim"]["phi"])
             u = _full_two_qubit(n, qa, qb, f) @ u
+            gate += 1
     return u[:, 0]
 
 
@@ -91,6 +95,35 @@ def test_four_qubit_gates_on_every_pair_match_brute_force(backend):
         st.apply_2q(g, 1, 3)
         got = st.flat()
     assert np.allclose(got, ref, atol=1e-13)
+
+
+@pytest.mark.parametrize("backend", BACKENDS)
+def test_per_gate_angles_match_brute_force(backend):
+    """Calibrated gates (Results: angles near pi/2, one per gate): each two-qubit gate
+    takes its own angle from the circuit's list, in circuit order; a swapped or shifted
+    angle changes the state."""
+    layers = [(["sqrt_y", "sqrt_w", "sqrt_x"], [(0, 1)]), (["sqrt_x", "sqrt_y", "sqrt_w"], [(1, 2)]),
+              (["sqrt_w", "sqrt_x", "sqrt_y"], [(0, 2)])]
+    c = _circuit(3, layers)
+    c["fsim"]["thetas"] = [1.4, 1.6, 1.1]
+    got = statevector.simulate(c, backend=backend)
+    assert np.allclose(got, _brute(c), atol=1e-14)
+    c2 = _circuit(3, layers)
+    c2["fsim"]["thetas"] = [1.6, 1.4, 1.1]
+    assert not np.allclose(got, statevector.simulate(c2, backend=backend), atol=1e-6)
+
+
+def test_jittered_circuit_angles():
+    """The jitter flag draws one angle per two-qubit gate around theta (seeded, circuit
+    order) and leaves the single-qubit gates as they were."""
+    import math
+    a = synth.make_circuit(3, 4, 8, 1001)
+    b = synth.make_circuit(3, 4, 8, 1001, theta_jitter=0.02, jitter_seed=9)
+    n2 = sum(len(l["couplers"]) for l in a["layers"])
+    th = np.array(b["fsim"]["thetas"])
+    assert len(th) == n2 and a["layers"] == b["layers"] and "thetas" not in a["fsim"]
+    assert np.all(np.abs(th - math.pi / 2) < 0.2) and 0.005 < np.std(th) < 0.05
+    assert synth.make_circuit(3, 4, 8, 1001, theta_jitter=0.02, jitter_seed=9)["fsim"] == b["fsim"]
 
 
 @pytest.mark.parametrize("backend", BACKENDS)
