@@ -44,17 +44,22 @@ enum {
 const char* tnc_last_error(void);
 
 /* Arithmetic of the contraction steps.  The slice sum and the sampler are FP64 in every
- * case, and tensors are stored as complex64 in every case.
- *   TNC_C64     GEMM steps on the FP32 matrix cores, FP32 accumulation.
+ * case, and tensors are stored as complex64 in every case, each with a power-of-two
+ * exponent per slice: the stored values times 2^E are the tensor (E and the tensor's
+ * largest component are recorded by the kernel that produces it).  Operands are rescaled
+ * exactly by powers of two as they are loaded, so no stored value leaves the range of the
+ * arithmetic, however small a slice's amplitudes (a slice of a heavily sliced 53-qubit
+ * network has amplitudes near 1e-39, below FP32's normal range); the FP64 slice sum
+ * applies 2^E.
+ *   TNC_C64     GEMM steps on the FP32 matrix cores, FP32 accumulation; operands whose
+ *               largest component lies outside [2^-20, 2^21) are brought to [1, 2).
  *   TNC_BF16X3  GEMM steps split every operand value x into hi = bf16(x) and
  *               lo = bf16(x - hi) and accumulate hi*hi + hi*lo + lo*hi in FP32 on the BF16
- *               matrix cores (about 16 significant bits per operand; BF16 keeps FP32's
- *               exponent range, so no scaling is needed).
- *   TNC_FP16X3  the same three products in FP16, with a power-of-two scale per operand and
- *               slice: a preceding pass finds each operand's largest component m in
- *               [2^e, 2^(e+1)), values are scaled by 2^(13 - e) before the split (so
- *               |hi| < 2^14, far below FP16's limit) and the product is scaled back when
- *               it is stored (about 22 significant bits per operand).
+ *               matrix cores (about 16 significant bits per operand; BF16 has FP32's
+ *               exponent range and the same rescaling as TNC_C64).
+ *   TNC_FP16X3  the same three products in FP16: every operand with largest component in
+ *               [2^e, 2^(e+1)) is scaled by 2^(13 - e) before the split (|hi| < 2^14, far
+ *               below FP16's limit; about 22 significant bits per operand).
  *   the 3M forms are declared for ABI stability and return TNC_E_UNSUPPORTED. */
 typedef enum {
   TNC_C64 = 0,
@@ -203,10 +208,9 @@ tnc_status tnc_plan_destroy(tnc_plan plan);
 tnc_status tnc_net_destroy(tnc_net net);
 
 /* Per-step description for reporting: kind 1 = GEMM, 2 = small-operand stream, 3 = slice
- * leaves, 4 = slice sum, 5 = split-K reduction, 6 = operand preparation for a split-precision
- * GEMM (BF16 hi/lo copy, or the per-slice largest component that sets the FP16 scale)
- * (0 is reserved: operands are never permuted, the GEMM reads them in their stored
- * layouts); rows, m, n, k in
+ * leaves, 4 = slice sum, 5 = split-K reduction, 6 = clearing of the scale records (once per
+ * call for slice-invariant tensors, once per batch for the others) (0 is reserved: operands
+ * are never permuted, the GEMM reads them in their stored layouts); rows, m, n, k in
  * elements; flops and bytes algorithmic (one slice); invariant = 1 if run once per call,
  * 2 if run once per batch (head reuse, see tnc_plan_work), 0 if run per slice.  For GEMMs:
  * tile configuration (0 = 128x64, 1 = 128x16, 2 = 64x32, 3 = 128x128 complex), split-K

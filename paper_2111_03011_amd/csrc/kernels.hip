@@ -21,15 +21,112 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// Fold per-lane maxima m >= 0 into the kAmaxSlots slots of record copy `slice`,
+// amax[slice * step + j], with atomic maxima on the float bits (non-negative floats order
+// like their bits); the slot is a hash of the workgroup index, which spreads the atomics of
+// a large output over many addresses, and readers take the maximum over the slots
+// (amax_read).  Every lane of the wave calls this; a lane without an element passes
+// slice = -1.  When the lanes with an element share one slice the wave reduces first and
+// issues one atomic.
+__device__ __forceinline__ void amax_commit(float m, int64_t slice, uint32_t* amax, int64_t step) {
+  amax += (blockIdx.x + 7u * blockIdx.y + 13u * blockIdx.z) & (kAmaxSlots - 1);
+  int64_t s0 = slice;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const int64_t o = __shfl_xor(s0, off);
+    s0 = s0 > o ? s0 : o;
+  }
+  if (s0 < 0) return;
+  if (__all(slice == s0 || slice < 0)) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0 && m > 0.f) atomicMax(amax + s0 * step, __float_as_uint(m));
+  } else if (slice >= 0 && m > 0.f) {
+    atomicMax(amax + slice * step, __float_as_uint(m));
+  }
+}
+
+// maximum over a record's kAmaxSlots slots (lane j reads slots j, j + 64, ...; every lane
+// of the wave gets the result)
+__device__ __forceinline__ uint32_t amax_read(const uint32_t* slots) {
+  const int lane = threadIdx.x & 63;
+  uint32_t v = 0;
+#pragma unroll
+  for (int k = 0; k < kAmaxSlots / 64; ++k) {
+    const uint32_t o = slots[lane + 64 * k];
+    v = v > o ? v : o;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint32_t o = __shfl_xor(v, off);
+    v = v > o ? v : o;
+  }
+  return v;
+}
+
+// amax_commit for a workgroup whose lanes all hold elements of one slice: the four waves'
+// maxima meet in LDS and one atomic maximum goes out per workgroup.  Every thread of the
+// workgroup calls it (it synchronises the workgroup).
+__device__ __forceinline__ void amax_commit_wg(float m, int64_t slice, uint32_t* amax, int64_t step) {
+  __shared__ float red[kThreads / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float w = red[0];
+#pragma unroll
+    for (int i = 1; i < kThreads / 64; ++i) w = fmaxf(w, red[i]);
+    if (w > 0.f)
+      atomicMax(amax + slice * step + ((blockIdx.x + 7u * blockIdx.y + 13u * blockIdx.z) & (kAmaxSlots - 1)),
+                __float_as_uint(w));
+  }
+}
+
+// Scale shift of an operand from its largest component (float bits): the FP32 forms
+// (f16 = false) leave operands whose largest component lies in [2^-20, 2^21) alone and
+// bring the others to [1, 2); the FP16 form brings it to [2^13, 2^14) (exponents clamped
+// to [-110, 127]).  An all-zero operand is not scaled.  The result lies in [-126, 127].
+__device__ __forceinline__ int rec_shift(uint32_t amax_bits, bool f16) {
+  const int e = int((amax_bits >> 23) & 0xffu) - 127;   // -127 for zero and subnormals
+  if (f16) return 13 - (e < -110 ? -110 : e);
+  if (amax_bits == 0u || (e >= -20 && e <= 20)) return 0;
+  return e > 126 ? -126 : -e;
+}
+
+// 2^k for k in [-126, 127]
+__device__ __forceinline__ float pow2f(int k) { return __uint_as_float(uint32_t(127 + k) << 23); }
+
+// Shift and exponent of record copy `slice` (every lane of the wave calls it).
+__device__ __forceinline__ void rec_load(const uint32_t* rec, int64_t step, int64_t slice, bool f16,
+                                         int& shift, int& expo) {
+  const uint32_t* r = rec + slice * step;
+  shift = rec_shift(amax_read(r), f16);
+  expo = int(r[kRecExp]);
+}
+
+
 // ---------------------------------------------------------------------------------
-// big x small stream
+// big x small stream: the small operand S (one copy shared by every row and slice) sits in
+// LDS; every thread contracts one m of the big operand X at a time (grid-stride within
+// one slice; grid y/z = slices).  With scale records, X and S are multiplied by their
+// power-of-two scales while loaded and the output's largest component is recorded.
 template <int NK, int NN>
 __global__ __launch_bounds__(kThreads) void k_stream(StreamArgs a) {
   constexpr int KS = 1 << NK, NS = 1 << NN;
   __shared__ float2 s_lds[KS * NS];
   __shared__ int64_t koff[KS];
-  __shared__ int32_t soff[KS * NS];
-  const bool s_shared = (a.s_rows == 1 && a.gs == nullptr && a.s_slice_stride == 0);
+  const int64_t sl = int64_t(blockIdx.y) + int64_t(blockIdx.z) * gridDim.y;
+  if (sl >= a.nb) return;
+  float sx = 1.f, ss = 1.f;
+  if (a.rec_c) {
+    int shx, shs, ex, es;
+    rec_load(a.rec_x, a.rec_x_step, sl, false, shx, ex);
+    rec_load(a.rec_s, a.rec_s_step, sl, false, shs, es);
+    sx = pow2f(shx);
+    ss = pow2f(shs);
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.rec_c[sl * a.rec_c_step + kRecExp] = uint32_t(ex + es - shx - shs);
+  }
   for (int k = threadIdx.x; k < KS; k += kThreads) {
     int64_t ko = 0;
     for (int j = 0; j < NK; ++j)
@@ -43,17 +140,16 @@ __global__ __launch_bounds__(kThreads) void k_stream(StreamArgs a) {
       if ((k >> j) & 1) so += 1 << a.s_kpos[j];
     for (int j = 0; j < NN; ++j)
       if ((n >> j) & 1) so += 1 << a.s_npos[j];
-    soff[q] = so;
-    if (s_shared) s_lds[q] = a.S[so];
+    const float2 v = a.S[so];
+    s_lds[q] = make_float2(v.x * ss, v.y * ss);
   }
   __syncthreads();
   const int64_t per_slice = a.rows << a.n_m;
-  const int64_t total = per_slice * a.nb;
   const int64_t mmask = (int64_t(1) << a.n_m) - 1;
-  for (int64_t g = int64_t(blockIdx.x) * kThreads + threadIdx.x; g < total;
+  float mx = 0.f;
+  for (int64_t g = int64_t(blockIdx.x) * kThreads + threadIdx.x; g < per_slice;
        g += int64_t(gridDim.x) * kThreads) {
-    const int64_t sl = g / per_slice, gs = g - sl * per_slice;
-    const int64_t r = gs >> a.n_m, m = gs & mmask;
+    const int64_t r = g >> a.n_m, m = g & mmask;
     const int64_t xr = a.gx ? a.gx[r] : (a.x_rows == 1 ? 0 : r);
     const float2* X = a.X + sl * a.x_slice_stride + xr * a.x_row_stride;
     int64_t xo = m;
@@ -64,37 +160,30 @@ __global__ __launch_bounds__(kThreads) void k_stream(StreamArgs a) {
     }
     float2 xv[KS];
 #pragma unroll
-    for (int k = 0; k < KS; ++k) xv[k] = X[xo + koff[k]];
+    for (int k = 0; k < KS; ++k) {
+      const float2 v = X[xo + koff[k]];
+      xv[k] = make_float2(v.x * sx, v.y * sx);
+    }
     float2 acc[NS];
 #pragma unroll
     for (int n = 0; n < NS; ++n) acc[n] = make_float2(0.f, 0.f);
-    if (s_shared) {
 #pragma unroll
-      for (int k = 0; k < KS; ++k) {
+    for (int k = 0; k < KS; ++k) {
 #pragma unroll
-        for (int n = 0; n < NS; ++n) {
-          const float2 s = s_lds[k * NS + n];
-          acc[n].x += xv[k].x * s.x - xv[k].y * s.y;
-          acc[n].y += xv[k].x * s.y + xv[k].y * s.x;
-        }
-      }
-    } else {
-      const int64_t sr = a.gs ? a.gs[r] : (a.s_rows == 1 ? 0 : r);
-      const float2* S = a.S + sl * a.s_slice_stride + sr * a.s_row_stride;
-#pragma unroll
-      for (int k = 0; k < KS; ++k) {
-#pragma unroll
-        for (int n = 0; n < NS; ++n) {
-          const float2 s = S[soff[k * NS + n]];
-          acc[n].x += xv[k].x * s.x - xv[k].y * s.y;
-          acc[n].y += xv[k].x * s.y + xv[k].y * s.x;
-        }
+      for (int n = 0; n < NS; ++n) {
+        const float2 sv = s_lds[k * NS + n];
+        acc[n].x += xv[k].x * sv.x - xv[k].y * sv.y;
+        acc[n].y += xv[k].x * sv.y + xv[k].y * sv.x;
       }
     }
     float2* C = a.C + sl * a.c_slice_stride + r * a.c_row_stride + (m << NN);
 #pragma unroll
-    for (int n = 0; n < NS; ++n) C[n] = acc[n];
+    for (int n = 0; n < NS; ++n) {
+      C[n] = acc[n];
+      mx = fmaxf(mx, fmaxf(fabsf(acc[n].x), fabsf(acc[n].y)));
+    }
   }
+  if (a.rec_c) amax_commit_wg(mx, sl, a.rec_c, a.rec_c_step);
 }
 
 // ---------------------------------------------------------------------------------
@@ -113,6 +202,15 @@ __global__ __launch_bounds__(kThreads) void k_stream_rows(StreamArgs a, int rw, 
   __shared__ int32_t soff[E];
   const int64_t sl = int64_t(blockIdx.y) + int64_t(blockIdx.z) * gridDim.y;
   if (sl >= a.nb) return;
+  float sx = 1.f, ss = 1.f;
+  if (a.rec_c) {
+    int shx, shs, ex, es;
+    rec_load(a.rec_x, a.rec_x_step, sl, false, shx, ex);
+    rec_load(a.rec_s, a.rec_s_step, sl, false, shs, es);
+    sx = pow2f(shx);
+    ss = pow2f(shs);
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.rec_c[sl * a.rec_c_step + kRecExp] = uint32_t(ex + es - shx - shs);
+  }
   for (int k = threadIdx.x; k < KS; k += kThreads) {
     int64_t ko = 0;
     for (int j = 0; j < NK; ++j)
@@ -145,50 +243,59 @@ __global__ __launch_bounds__(kThreads) void k_stream_rows(StreamArgs a, int rw, 
     const int64_t rr = e / E, r = r0 + rr;
     const int q = int(e % E);
     const int64_t sr = a.gs ? a.gs[r] : (a.s_rows == 1 ? 0 : r);
-    s_lds[e] = a.S[sl * a.s_slice_stride + sr * a.s_row_stride + soff[q]];
+    const float2 v = a.S[sl * a.s_slice_stride + sr * a.s_row_stride + soff[q]];
+    s_lds[e] = make_float2(v.x * ss, v.y * ss);
   }
   __syncthreads();
   const int item = threadIdx.x / nsplit, part = threadIdx.x % nsplit;
   const int64_t items = (M >= kThreads) ? kThreads : nrows * M;
-  if (item >= items) return;
-  int64_t rr, m;
-  if (M >= kThreads) {
-    rr = 0;
-    m = m_base + item;
-  } else {
-    rr = item >> a.n_m;
-    m = item & (M - 1);
-  }
-  const int64_t r = r0 + rr;
-  const int64_t xr = a.gx ? a.gx[r] : (a.x_rows == 1 ? 0 : r);
-  const float2* X = a.X + sl * a.x_slice_stride + xr * a.x_row_stride;
-  int64_t xo = m;
+  float mx = 0.f;
+  if (item < items) {
+    int64_t rr, m;
+    if (M >= kThreads) {
+      rr = 0;
+      m = m_base + item;
+    } else {
+      rr = item >> a.n_m;
+      m = item & (M - 1);
+    }
+    const int64_t r = r0 + rr;
+    const int64_t xr = a.gx ? a.gx[r] : (a.x_rows == 1 ? 0 : r);
+    const float2* X = a.X + sl * a.x_slice_stride + xr * a.x_row_stride;
+    int64_t xo = m;
 #pragma unroll
-  for (int j = 0; j < NK; ++j) {
-    const int p = a.x_kins[j];
-    xo = ((xo >> p) << (p + 1)) | (xo & ((int64_t(1) << p) - 1));
-  }
-  float2 xv[KS];
-#pragma unroll
-  for (int k = 0; k < KS; ++k) xv[k] = X[xo + koff[k]];
-  const float2* srow = s_lds + rr * E;
-  float2* C = a.C + sl * a.c_slice_stride + r * a.c_row_stride + (m << NN);
-  const int nper = NS / nsplit;
-  for (int n = part * nper; n < (part + 1) * nper; ++n) {
-    float2 acc = make_float2(0.f, 0.f);
+    for (int j = 0; j < NK; ++j) {
+      const int p = a.x_kins[j];
+      xo = ((xo >> p) << (p + 1)) | (xo & ((int64_t(1) << p) - 1));
+    }
+    float2 xv[KS];
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
-      const float2 sv = srow[k * NS + n];
-      acc.x += xv[k].x * sv.x - xv[k].y * sv.y;
-      acc.y += xv[k].x * sv.y + xv[k].y * sv.x;
+      const float2 v = X[xo + koff[k]];
+      xv[k] = make_float2(v.x * sx, v.y * sx);
     }
-    C[n] = acc;
+    const float2* srow = s_lds + rr * E;
+    float2* C = a.C + sl * a.c_slice_stride + r * a.c_row_stride + (m << NN);
+    const int nper = NS / nsplit;
+    for (int n = part * nper; n < (part + 1) * nper; ++n) {
+      float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int k = 0; k < KS; ++k) {
+        const float2 sv = srow[k * NS + n];
+        acc.x += xv[k].x * sv.x - xv[k].y * sv.y;
+        acc.y += xv[k].x * sv.y + xv[k].y * sv.x;
+      }
+      C[n] = acc;
+      mx = fmaxf(mx, fmaxf(fabsf(acc.x), fabsf(acc.y)));
+    }
   }
+  if (a.rec_c) amax_commit_wg(mx, sl, a.rec_c, a.rec_c_step);
 }
 
 // ---------------------------------------------------------------------------------
 // complex64 GEMM on v_mfma_f32_32x32x2f32
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x2v __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb) {
   // Workgroups are dealt to the 8 XCDs round-robin; renumber them so that each XCD
@@ -229,6 +336,18 @@ __device__ __forceinline__ float2 keep_if(float2 v, uint32_t mask) {
 // in LDS (LDS_TAB) or one entry per lane in registers, read with readlane.  Offsets within
 // one operand row fit in 31 bits (also checked when the plan is compiled).
 constexpr int kKLevels = 4;
+
+// Operand scales of a GEMM for slice copy sl from the records of A and B; the workgroup
+// that owns the slice's first tile (`writer`) records C's exponent.
+__device__ __forceinline__ void rec_scales(const GemmArgs& a, int64_t sl, bool f16, bool writer,
+                                           float& sa, float& sb) {
+  int sha, shb, ea, eb;
+  rec_load(a.rec_a, a.rec_a_step, sl, f16, sha, ea);
+  rec_load(a.rec_b, a.rec_b_step, sl, f16, shb, eb);
+  sa = pow2f(sha);
+  sb = pow2f(shb);
+  if (writer && threadIdx.x == 0) a.rec_c[sl * a.rec_c_step + kRecExp] = uint32_t(ea + eb - sha - shb);
+}
 
 template <int BM, int BN, int BK, bool A_MFAST, bool B_NFAST, bool LDS_TAB>
 struct GemmTile {
@@ -321,7 +440,7 @@ struct GemmTile {
     k_begin = int64_t(ks) * a.k_chunk;
     k_end = (k_begin + a.k_chunk < a.K) ? k_begin + a.k_chunk : a.K;
     nlev = a.nk > LBK ? (a.nk - LBK + 5) / 6 : 0;
-    if (LDS_TAB) {
+    if (LDS_TAB && nlev > 0) {
       for (int e = threadIdx.x; e < kTab; e += kThreads) {
         const int op = e / (kLev * 64), l = (e / 64) % kLev, d = e % 64;
         const int lo = LBK + 6 * l;
@@ -372,7 +491,7 @@ struct GemmTile {
       b_off[i] = in ? int32_t(scatter_u<LBK>(kr, a.b_kpos, nbk) + scatter_u<LBN>(n, a.b_npos, nbn)) : 0;
       in_bits |= uint32_t(in) << (A_LD + i);
     }
-    if (LDS_TAB) __syncthreads();
+    if (LDS_TAB && nlev > 0) __syncthreads();
     return true;
   }
 
@@ -421,12 +540,25 @@ struct GemmTile {
     }
   }
 
+  // the workgroup of the slice's first tile, row and split (records C's exponent)
+  __device__ __forceinline__ bool first_of_slice() const {
+    return m0 == 0 && n0 == 0 && r == 0 && ks == 0;
+  }
+
   // zero the slots that are out of range
   __device__ __forceinline__ static void apply(uint32_t valid, float2* ra, float2* rb) {
 #pragma unroll
     for (int i = 0; i < A_LD; ++i) ra[i] = keep_if(ra[i], ((valid >> i) & 1) ? ~0u : 0u);
 #pragma unroll
     for (int i = 0; i < B_LD; ++i) rb[i] = keep_if(rb[i], ((valid >> (A_LD + i)) & 1) ? ~0u : 0u);
+  }
+
+  // multiply the staged values by the operands' power-of-two scales (exact)
+  __device__ __forceinline__ static void scale(float sa, float sb, float2* ra, float2* rb) {
+#pragma unroll
+    for (int i = 0; i < A_LD; ++i) ra[i] = make_float2(ra[i].x * sa, ra[i].y * sa);
+#pragma unroll
+    for (int i = 0; i < B_LD; ++i) rb[i] = make_float2(rb[i].x * sb, rb[i].y * sb);
   }
 
   __device__ __forceinline__ float* out(const GemmArgs& a) const {
@@ -449,26 +581,17 @@ struct GemmTile {
     return out(a) + (m0 + row) * N * 2;
   }
 
-  // largest |value| among the accumulator entries store_acc writes (same layout and bounds)
+  // largest |value| among this lane's accumulators: entries outside the output hold exact
+  // zeros (their operand slots were zeroed when staged), so no bounds are needed
   template <int UM, int UN>
-  __device__ __forceinline__ float acc_absmax(const GemmArgs& a, const f32x16 (&acc)[UM][UN],
-                                              int wm_base, int wn_base) const {
-    const int lane = threadIdx.x & 63, half = lane >> 5, j32 = lane & 31;
+  __device__ __forceinline__ static float acc_absmax(const f32x16 (&acc)[UM][UN]) {
     float m = 0.f;
 #pragma unroll
     for (int i = 0; i < UM; ++i)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int row = wm_base + i * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
-        bool row_ok;
-        if (a.stk) row_ok = (((m0 & 127) + row) >> a.nm) < stk_count;
-        else row_ok = m0 + row < M;
+      for (int j = 0; j < UN; ++j)
 #pragma unroll
-        for (int j = 0; j < UN; ++j) {
-          const int64_t np = n0 + wn_base + j * 16 + (j32 >> 1);
-          if (row_ok && np < N) m = fmaxf(m, fabsf(acc[i][j][v]));
-        }
-      }
+        for (int v = 0; v < 16; ++v) m = fmaxf(m, fabsf(acc[i][j][v]));
     return m;
   }
 
@@ -534,6 +657,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int wm = wave % WAVES_M, wn = wave / WAVES_M;
+  float sa = 1.f, sb = 1.f;
+  bool scaled = false;
 
   f32x16 acc[UM][UN];
 #pragma unroll
@@ -547,6 +672,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
   uint32_t valid = 0;
   auto store = [&](int stage) {
     if (valid != t.full_bits) Tile::apply(valid, ra, rb);
+    if (scaled) Tile::scale(sa, sb, ra, rb);
     float* as = As + stage * A_STAGE;
     float* bs = Bs + stage * B_STAGE;
 #pragma unroll
@@ -572,10 +698,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
   for (int j = 0; j < UN; ++j) b_rd[j] = 2 * (wn * UN * 16 + j * 16 + (j32 >> 1));
 
   int stage = 0;
-  if (t.k_begin < t.k_end) {
-    t.load(a, t.k_begin, ra, rb, valid);
-    store(0);
+  if (t.k_begin < t.k_end) t.load(a, t.k_begin, ra, rb, valid);
+  if (a.rec_c) {   // the records are read while the first tile's loads are in flight
+    rec_scales(a, t.sl, false, t.first_of_slice(), sa, sb);
+    scaled = (sa != 1.f) || (sb != 1.f);
   }
+  if (t.k_begin < t.k_end) store(0);
   __syncthreads();
   for (int64_t k0 = t.k_begin; k0 < t.k_end; k0 += BK) {
     const bool more = k0 + BK < t.k_end;
@@ -618,6 +746,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
     __syncthreads();
     stage ^= 1;
   }
+  if (a.rec_c && a.k_splits == 1)
+    amax_commit_wg(Tile::template acc_absmax<UM, UN>(acc), t.sl, a.rec_c, a.rec_c_step);
   t.template store_acc<UM, UN>(a, acc, wm * UM * 32, wn * UN * 16);
 }
 
@@ -644,6 +774,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
   Tile t;
   if (!t.init(a, ktab)) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float sa = 1.f, sb = 1.f;
+  bool scaled = false;
   f32x4 acc[UM];
 #pragma unroll
   for (int i = 0; i < UM; ++i)
@@ -654,6 +786,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
   uint32_t valid = 0;
   auto store = [&](int stage) {
     if (valid != t.full_bits) Tile::apply(valid, ra, rb);
+    if (scaled) Tile::scale(sa, sb, ra, rb);
     float* as = As + stage * A_STAGE;
     float* bs = Bs + stage * B_STAGE;
 #pragma unroll
@@ -675,10 +808,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
   const int b_rd = (q >> 1) * BS + 2 * (col >> 1);
 
   int stage = 0;
-  if (t.k_begin < t.k_end) {
-    t.load(a, t.k_begin, ra, rb, valid);
-    store(0);
+  if (t.k_begin < t.k_end) t.load(a, t.k_begin, ra, rb, valid);
+  if (a.rec_c) {
+    rec_scales(a, t.sl, false, t.first_of_slice(), sa, sb);
+    scaled = (sa != 1.f) || (sb != 1.f);
   }
+  if (t.k_begin < t.k_end) store(0);
   __syncthreads();
   for (int64_t k0 = t.k_begin; k0 < t.k_end; k0 += BK) {
     const bool more = k0 + BK < t.k_end;
@@ -700,13 +835,107 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
     stage ^= 1;
   }
   const int64_t np = t.n0 + (col >> 1);
+  float mx = 0.f;
 #pragma unroll
   for (int i = 0; i < UM; ++i)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       float* o = t.row_ptr(a, wave * 32 + i * 16 + 4 * q + v);
-      if (o && np < t.N) o[np * 2 + bc] = acc[i][v];
+      if (o && np < t.N) {
+        o[np * 2 + bc] = acc[i][v];
+        mx = fmaxf(mx, fabsf(acc[i][v]));
+      }
     }
+  if (a.rec_c && a.k_splits == 1) amax_commit_wg(mx, t.sl, a.rec_c, a.rec_c_step);
+}
+
+// ---------------------------------------------------------------------------------
+// complex64 products with a short contraction (K = 2^NK <= 16) and a wide output,
+// C[r][m][n] = sum_k A[m,k] B[k,n], on the vector ALUs.  Such steps are bound by writing
+// C (up to 8 GiB per slice): a workgroup owns kOuterCols columns x kOuterRows rows of one
+// output row; each thread keeps the KS x 2 values of B for two consecutive columns in
+// registers, the workgroup stages kOuterStage rows of A at a time in LDS (read as
+// broadcasts), and every thread writes its two complex outputs of a row as one 16-byte
+// store, consecutive lanes at consecutive addresses.  Operands are read in their stored
+// label order (scattered offsets, as in the GEMM); rows may be folded into M (fold) but
+// not stacked; no split-K.
+constexpr int kOuterCols = 512, kOuterRows = 256, kOuterStage = 64;
+
+template <int NK>
+__global__ __launch_bounds__(kThreads) void k_gemm_outer(GemmArgs a) {
+  constexpr int KS = 1 << NK;
+  __shared__ float2 As[kOuterStage * KS];
+  const int64_t M = a.M, N = a.N;
+  const int cols = N < kOuterCols ? int(N) : kOuterCols;   // columns of this workgroup
+  const int tpr = cols / 2;                                 // threads per output row
+  const int rpp = kThreads / tpr;                           // output rows per pass
+  const int64_t col_blocks = N / cols;
+  const int64_t mrows = M < kOuterRows ? M : kOuterRows;
+  const int64_t cb = int64_t(blockIdx.x) % col_blocks, mb = int64_t(blockIdx.x) / col_blocks;
+  const int64_t n0 = cb * cols, mw0 = mb * mrows;
+  const int64_t z = int64_t(blockIdx.y) + int64_t(blockIdx.z) * gridDim.y;
+  if (z >= a.rows * a.nb) return;
+  const int64_t sl = z / a.rows, r = z - sl * a.rows;
+  const int64_t ar = a.ga ? a.ga[r] : (a.a_rows == 1 ? 0 : r);
+  const int64_t br = a.gb ? a.gb[r] : (a.b_rows == 1 ? 0 : r);
+  const float2* A = a.A + sl * a.a_slice_stride + ar * a.a_row_stride;
+  const float2* B = a.B + sl * a.b_slice_stride + br * a.b_row_stride;
+  float2* C = a.C + sl * a.c_slice_stride + r * a.c_row_stride;
+  float sa = 1.f, sb = 1.f;
+  if (a.rec_c) {
+    int sha, shb, ea, eb;
+    rec_load(a.rec_a, a.rec_a_step, sl, false, sha, ea);
+    rec_load(a.rec_b, a.rec_b_step, sl, false, shb, eb);
+    sa = pow2f(sha);
+    sb = pow2f(shb);
+    if (blockIdx.x == 0 && r == 0 && threadIdx.x == 0)
+      a.rec_c[sl * a.rec_c_step + kRecExp] = uint32_t(ea + eb - sha - shb);
+  }
+  // B: this thread's two columns, every k
+  const int tc = threadIdx.x % tpr, tr = threadIdx.x / tpr;
+  const int64_t n = n0 + 2 * tc;
+  float2 b0[KS], b1[KS];
+  {
+    const int64_t o0 = scatter_u<kMaxRank>(n, a.b_npos, a.nn), o1 = scatter_u<kMaxRank>(n + 1, a.b_npos, a.nn);
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const int64_t ko = scatter_u<NK>(k, a.b_kpos, NK);
+      const float2 v0 = B[o0 + ko], v1 = B[o1 + ko];
+      b0[k] = make_float2(v0.x * sb, v0.y * sb);
+      b1[k] = make_float2(v1.x * sb, v1.y * sb);
+    }
+  }
+  const int64_t mloc_mask = (int64_t(1) << a.nm) - 1;
+  const int64_t m_end = (mw0 + mrows < M) ? mw0 + mrows : M;
+  float mx = 0.f;
+  for (int64_t m0 = mw0; m0 < m_end; m0 += kOuterStage) {
+    const int stage_rows = int(m_end - m0 < kOuterStage ? m_end - m0 : kOuterStage);
+    __syncthreads();   // the previous stage has been read
+    for (int e = threadIdx.x; e < stage_rows * KS; e += kThreads) {
+      const int i = e / KS, k = e % KS;
+      const int64_t m = m0 + i;
+      const int64_t mo = (a.fold ? (m >> a.nm) * a.fold_stride : 0) +
+                         scatter_u<kMaxRank>(m & mloc_mask, a.a_mpos, a.nm);
+      const float2 v = A[mo + scatter_u<NK>(k, a.a_kpos, NK)];
+      As[e] = make_float2(v.x * sa, v.y * sa);
+    }
+    __syncthreads();
+    for (int i = tr; i < stage_rows; i += rpp) {
+      float c0r = 0.f, c0i = 0.f, c1r = 0.f, c1i = 0.f;
+#pragma unroll
+      for (int k = 0; k < KS; ++k) {
+        const float2 av = As[i * KS + k];
+        c0r += av.x * b0[k].x - av.y * b0[k].y;
+        c0i += av.x * b0[k].y + av.y * b0[k].x;
+        c1r += av.x * b1[k].x - av.y * b1[k].y;
+        c1i += av.x * b1[k].y + av.y * b1[k].x;
+      }
+      mx = fmaxf(mx, fmaxf(fmaxf(fabsf(c0r), fabsf(c0i)), fmaxf(fabsf(c1r), fabsf(c1i))));
+      float4* dst = reinterpret_cast<float4*>(C + (m0 + i) * N + n);
+      *dst = make_float4(c0r, c0i, c1r, c1i);
+    }
+  }
+  if (a.rec_c) amax_commit_wg(mx, sl, a.rec_c, a.rec_c_step);
 }
 
 // ---------------------------------------------------------------------------------
@@ -721,47 +950,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
-  hi = __bf16(x);
-  lo = __bf16(x - float(hi));
-}
 
-typedef float f32x2v __attribute__((ext_vector_type(2)));
-
-// Fold per-lane maxima m >= 0 into the slice's kAmaxSlots slots amax[slice * step + j] with
-// atomic maxima on the float bits (non-negative floats order like their bits); the slot is
-// the workgroup index modulo kAmaxSlots, which spreads the atomics of a large output over
-// many addresses, and readers take the maximum over the slots (amax_read).  Every lane of
-// the wave calls this; a lane without an element passes slice = -1.  When the lanes with an
-// element share one slice the wave reduces first and issues one atomic.
-__device__ __forceinline__ void amax_commit(float m, int64_t slice, uint32_t* amax, int step) {
-  amax += blockIdx.x & (kAmaxSlots - 1);
-  int64_t s0 = slice;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const int64_t o = __shfl_xor(s0, off);
-    s0 = s0 > o ? s0 : o;
-  }
-  if (s0 < 0) return;
-  if (__all(slice == s0 || slice < 0)) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
-    if ((threadIdx.x & 63) == 0 && m > 0.f) atomicMax(amax + s0 * step, __float_as_uint(m));
-  } else if (slice >= 0 && m > 0.f) {
-    atomicMax(amax + slice * step, __float_as_uint(m));
-  }
-}
-
-// maximum over a slice's kAmaxSlots slots (lane j reads slot j; every lane gets the result)
-__device__ __forceinline__ uint32_t amax_read(const uint32_t* slots) {
-  uint32_t v = slots[threadIdx.x & (kAmaxSlots - 1)];
-#pragma unroll
-  for (int off = kAmaxSlots / 2; off > 0; off >>= 1) {
-    const uint32_t o = __shfl_xor(v, off);
-    v = v > o ? v : o;
-  }
-  return v;
-}
 
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
@@ -792,11 +981,12 @@ __device__ __forceinline__ void split_pair(float2 x, uint32_t& hi, uint32_t& lo)
   lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf16x2));
 }
 
-// MODE 0: BF16 split while staging; 1: BF16 operands pre-split; 2: FP16 split of operands
-// scaled by a power of two per slice (from their largest component), undone on the output
+// MODE 0: BF16 split while staging; 2: FP16 split of operands scaled by a power of two
+// per slice that brings their largest component to [2^13, 2^14) (scale records: the output
+// keeps the product of the two scales, recorded in its exponent)
 template <int WAVES_M, int WAVES_N, int UM, int UN, bool A_MFAST, bool B_NFAST, int MODE>
 __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
-  constexpr bool PRESPLIT = (MODE == 1), F16 = (MODE == 2);
+  constexpr bool F16 = (MODE == 2);
   static_assert(WAVES_M * WAVES_N == 4, "four waves per workgroup");
   constexpr int BK = 16;                       // complex k per LDS stage (two MFMA steps)
   constexpr int BM = WAVES_M * UM * 32;
@@ -816,23 +1006,10 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int wm = wave % WAVES_M, wn = wave / WAVES_M;
-  // FP16: operand scales 2^(13 - e) for a largest component in [2^e, 2^(e+1)); e is read
-  // from the exponent field and clamped to [-110, 127] (zero, subnormal or infinite maxima),
-  // so every scale and inverse scale is a normal FP32 power of two
-  float sc_a = 1.f, sc_b = 1.f, us_a = 1.f, us_b = 1.f;
-  if (F16) {
-    auto expo = [](uint32_t bits) {
-      const int e = int((bits >> 23) & 0xffu) - 127;
-      return e < -110 ? -110 : (e > 127 ? 127 : e);
-    };
-    auto pow2 = [](int k) { return __uint_as_float(uint32_t(127 + k) << 23); };
-    const int ea = expo(amax_read(a.amax_a + t.sl * a.amax_a_step));
-    const int eb = expo(amax_read(a.amax_b + t.sl * a.amax_b_step));
-    sc_a = pow2(13 - ea);
-    sc_b = pow2(13 - eb);
-    us_a = pow2(ea - 13);
-    us_b = pow2(eb - 13);
-  }
+  // operand scales from the scale records: FP16 always (hi below 2^14, far from FP16's
+  // limit), BF16 (FP32's exponent range) only for operands far from 1
+  float sc_a = 1.f, sc_b = 1.f;
+  if (a.rec_c) rec_scales(a, t.sl, F16, t.first_of_slice(), sc_a, sc_b);
 
   f32x16 acc[UM][UN];
 #pragma unroll
@@ -870,26 +1047,13 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
     __bf16* bh = al + A_PLANE;
     __bf16* bl = bh + B_PLANE;
     uint32_t wh[A_LD + B_LD], wl[A_LD + B_LD];   // packed (re, im) hi and lo words
-    if (PRESPLIT) {
-      // operands already hold (re_hi, im_hi | re_lo, im_lo) as two 32-bit words per element
-#pragma unroll
-      for (int i = 0; i < A_LD; ++i) {
-        const uint2 w = __builtin_bit_cast(uint2, ra[i]);
-        wh[i] = w.x;
-        wl[i] = w.y;
-      }
-#pragma unroll
-      for (int i = 0; i < B_LD; ++i) {
-        const uint2 w = __builtin_bit_cast(uint2, rb[i]);
-        wh[A_LD + i] = w.x;
-        wl[A_LD + i] = w.y;
-      }
-    } else if (F16) {
+    if (F16) {
 #pragma unroll
       for (int i = 0; i < A_LD; ++i) split_pair_f16(ra[i], sc_a, wh[i], wl[i]);
 #pragma unroll
       for (int i = 0; i < B_LD; ++i) split_pair_f16(rb[i], sc_b, wh[A_LD + i], wl[A_LD + i]);
     } else {
+      if (sc_a != 1.f || sc_b != 1.f) Tile::scale(sc_a, sc_b, ra, rb);
 #pragma unroll
       for (int i = 0; i < A_LD + B_LD; ++i) split_pair(i < A_LD ? ra[i] : rb[i - A_LD], wh[i], wl[i]);
     }
@@ -995,45 +1159,19 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
     __syncthreads();
     stage ^= 1;
   }
-  if (F16) {
-#pragma unroll
-    for (int i = 0; i < UM; ++i)
-#pragma unroll
-      for (int jj = 0; jj < UN; ++jj)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) acc[i][jj][v] = acc[i][jj][v] * us_a * us_b;
-    if (a.amax_c && a.k_splits == 1)
-      amax_commit(t.template acc_absmax<UM, UN>(a, acc, wm * UM * 32, wn * UN * 16), t.sl,
-                  a.amax_c, a.amax_c_step);
-  }
+  if (a.rec_c && a.k_splits == 1)
+    amax_commit_wg(Tile::template acc_absmax<UM, UN>(acc), t.sl, a.rec_c, a.rec_c_step);
   t.template store_acc<UM, UN>(a, acc, wm * UM * 32, wn * UN * 16);
 }
 
-// largest |re|, |im| of each slice copy: grid-stride maximum, wave reduction, one unsigned
-// atomic maximum per wave on the float's bits (non-negative floats order like their bits)
-__global__ __launch_bounds__(kThreads) void k_absmax(const float2* X, int64_t elems, int64_t sstride,
-                                                    uint32_t* out, int out_step) {
-  const int64_t s = blockIdx.y;
-  const float2* x = X + s * sstride;
-  float m = 0.f;
-  for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < elems;
-       i += int64_t(gridDim.x) * kThreads) {
-    const float2 v = x[i];
-    m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
-  if ((threadIdx.x & 63) == 0)
-    atomicMax(out + s * out_step + (blockIdx.x & (kAmaxSlots - 1)), __float_as_uint(m));
-}
-
 __global__ __launch_bounds__(kThreads) void k_zero_u32(uint32_t* p, int64_t n) {
-  const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-  if (i < n) p[i] = 0u;
+  for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n;
+       i += int64_t(gridDim.x) * kThreads)
+    p[i] = 0u;
 }
 
 __global__ __launch_bounds__(kThreads) void k_reduce(ReduceArgs a) {
-  if (a.amax) {
+  if (a.rec) {
     // wave-uniform trip count, so that every lane takes part in amax_commit
     for (int64_t b = int64_t(blockIdx.x) * kThreads + (threadIdx.x & ~63); b < a.elems;
          b += int64_t(gridDim.x) * kThreads) {
@@ -1051,7 +1189,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce(ReduceArgs a) {
         m = fmaxf(fabsf(s.x), fabsf(s.y));
         slice = i / a.slice_elems;
       }
-      amax_commit(m, slice, a.amax, a.amax_step);
+      amax_commit(m, slice, a.rec, a.rec_step);
     }
     return;
   }
@@ -1109,24 +1247,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce_wide(ReduceArgs a) {
       m = fmaxf(fabsf(t.x), fabsf(t.y));
       slice = i / a.slice_elems;
     }
-    if (a.amax) amax_commit(m, slice, a.amax, a.amax_step);
-  }
-}
-
-// out[i] = (bf16 re_hi, im_hi | bf16 re_lo, im_lo) of in[i]: hi = bf16(x), lo = bf16(x - hi)
-// (round to nearest even), packed low half first; same element offsets as the input.
-__global__ __launch_bounds__(kThreads) void k_split_bf16(const float2* in, uint2* out, int64_t n) {
-  for (int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x; i < n;
-       i += int64_t(gridDim.x) * kThreads) {
-    const float2 v = in[i];
-    __bf16 rh, rl, ih, il;
-    split_bf16(v.x, rh, rl);
-    split_bf16(v.y, ih, il);
-    const uint32_t hi = uint32_t(__builtin_bit_cast(uint16_t, rh)) |
-                        (uint32_t(__builtin_bit_cast(uint16_t, ih)) << 16);
-    const uint32_t lo = uint32_t(__builtin_bit_cast(uint16_t, rl)) |
-                        (uint32_t(__builtin_bit_cast(uint16_t, il)) << 16);
-    out[i] = make_uint2(hi, lo);
+    if (a.rec) amax_commit(m, slice, a.rec, a.rec_step);
   }
 }
 
@@ -1169,8 +1290,10 @@ __global__ __launch_bounds__(kThreads) void k_slice_sum(SliceSumArgs a) {
     double2 o = a.overwrite ? make_double2(0.0, 0.0) : *out;
     for (int64_t sl = 0; sl < a.nb; ++sl) {     // slice order, one rounding per slice
       const float2 v = a.F[sl * a.f_slice_stride + off];
-      o.x += double(v.x);
-      o.y += double(v.y);
+      // the stored values times 2^E (exact in FP64)
+      const double f = a.rec_f ? ldexp(1.0, int(a.rec_f[sl * a.rec_f_step + kRecExp])) : 1.0;
+      o.x += double(v.x) * f;
+      o.y += double(v.y) * f;
     }
     *out = o;
   }
@@ -1386,10 +1509,14 @@ int grid_for(int64_t work, int64_t per_block, int64_t cap = 8192) {
 template <int NK, int NN>
 hipError_t launch_stream_t(const StreamArgs& a, hipStream_t s) {
   const bool s_shared = (a.s_rows == 1 && a.gs == nullptr && a.s_slice_stride == 0);
+  const int64_t gy = a.nb < 65535 ? a.nb : 65535;
+  const int64_t gz = (a.nb + gy - 1) / gy;
   if (s_shared) {
-    const int64_t total = (a.rows << a.n_m) * a.nb;
-    hipLaunchKernelGGL((k_stream<NK, NN>), dim3(grid_for(total, kThreads, 65536)), dim3(kThreads),
-                       0, s, a);
+    const int64_t per_slice = a.rows << a.n_m;
+    const int64_t cap = a.nb >= 65536 ? 1 : 65536 / a.nb;
+    hipLaunchKernelGGL((k_stream<NK, NN>),
+                       dim3(unsigned(grid_for(per_slice, kThreads, cap)), unsigned(gy), unsigned(gz)),
+                       dim3(kThreads), 0, s, a);
     return hipGetLastError();
   }
   constexpr int KS = 1 << NK, NS = 1 << NN, E = KS * NS;
@@ -1407,8 +1534,6 @@ hipError_t launch_stream_t(const StreamArgs& a, hipStream_t s) {
     nsplit = int(ns < NS ? ns : NS);
     chunks = (a.rows + rw - 1) / rw;
   }
-  const int64_t gy = a.nb < 65535 ? a.nb : 65535;
-  const int64_t gz = (a.nb + gy - 1) / gy;
   hipLaunchKernelGGL((k_stream_rows<NK, NN>), dim3(unsigned(chunks), unsigned(gy), unsigned(gz)),
                      dim3(kThreads), 0, s, a, rw, nsplit);
   return hipGetLastError();
@@ -1443,16 +1568,17 @@ hipError_t launch_gemm_cfg(const GemmArgs& a, hipStream_t s) {
       default: hipLaunchKernelGGL((k_gemm<WM, WN, UM, UN, BK, true, true>), grid, dim3(kThreads), 0, s, a); break;
     }
   } else {
-    const int mode = a.precision == 1 ? 0 : (a.precision == 2 ? 1 : 2);
+    if (a.precision != 1 && a.precision != 3) return hipErrorInvalidValue;
+    const int mode = a.precision == 1 ? 0 : 2;
     switch (sel * 3 + mode) {
 #define TNC_SPLIT_CASE(S, MD, AF, BF)                                                          \
   case S * 3 + MD:                                                                            \
     hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, AF, BF, MD>), grid, dim3(kThreads), 0, s, a); \
     break;
-      TNC_SPLIT_CASE(0, 0, false, false) TNC_SPLIT_CASE(0, 1, false, false) TNC_SPLIT_CASE(0, 2, false, false)
-      TNC_SPLIT_CASE(1, 0, true, false) TNC_SPLIT_CASE(1, 1, true, false) TNC_SPLIT_CASE(1, 2, true, false)
-      TNC_SPLIT_CASE(2, 0, false, true) TNC_SPLIT_CASE(2, 1, false, true) TNC_SPLIT_CASE(2, 2, false, true)
-      TNC_SPLIT_CASE(3, 0, true, true) TNC_SPLIT_CASE(3, 1, true, true) TNC_SPLIT_CASE(3, 2, true, true)
+      TNC_SPLIT_CASE(0, 0, false, false) TNC_SPLIT_CASE(0, 2, false, false)
+      TNC_SPLIT_CASE(1, 0, true, false) TNC_SPLIT_CASE(1, 2, true, false)
+      TNC_SPLIT_CASE(2, 0, false, true) TNC_SPLIT_CASE(2, 2, false, true)
+      TNC_SPLIT_CASE(3, 0, true, true) TNC_SPLIT_CASE(3, 2, true, true)
 #undef TNC_SPLIT_CASE
       default: return hipErrorInvalidValue;
     }
@@ -1494,7 +1620,35 @@ hipError_t launch_gemm_n8(const GemmArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int NK>
+hipError_t launch_gemm_outer_k(const GemmArgs& a, hipStream_t s) {
+  const int64_t cols = a.N < kOuterCols ? a.N : kOuterCols;
+  const int64_t mrows = a.M < kOuterRows ? a.M : kOuterRows;
+  const int64_t blocks = (a.N / cols) * ((a.M + mrows - 1) / mrows);
+  const int64_t zs = a.rows * a.nb;
+  const int64_t gy = zs < 65535 ? zs : 65535;
+  const int64_t gz = (zs + gy - 1) / gy;
+  hipLaunchKernelGGL((k_gemm_outer<NK>), dim3(unsigned(blocks), unsigned(gy), unsigned(gz)),
+                     dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+// The short-K kernel: K <= 16, N >= 2, M a multiple of the staged rows (or smaller), no
+// row stacking and no split-K (the plan compiler only offers it then).
+hipError_t launch_gemm_outer(const GemmArgs& a, hipStream_t s) {
+  if (a.stk || a.k_splits != 1 || a.N < 2 || a.nk > 4) return hipErrorInvalidValue;
+  switch (a.nk) {
+    case 0: return launch_gemm_outer_k<0>(a, s);
+    case 1: return launch_gemm_outer_k<1>(a, s);
+    case 2: return launch_gemm_outer_k<2>(a, s);
+    case 3: return launch_gemm_outer_k<3>(a, s);
+    case 4: return launch_gemm_outer_k<4>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t s) {
+  if (a.config == 6) return launch_gemm_outer(a, s);
   if (a.config == 5) {
     if (a.precision == 0) return launch_gemm_n8(a, s);
     GemmArgs b = a;            // the split-precision kernels have no 8-wide tile
@@ -1511,25 +1665,8 @@ hipError_t launch_gemm(const GemmArgs& a, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_split_bf16(const float2* in, void* out, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_split_bf16, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, in,
-                     static_cast<uint2*>(out), n);
-  return hipGetLastError();
-}
-
 hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(n, kThreads)), dim3(kThreads), 0, s, p, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_absmax(const float2* X, int64_t elems, int64_t slice_stride, int64_t copies,
-                         uint32_t* out, int out_step, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(copies * out_step, kThreads)), dim3(kThreads), 0, s,
-                     out, copies * out_step);
-  int64_t bx = (elems + 4 * kThreads - 1) / (4 * kThreads);
-  bx = bx < 1 ? 1 : (bx > 1024 ? 1024 : bx);
-  hipLaunchKernelGGL(k_absmax, dim3(unsigned(bx), unsigned(copies)), dim3(kThreads), 0, s, X, elems,
-                     slice_stride, out, out_step);
   return hipGetLastError();
 }
 

@@ -99,10 +99,20 @@ namespace {
 
 enum Kind { K_PERMUTE = 0, K_GEMM = 1, K_STREAM = 2, K_LEAVES = 3, K_SUM = 4, K_REDUCE = 5, K_SPLIT = 6 };
 constexpr int kKinds = 7;
-// operand preparation launches (kind K_SPLIT): the BF16 hi/lo copy, the largest-component
-// pass of an operand whose producer does not record it, and the clearing of a slot that
-// the producing launch folds its output's largest component into
-enum SplitOp { SPLIT_BF16 = 0, SPLIT_AMAX = 1, SPLIT_ZERO = 2 };
+// kind K_SPLIT: the clearing of a block of scale records before their producers fold
+// their outputs' largest components into them
+enum SplitOp { SPLIT_ZERO = 2 };
+
+// Scale records (see kRecWords) live in three blocks: constants (the leaves' largest
+// components, measured on the host, exponent 0), one copy for the slice-invariant tensors
+// (cleared at the start of every call) and one per slice copy of a batch for the
+// slice-dependent ones (cleared at the start of every batch).
+enum RecBlock { REC_CONST = 0, REC_INV = 1, REC_DEP = 2 };
+struct Rec {
+  int block = REC_CONST;
+  int64_t index = 0;          // record number inside its block
+  bool per_slice = false;     // one record per slice copy (else one shared by every slice)
+};
 
 struct Buf {
   uint64_t bytes = 0;         // all copies
@@ -121,11 +131,10 @@ struct Launch {
   int b_in0 = -1, b_in1 = -1, b_out = -1, b_tmp = -1;
   int64_t g0 = -1, g1 = -1;   // byte offsets of row gathers in the constants block
   int64_t stk_off = -1, perm_off = -1;   // row-stacking tables (GEMM), same block
-  int b_amax_a = -1, b_amax_b = -1;      // FP16 split: largest component of A and B per slice
-  int b_amax_c = -1;                     // FP16 split: the output's, folded in by this launch
+  int rec_in0 = -1, rec_in1 = -1, rec_out = -1;   // scale records of the operands and result
   bool shared = false;        // slice-dependent, but the same for every slice of a batch
-  int split_op = 0;                      // K_SPLIT: SPLIT_BF16, SPLIT_AMAX or SPLIT_ZERO
-  int64_t n_elems = 0;        // elements per slice copy (split launches)
+  int split_op = 0;                      // K_SPLIT: SPLIT_ZERO
+  int64_t n_elems = 0;        // words per slice copy (record clearing)
   bool enabled = true;        // a split-K reduction is switched off when tuning drops split-K
   int max_splits = 1;         // split-K factor the partial buffer was sized for
   StreamArgs st{};
@@ -140,7 +149,7 @@ struct TState {
   std::vector<uint64_t> keys;
   bool dep = false;
   int buf = -1;
-  int amax = -1;                // FP16 split: buffer with the largest |re|, |im| per slice
+  int rec = -1;                 // scale record
   uint64_t dbits[2] = {0, 0};   // slice-id bits (sliced labels) the tensor depends on
   bool shared = false;          // dep, and none of its bits varies inside a batch
   bool per_slice() const { return dep && !shared; }
@@ -170,6 +179,9 @@ struct tnc_plan_s {
   int64_t n_slices() const { return int64_t(slice_ids.size() / 2); }
 
   std::vector<Buf> bufs;
+  std::vector<Rec> recs;
+  int rec_buf[3] = {-1, -1, -1};     // buffers of the three record blocks
+  int64_t rec_count[3] = {0, 0, 0};  // records per block (per slice copy)
   std::vector<uint8_t> consts;
   uint64_t consts_bytes = 0, ws_bytes = 0;
   std::vector<Launch> inv, dep;
@@ -350,6 +362,12 @@ struct Compiler {
           dense.push_back(full[j]);
       }
       s.dense = dense;
+      float mx = 0.f;
+      for (float v : host) mx = std::max(mx, std::fabs(v));
+      uint32_t bits;
+      std::memcpy(&bits, &mx, 4);
+      s.rec = new_rec(REC_CONST, false);
+      const_amax.push_back(bits);
       if (sl.empty()) {
         s.buf = const_buf(host.data(), host.size() * sizeof(float));
       } else {
@@ -434,8 +452,8 @@ struct Compiler {
   // Estimated fraction of the MFMA tile work that is useful, for P on the M side
   static double tile_fill(const TState& P, const TState& Q, const TState& C, int nm, int nn) {
     const int64_t M = int64_t(1) << nm, N = int64_t(1) << nn, rows = C.rows();
-    static const int64_t kBM[kConfigs] = {128, 128, 64, 128, 128, 128};
-    static const int64_t kBN[kConfigs] = {64, 16, 32, 128, 32, 8};
+    static const int64_t kBM[kConfigs] = {128, 128, 64, 128, 128, 128, 256};
+    static const int64_t kBN[kConfigs] = {64, 16, 32, 128, 32, 8, 512};
     int64_t m_eff = M;
     if (rows > 1 && Q.rows() == 1 && P.q == C.q && M >= 128) m_eff = M * rows;
     double fm;
@@ -451,23 +469,34 @@ struct Compiler {
     return fm * std::min(1.0, double(N) / double(kBN[cfg_n]));
   }
 
-  static constexpr int kConfigs = 6;   // GEMM tile configurations (see launch_gemm)
+  // GEMM tile configurations (see launch_gemm); 6 is the short-K vector kernel
+  static constexpr int kConfigs = 7;
 
   static bool stacking_enabled() {
     static const bool on = std::getenv("TNC_NO_STACK") == nullptr;
     return on;
   }
 
-  static void choose_tiles(GemmArgs& g, int64_t M, int64_t N, int64_t Kd, int64_t rows) {
+  // the short-K vector kernel (configuration 6) takes K <= 16 without row stacking
+  static bool outer_ok(const GemmArgs& g, bool stacked) { return g.nk <= 4 && !stacked; }
+
+  static void choose_tiles(GemmArgs& g, int64_t M, int64_t N, int64_t Kd, int64_t rows,
+                           bool stacked) {
     static const int group = std::getenv("TNC_GEMM_GROUP") ? std::atoi(std::getenv("TNC_GEMM_GROUP")) : 4;
     g.group_m = group;
     const char* force = std::getenv("TNC_GEMM_CONFIG");
     const char* blocks_env = std::getenv("TNC_SPLITK_BLOCKS");
     const int64_t target = blocks_env ? std::atoll(blocks_env) : 2048;
     g.config = (N <= 8) ? 5 : (N <= 16) ? 1 : (M <= 64 ? 2 : (N <= 32 ? 4 : 0));
-    if (force) g.config = std::min(kConfigs - 1, std::max(0, std::atoi(force)));
-    static const int64_t kBM[kConfigs] = {128, 128, 64, 128, 128, 128};
-    static const int64_t kBN[kConfigs] = {64, 16, 32, 128, 32, 8};
+    // short contraction, wide output of at least 2^22 elements: bound by writing C
+    if (outer_ok(g, stacked) && N >= 64 && double(M) * double(N) * double(rows) >= 4194304.0)
+      g.config = 6;
+    if (force) {
+      const int f = std::min(kConfigs - 1, std::max(0, std::atoi(force)));
+      if (f != 6 || outer_ok(g, stacked)) g.config = f;
+    }
+    static const int64_t kBM[kConfigs] = {128, 128, 64, 128, 128, 128, 256};
+    static const int64_t kBN[kConfigs] = {64, 16, 32, 128, 32, 8, 512};
     const int64_t BM = kBM[g.config], BN = kBN[g.config];
     const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN) * rows;
     g.k_splits = 1;
@@ -480,62 +509,40 @@ struct Compiler {
     }
   }
 
-  // Pre-splitting GEMM operands (instead of splitting while staging tiles) is off unless
-  // TNC_BF16_PRESPLIT is set: measured on MI355X it did not pay for its extra pass.
-  static bool presplit_wanted(int64_t M, int64_t N, int64_t K) {
-    static const bool on = std::getenv("TNC_BF16_PRESPLIT") != nullptr;
-    return on && M >= 256 && N >= 64 && K >= 128;
+  // a new scale record: slice-invariant tensors in the per-call block, slice-dependent
+  // ones in the per-batch block (one per slice copy unless shared by the batch)
+  int new_rec(int block, bool per_slice) {
+    Rec r;
+    r.block = block;
+    r.index = plan.rec_count[block]++;
+    r.per_slice = per_slice;
+    plan.recs.push_back(r);
+    return int(plan.recs.size() - 1);
   }
+  std::vector<uint32_t> const_amax;   // largest component of each constant record
 
-  // hi/lo BF16 copy of an operand for the split-precision GEMM (same element offsets);
-  // an operand shared by every slice is split once per call
-  int emit_split(const TState& T) {
-    Launch L;
-    L.kind = K_SPLIT;
-    L.inv = !T.dep;
-    L.b_in0 = T.buf;
-    L.b_out = new_buf(uint64_t(T.elems()) * 8, false, T.per_slice());
-    L.n_elems = T.elems();
-    L.bufs = {L.b_in0, L.b_out};
-    L.info = tnc_step_info{K_SPLIT, L.inv, T.rows(), int64_t(1) << T.dense.size(), 0, 0, 0.0,
-                           16.0 * double(T.elems())};
-    account(L);
-    list(L.inv).push_back(L);
-    return L.b_out;
-  }
-
-  // largest |re|, |im| of an operand for the FP16 split (one value per slice copy); an
-  // operand shared by every slice is measured once per call
-  int emit_amax(const TState& T) {
-    Launch L;
-    L.kind = K_SPLIT;
-    L.split_op = SPLIT_AMAX;
-    L.inv = !T.dep;
-    L.b_in0 = T.buf;
-    L.b_out = new_buf(4 * kAmaxSlots, false, T.per_slice());
-    L.n_elems = T.elems();
-    L.bufs = {L.b_in0, L.b_out};
-    L.info = tnc_step_info{K_SPLIT, L.inv, T.rows(), int64_t(1) << T.dense.size(), 0, 0, 0.0,
-                           8.0 * double(T.elems())};
-    account(L);
-    list(L.inv).push_back(L);
-    return L.b_out;
-  }
-
-  // slot for the largest component of a tensor about to be produced, cleared before the
-  // producing launch folds into it
-  int emit_amax_slot(bool inv, bool per_slice) {
-    Launch L;
-    L.kind = K_SPLIT;
-    L.split_op = SPLIT_ZERO;
-    L.inv = inv;
-    L.shared = !inv && !per_slice;
-    L.b_out = new_buf(4 * kAmaxSlots, false, per_slice);
-    L.bufs = {L.b_out};
-    L.info = tnc_step_info{K_SPLIT, inv, 1, 1, 0, 0, 0.0, 8.0};
-    account(L);
-    list(inv).push_back(L);
-    return L.b_out;
+  // the record blocks and their clearing launches, once every tensor has its record
+  void finish_records() {
+    std::vector<uint32_t> words(size_t(plan.rec_count[REC_CONST]) * kRecWords, 0u);
+    for (size_t i = 0; i < const_amax.size(); ++i)
+      for (int j = 0; j < kAmaxSlots; ++j) words[i * kRecWords + j] = const_amax[i];
+    if (!words.empty()) plan.rec_buf[REC_CONST] = const_buf(words.data(), words.size() * 4);
+    for (int blk : {REC_INV, REC_DEP}) {
+      if (plan.rec_count[blk] == 0) continue;
+      const uint64_t words_per_copy = uint64_t(plan.rec_count[blk]) * kRecWords;
+      // not listed in any launch's buffers: kept for the whole call
+      plan.rec_buf[blk] = new_buf(words_per_copy * 4, false, blk == REC_DEP);
+      Launch Z;
+      Z.kind = K_SPLIT;
+      Z.split_op = SPLIT_ZERO;
+      Z.inv = blk == REC_INV;
+      Z.b_out = plan.rec_buf[blk];
+      Z.n_elems = int64_t(words_per_copy);
+      Z.info = tnc_step_info{K_SPLIT, Z.inv, 1, int64_t(words_per_copy), 0, 0, 0.0,
+                             4.0 * double(words_per_copy)};
+      std::vector<Launch>& lst = list(Z.inv);
+      lst.insert(lst.begin(), Z);
+    }
   }
 
   TState step(TState& A, TState& B) {
@@ -595,6 +602,10 @@ struct Compiler {
       C.dense = MX;
       C.dense.insert(C.dense.end(), NS.begin(), NS.end());
       C.buf = new_buf(uint64_t(C.elems()) * 8, false, ps);
+      C.rec = new_rec(inv ? REC_INV : REC_DEP, ps);
+      L.rec_in0 = X.rec;
+      L.rec_in1 = S.rec;
+      L.rec_out = C.rec;
       a.x_slice_stride = sstride(X.buf);
       a.s_slice_stride = sstride(S.buf);
       a.c_slice_stride = sstride(C.buf);
@@ -704,7 +715,7 @@ struct Compiler {
     g.K = Kd;
     g.rows = rows;
     g.c_row_stride = c_row_stride;
-    choose_tiles(g, M, N, Kd, rows);
+    choose_tiles(g, M, N, Kd, rows, !stk.empty());
     if (!stk.empty()) {
       g.k_splits = 1;   // the split-K reduce assumes C in the launch's own layout
       g.k_chunk = Kd;
@@ -713,25 +724,12 @@ struct Compiler {
     }
     g.precision = 0;
     if (plan.precision != TNC_C64 && g.config == 5) g.config = 1;   // no 8-wide split tile
-    int amax_a = -1, amax_b = -1;
-    if (plan.precision == TNC_FP16X3) {
-      g.precision = 3;
-      if (P.amax < 0) P.amax = emit_amax(P);
-      if (Q.amax < 0) Q.amax = emit_amax(Q);
-      amax_a = P.amax;
-      amax_b = Q.amax;
-      C.amax = emit_amax_slot(inv, ps);
-    }
-    if (plan.precision == TNC_BF16X3) {
-      // fat products split each operand once (every output tile re-reads its panels);
-      // thin ones split while staging tiles into LDS
-      const bool fat = presplit_wanted(M, N, Kd);
-      g.precision = fat ? 2 : 1;
-      if (fat) {
-        pbuf = emit_split(P);
-        qbuf = emit_split(Q);
-      }
-    }
+    if (plan.precision == TNC_FP16X3) g.precision = 3;
+    if (plan.precision == TNC_BF16X3) g.precision = 1;
+    C.rec = new_rec(inv ? REC_INV : REC_DEP, ps);
+    L.rec_in0 = P.rec;
+    L.rec_in1 = Q.rec;
+    L.rec_out = C.rec;
     C.dense = cat(MP, NQ);
     C.buf = new_buf(uint64_t(C.elems()) * 8, false, ps);
     g.a_slice_stride = sstride(pbuf);
@@ -741,14 +739,6 @@ struct Compiler {
     L.b_in1 = qbuf;
     L.b_out = C.buf;
     L.bufs = {pbuf, qbuf, C.buf};
-    if (amax_a >= 0) {
-      L.b_amax_a = amax_a;
-      L.b_amax_b = amax_b;
-      L.b_amax_c = C.amax;
-      L.bufs.push_back(amax_a);
-      L.bufs.push_back(amax_b);
-      L.bufs.push_back(C.amax);
-    }
     int part = -1;
     L.max_splits = g.k_splits;
     if (g.k_splits > 1) {
@@ -772,10 +762,7 @@ struct Compiler {
       R.b_out = C.buf;
       R.bufs = {part, C.buf};
       R.rd.slice_elems = rows * M * N;
-      if (C.amax >= 0) {
-        R.b_amax_c = C.amax;
-        R.bufs.push_back(C.amax);
-      }
+      R.rec_out = C.rec;
       R.info = tnc_step_info{K_REDUCE, inv, rows, M, N, 0, 0.0,
                              8.0 * double(g.k_splits + 1) * double(rows * M * N)};
       account(R);
@@ -822,6 +809,7 @@ struct Compiler {
     L.kind = K_SUM;
     L.inv = false;
     L.b_in0 = F.buf;
+    L.rec_in0 = F.rec;
     L.bufs = {F.buf};
     L.info = tnc_step_info{K_SUM, 0, s.L, int64_t(1) << s.n_open, 0, 0, 0.0,
                            double(s.L << s.n_open) * (8.0 + 32.0)};
@@ -844,6 +832,7 @@ struct Compiler {
     plan.sample_chunk = std::max<int64_t>(plan.L, 65536);
     plan.b_samples = new_buf(uint64_t(plan.sample_chunk) * 8);
     plan.b_counter = new_buf(8);
+    finish_records();
   }
 };
 
@@ -951,6 +940,18 @@ struct Exec {
 
   int64_t* counter() const { return reinterpret_cast<int64_t*>(ws + p.bufs[p.b_counter].off); }
 
+  // scale record r (copy 0) and its step in words per slice copy
+  uint32_t* rec(int r) const {
+    if (r < 0) return nullptr;
+    const Rec& x = p.recs[size_t(r)];
+    return reinterpret_cast<uint32_t*>(ws + p.bufs[p.rec_buf[x.block]].off) + x.index * kRecWords;
+  }
+  int64_t rec_step(int r) const {
+    if (r < 0) return 0;
+    const Rec& x = p.recs[size_t(r)];
+    return x.per_slice ? p.rec_count[x.block] * kRecWords : 0;
+  }
+
   void check(hipError_t err) {
     if (err != hipSuccess) fail(TNC_E_HIP, std::string("kernel launch: ") + hipGetErrorString(err));
   }
@@ -975,6 +976,12 @@ struct Exec {
         a.gx = gat(L.g0);
         a.gs = gat(L.g1);
         a.nb = nb;
+        a.rec_x = rec(L.rec_in0);
+        a.rec_s = rec(L.rec_in1);
+        a.rec_c = rec(L.rec_out);
+        a.rec_x_step = rec_step(L.rec_in0);
+        a.rec_s_step = rec_step(L.rec_in1);
+        a.rec_c_step = rec_step(L.rec_out);
         err = launch_stream(a, st);
         break;
       }
@@ -987,14 +994,12 @@ struct Exec {
         a.gb = gat(L.g1);
         a.stk = gat(L.stk_off);
         a.perm = gat(L.perm_off);
-        if (L.b_amax_a >= 0) {
-          a.amax_a = reinterpret_cast<const uint32_t*>(ptr(L.b_amax_a));
-          a.amax_b = reinterpret_cast<const uint32_t*>(ptr(L.b_amax_b));
-          a.amax_a_step = p.bufs[L.b_amax_a].per_slice ? kAmaxSlots : 0;
-          a.amax_b_step = p.bufs[L.b_amax_b].per_slice ? kAmaxSlots : 0;
-          a.amax_c = reinterpret_cast<uint32_t*>(ptr(L.b_amax_c));
-          a.amax_c_step = p.bufs[L.b_amax_c].per_slice ? kAmaxSlots : 0;
-        }
+        a.rec_a = rec(L.rec_in0);
+        a.rec_b = rec(L.rec_in1);
+        a.rec_c = rec(L.rec_out);
+        a.rec_a_step = rec_step(L.rec_in0);
+        a.rec_b_step = rec_step(L.rec_in1);
+        a.rec_c_step = rec_step(L.rec_out);
         a.partial = L.b_tmp >= 0 ? ptr(L.b_tmp) : nullptr;
         a.nb = nb;
         err = launch_gemm(a, st);
@@ -1002,15 +1007,7 @@ struct Exec {
       }
       case K_SPLIT: {
         const int64_t copies = plan_copies(L, nb);
-        if (L.split_op == SPLIT_ZERO) {
-          err = launch_zero_u32(reinterpret_cast<uint32_t*>(ptr(L.b_out)), copies * kAmaxSlots, st);
-        } else if (L.split_op == SPLIT_AMAX) {
-          const int64_t sstride = p.bufs[L.b_in0].per_slice ? int64_t(p.bufs[L.b_in0].elems) : 0;
-          err = launch_absmax(ptr(L.b_in0), L.n_elems, sstride, copies,
-                              reinterpret_cast<uint32_t*>(ptr(L.b_out)), kAmaxSlots, st);
-        } else {
-          err = launch_split_bf16(ptr(L.b_in0), ptr(L.b_out), L.n_elems * copies, st);
-        }
+        err = launch_zero_u32(reinterpret_cast<uint32_t*>(ptr(L.b_out)), copies * L.n_elems, st);
         break;
       }
       case K_REDUCE: {
@@ -1018,10 +1015,8 @@ struct Exec {
         a.partial = ptr(L.b_in0);
         a.C = ptr(L.b_out);
         a.elems = L.rd.elems * nb;
-        if (L.b_amax_c >= 0) {
-          a.amax = reinterpret_cast<uint32_t*>(ptr(L.b_amax_c));
-          a.amax_step = p.bufs[L.b_amax_c].per_slice ? kAmaxSlots : 0;
-        }
+        a.rec = rec(L.rec_out);
+        a.rec_step = rec_step(L.rec_out);
         err = launch_reduce(a, st);
         break;
       }
@@ -1045,6 +1040,8 @@ struct Exec {
         a.row_of = reinterpret_cast<const int32_t*>(ws + p.row_of_off);
         a.overwrite = 0;
         a.nb = nb;
+        a.rec_f = rec(L.rec_in0);
+        a.rec_f_step = rec_step(L.rec_in0);
         err = launch_slice_sum(a, st);
         break;
       }
@@ -1365,6 +1362,10 @@ int autotune(tnc_plan_s& p, uint8_t* ws, hipStream_t st, int reps) {
   Exec e{p, ws, st};
   e.upload();
   e.check(launch_set_i64(e.counter(), 0, st));
+  // cleared scale records: the timed launches read defined (zero) largest components
+  for (int phase = 0; phase < 2; ++phase)
+    for (const Launch& L : phase == 0 ? p.inv : p.dep)
+      if (L.kind == K_SPLIT) e.launch(L, phase == 0 ? 1 : p.batch, nullptr, st, false);
   int changed = 0;
   hipEvent_t t0, t1;
   HIPCHK(hipEventCreate(&t0));
@@ -1389,11 +1390,13 @@ int autotune(tnc_plan_s& p, uint8_t* ws, hipStream_t st, int reps) {
       } else {
         // the planned choice is timed first, so that it survives ties
         std::vector<std::pair<int, int>> cands{best};
-        for (int cfg = 0; cfg < Compiler::kConfigs; ++cfg)
-          if (cfg != 5 || L.gm.precision == 0)
-          for (int sp = 1; sp <= L.max_splits; sp *= 2)
+        for (int cfg = 0; cfg < Compiler::kConfigs; ++cfg) {
+          if (cfg == 5 && L.gm.precision != 0) continue;
+          if (cfg == 6 && !Compiler::outer_ok(L.gm, L.stk_off >= 0)) continue;
+          for (int sp = 1; sp <= (cfg == 6 ? 1 : L.max_splits); sp *= 2)
             if ((sp == 1 || L.gm.K / sp >= 256) && std::make_pair(cfg, sp) != best)
               cands.push_back({cfg, sp});
+        }
         float best_ms = 1e30f;
         for (const auto& cand : cands) {
           {

@@ -12,6 +12,21 @@ namespace tnc {
 
 constexpr int kMaxRank = 40;
 
+// Scale records.  Every tensor carries, per slice copy, a record of kRecWords 32-bit words:
+// words 0..kAmaxSlots-1 hold float bits of the largest |re|, |im| of its stored values
+// (folded in by atomic maxima from many workgroups; readers take the maximum over the
+// slots), word kRecExp the int32 exponent E such that the tensor's true values are the
+// stored ones times 2^E.  A kernel contracting A and B multiplies them while loading by
+// 2^sA and 2^sB (exact powers of two chosen from their largest components), stores the
+// product as it comes out and records E_C = E_A + E_B - sA - sB; the FP64 slice sum
+// multiplies by 2^E.  This keeps every stored value inside the floating-point range of the
+// arithmetic however small the amplitudes of one slice become.  A null record pointer
+// turns the mechanism off for that launch.  Steps are in words per slice copy (0: one
+// record shared by every slice).
+constexpr int kAmaxSlots = 256;  // atomic-maximum slots per record
+constexpr int kRecExp = 256;     // word holding the exponent
+constexpr int kRecWords = 264;   // words per record (slots, exponent, padding)
+
 // C[r][m][n] = sum_k X[gx(r)][m (+) k] * S[gs(r)][k, n] for a small S (<= 2^6 x 2^4).
 // m enumerates X's free labels in X order; K positions in X are spread anywhere.
 struct StreamArgs {
@@ -31,6 +46,11 @@ struct StreamArgs {
   int8_t x_kins[6];           // X K positions ascending (zero-bit insertion order)
   int8_t s_kpos[6];           // k bit j -> S bit position
   int8_t s_npos[4];           // n bit j -> S bit position
+  // scale records of X, S and C (see kRecWords)
+  const uint32_t* rec_x;
+  const uint32_t* rec_s;
+  uint32_t* rec_c;
+  int64_t rec_x_step, rec_s_step, rec_c_step;
 };
 
 // C[r][m][n] = sum_k A[ga(r)][m,k] B[gb(r)][k,n] with C stored [M][N] row-major.
@@ -60,8 +80,7 @@ struct GemmArgs {
   float2* partial;
   int config;                 // tile configuration id
   int precision;              // 0: complex64 on FP32 MFMA; 1: BF16 hi+lo split in the kernel;
-                              // 2: BF16 hi+lo, operands already split by k_split_bf16;
-                              // 3: FP16 hi+lo of operands scaled by a power of two per slice
+                              // 3: FP16 hi+lo of operands scaled to [2^13, 2^14) per slice
   // Row stacking (stk != nullptr): output rows that share one B row are stacked along M.
   // M is then a multiple of 128 and each output row contributes 2^nm consecutive m; the
   // 128-row block b holds output rows perm[stk[3b]], ..., perm[stk[3b] + stk[3b+1] - 1]
@@ -70,17 +89,12 @@ struct GemmArgs {
   const int32_t* stk;
   const int32_t* perm;
   int group_m;                // tiles are numbered in groups of group_m tile rows (L2 reuse)
-  // precision 3 (FP16 hi+lo): largest |re|, |im| of A and B per slice, as float bits, the
-  // maximum over the kAmaxSlots slots amax_a[slice * amax_a_step + j] (step 0: operand
-  // shared by every slice, else kAmaxSlots)
-  const uint32_t* amax_a;
-  const uint32_t* amax_b;
-  int amax_a_step, amax_b_step;
-  // precision 3: when set and the launch writes C itself (k_splits == 1), the largest
-  // |re|, |im| of C per slice is folded into the slots amax_c[slice * amax_c_step + j] with
-  // atomic maxima (the slots are zero before the launch)
-  uint32_t* amax_c;
-  int amax_c_step;
+  // scale records of A, B and C (see kRecWords); with k_splits > 1 the reduction folds
+  // C's largest component in, the GEMM writes its exponent
+  const uint32_t* rec_a;
+  const uint32_t* rec_b;
+  uint32_t* rec_c;
+  int64_t rec_a_step, rec_b_step, rec_c_step;
 };
 
 struct ReduceArgs {           // C[i] = sum_s partial[s][i]  (i over every slice of the launch)
@@ -88,10 +102,10 @@ struct ReduceArgs {           // C[i] = sum_s partial[s][i]  (i over every slice
   float2* C;
   int64_t elems;
   int splits;
-  // optional: largest |re|, |im| of C per slice (slice = i / slice_elems) folded into
-  // amax[slice * amax_step] with an atomic maximum (the slots are zero before the launch)
-  uint32_t* amax;
-  int amax_step;
+  // optional: C's scale record; the largest |re|, |im| of C per slice (slice = i /
+  // slice_elems) is folded into its slots with atomic maxima
+  uint32_t* rec;
+  int64_t rec_step;
   int64_t slice_elems;
 };
 
@@ -131,20 +145,16 @@ struct SliceSumArgs {
   int n_open;
   int64_t open_stride[64];    // element stride of open qubit t (t = 0 is mu's top bit)
   int overwrite;
+  const uint32_t* rec_f;      // F's scale record (nullable): values times 2^E
+  int64_t rec_f_step;
 };
 
 // Launchers (return hipError_t of the launch).
 hipError_t launch_stream(const StreamArgs& a, hipStream_t s);
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t s);
-// out[s * out_step] = bits of max |re|, |im| over the `elems` elements of copy s of X
-// (copies at X + s * slice_stride), for s < copies
-constexpr int kAmaxSlots = 64;   // slots per slice of a largest-component record
+// p[0..n) = 0 (clears scale records before their producers fold into them)
 hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
-hipError_t launch_absmax(const float2* X, int64_t elems, int64_t slice_stride, int64_t copies,
-                         uint32_t* out, int out_step, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
-// out (8 bytes per element): bf16 (re_hi, im_hi) then (re_lo, im_lo) of each complex64 input
-hipError_t launch_split_bf16(const float2* in, void* out, int64_t n, hipStream_t s);
 hipError_t launch_slice_leaves(const SliceLeafArgs& a, int64_t total_elems, hipStream_t s);
 hipError_t launch_slice_sum(const SliceSumArgs& a, hipStream_t s);
 hipError_t launch_fill_zero(double* p, int64_t n_doubles, hipStream_t s);

@@ -28,7 +28,7 @@ TNC_E_INTERNAL = -7
 TNC_C64, TNC_FP16X3, TNC_BF16X3, TNC_FP16X3_3M, TNC_BF16X3_3M = range(5)
 
 KIND_NAMES = ("permute", "gemm", "stream", "slice_leaves", "slice_sum", "splitk_reduce",
-              "split_operand")
+              "scale_records")
 
 EXPORTS = (
     "tnc_last_error", "tnc_net_create", "tnc_net_set_path", "tnc_net_set_slices",

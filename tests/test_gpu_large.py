@@ -1,15 +1,18 @@
 """The 53-qubit share at full size (6x9 grid minus one site, 20 cycles, largest intermediate
 2^30, 2^14 groups x 6 open qubits = 2^20 amplitudes, 98 sliced bonds).
 
-The oracle cannot contract this network (its own greedy path for a single group peaks at
-2^26 to 2^33 elements depending on tie-breaks), so parity here is a property that holds at
-any size: the amplitudes of a group computed inside the sparse state (rows of all 2^14
-groups, gathered operand rows) equal those of a separate contraction with that group
-alone (no rows at all) - the same slices, the same path."""
+Oracle parity at full size: stored oracle amplitudes of single (slice, group) pairs
+(tests/golden, the oracle's own network for one group with the slice's bonds fixed,
+contracted along its seeded random-greedy path, which keeps every intermediate <= 2^26)
+against the same group inside the library's 2^14-group sparse state, contracted in the
+launch configuration bench.py times (one slice per launch sequence, autotuned tiles).
+Properties that hold at any size complete it: a group inside the sparse state equals a
+separate contraction with that group alone, and head reuse equals the plain plan."""
 
 import numpy as np
 import pytest
 
+import synth
 from oracle import metrics
 from tests.gpu_util import log, require_gpu
 
@@ -19,6 +22,38 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module", autouse=True)
 def _gpu():
     require_gpu()
+
+
+@pytest.mark.parametrize("form", [("c64", 0, 1e-5), ("bf16x3", 2, 1e-3), ("fp16x3", 1, 1e-5)],
+                         ids=["c64", "bf16x3", "fp16x3"])
+def test_large_pairs_match_stored_oracle(form):
+    """On the jittered twin of the share (same structure, plan and slices; at theta = pi/2
+    exactly most slices are exact zeros): each stored pair against its group inside the
+    2^14-group sparse state.  The amplitudes lie far below FP32's normal range, reached
+    through the per-slice scale records."""
+    from paper_2111_03011_amd.contractor import Contraction
+    from paper_2111_03011_amd.workload import config_workload, jittered_twin
+    from tests.golden_data import large_pairs
+    name, prec, tol = form
+    pairs, bonds, jitter = large_pairs()
+    j = synth.config("large")["parity_jitter"]
+    assert jitter == (j["theta_jitter"], j["jitter_seed"])
+    w = jittered_twin(config_workload("large"), *jitter)
+    assert [tuple(b) for b in w.sliced_bonds] == bonds, "the stored pairs were made for another slicing"
+    c = Contraction(w.net, w.plan.path, sliced_labels=w.plan.sliced_labels, slice_ids=w.slice_ids,
+                    open_qubits=w.open_qubits, closed_bits=w.closed_bits, max_batch_slices=1,
+                    precision=prec)
+    c.autotune(reps=1)
+    for p in pairs:
+        assert int(w.slice_ids[p.pos]) == p.slice_id and int(w.closed_bits[p.group]) == p.closed
+        log(f"large {name}: slice position {p.pos}, group {p.group} of 2^14")
+        c.contract_range(p.pos, 1)
+        got = c.amps[p.group].cpu().numpy()
+        err = metrics.rel_error(got, p.amps)
+        mx = metrics.max_error_over_rms(got, p.amps)
+        log(f"  rel err {err:.3e}, max err / rms {mx:.3e}, |amp| ~ {np.abs(p.amps).max():.1e}")
+        assert err <= tol and mx <= 10 * tol
+    c.close()
 
 
 def test_large_sparse_state_equals_single_groups():

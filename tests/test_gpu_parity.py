@@ -411,3 +411,72 @@ def test_every_tile_configuration(config, precision):
         log(f"  split-K {g[0].k_splits}: rel err {err:.3e}")
         assert err <= tol
         c.close()
+
+
+@pytest.mark.parametrize("precision", [0, 2, 1])
+@pytest.mark.parametrize("rank_a,rank_b,shared,interleave", [
+    (14, 16, 4, True),    # K = 16, N = 4096 wider than a workgroup's 512 columns
+    (12, 13, 3, False),   # K = 8, N = 1024
+    (11, 8, 1, True),     # K = 2, N = 128 (several output rows per pass)
+    (9, 6, 0, False),     # K = 1: an outer product
+    (8, 7, 2, True),      # K = 4, N = 32, M = 64 (one partial stage)
+])
+def test_short_k_vector_kernel(rank_a, rank_b, shared, interleave, precision):
+    """Configuration 6 (products with K <= 16 on the vector ALUs, chosen for wide outputs)
+    forced on pair products of several shapes, operands read in interleaved label orders;
+    every form computes it in FP32."""
+    import os
+    log(f"short-K kernel: ranks {rank_a}, {rank_b}, K 2^{shared}, precision {precision}")
+    fa = rank_a - shared
+    k = list(range(shared))
+    free_a = list(range(shared, shared + fa))
+    order_a = None
+    if interleave and shared:
+        order_a = []
+        for i in range(max(fa, shared)):
+            if i < fa:
+                order_a.append(free_a[i])
+            if i < shared:
+                order_a.append(k[i])
+    net = random_pair_network(rank_a, rank_b, shared, 900 + rank_a * 10 + rank_b, order_a, None)
+    ref = ocontract.contract_path(net.tensors, net.labels, [(0, 1)], net.out_label).reshape(-1)
+    os.environ["TNC_GEMM_CONFIG"] = "6"
+    try:
+        c = _contraction(net, [(0, 1)], open_qubits=list(range(net.n_qubits)), closed_bits=[0],
+                         precision=precision)
+    finally:
+        os.environ.pop("TNC_GEMM_CONFIG", None)
+    g = [l for l in c.launches() if l.kind == 1]
+    if not g:
+        c.close()
+        pytest.skip("this product runs as a small-operand stream")
+    assert len(g) == 1 and g[0].config == 6, [(l.config, l.m, l.n, l.k) for l in g]
+    c.contract()
+    err = metrics.rel_error(c.amps.cpu().numpy()[0], ref)
+    c.close()
+    log(f"  M {g[0].m} N {g[0].n} K {g[0].k}: rel err {err:.3e}")
+    assert err <= TOL
+
+
+def test_short_k_vector_kernel_rows_and_fold():
+    """Configuration 6 on sparse-state steps: output rows with gathered operand rows, and
+    rows folded into M, against the oracle's per-group contraction."""
+    import os
+    log("short-K kernel with rows")
+    for case in [(3, 7, 1, 6, 3, 12), (3, 7, 0, 6, 3, 8)]:
+        net, open_q, closed = _grouped_pair(*case, seed=77)
+        ref = _grouped_reference(net, open_q, closed)
+        os.environ["TNC_GEMM_CONFIG"] = "6"
+        try:
+            c = _contraction(net, [(0, 1)], open_qubits=open_q, closed_bits=closed)
+        finally:
+            os.environ.pop("TNC_GEMM_CONFIG", None)
+        g = [l for l in c.launches() if l.kind == 1]
+        if not g or g[0].config != 6:
+            c.close()
+            continue
+        c.contract()
+        err = metrics.rel_error(c.amps.cpu().numpy(), ref)
+        log(f"  case {case}: rows {g[0].rows} M {g[0].m} N {g[0].n} K {g[0].k} mode {g[0].row_mode}: rel err {err:.3e}")
+        c.close()
+        assert err <= TOL
