@@ -178,46 +178,70 @@ def timed_steps(c, w, args, steps: int, warmup: int, tag: str):
     return ms, norm
 
 
-def roofline(kt, precision: str, traffic):
-    """Dominant kernel by measured time: algorithmic work of its timed launches over their
-    summed durations (HIP events on the contraction stream)."""
-    dom = max(kt, key=lambda k: kt[k]["ms"])
-    d = kt[dom]
+def kernel_family(kind: int, config: int, precision: str) -> str:
+    """Name of the HIP kernel (template family) a launch of the plan runs."""
+    if kind == 1:
+        if config == 6:
+            return "k_gemm_outer"
+        if config == 5 and precision == "c64":
+            return "k_gemm_n8"
+        return "k_gemm" if precision == "c64" else "k_gemm_bf16x3"
+    return {2: "k_stream", 3: "k_slice_leaves", 4: "k_slice_sum", 5: "k_reduce",
+            6: "k_zero_u32"}.get(kind, f"kind{kind}")
+
+
+def roofline(rows, precision: str, traffic):
+    """Dominant kernel by measured time (summed over its timed launches): algorithmic work
+    of those launches over their summed durations (HIP event pairs on the contraction
+    stream around each launch)."""
+    fam = {}
+    for r in rows:
+        f = fam.setdefault(kernel_family(r["kind_id"], r["config"], precision),
+                           {"ms": 0.0, "flops": 0.0, "bytes": 0.0, "launches": 0})
+        f["ms"] += r["ms"] * r["count"]
+        f["flops"] += r["flops"] * r["count"]
+        f["bytes"] += r["bytes"] * r["count"]
+        f["launches"] += r["count"]
+    dom = max(fam, key=lambda k: fam[k]["ms"])
+    d = fam[dom]
     per = max(d["launches"], 1)
-    if dom == "gemm":
+    if dom in ("k_gemm", "k_gemm_n8"):
         algo = d["flops"] / (d["ms"] * 1e-3) / 1e12
-        if precision == "c64":
-            # one v_mfma_f32_32x32x2f32 per complex k: matrix-core flops = algorithmic flops
-            r = {"kernel": "k_gemm (complex64 on v_mfma_f32_32x32x2f32)", "bound": "mfma",
-                 "achieved": algo, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
-                 "frac": algo / (PEAK_FP32_MFMA / 1e12)}
-        else:
-            # three products (hi*hi, hi*lo, lo*hi) per algorithmic flop; FP16 and BF16 share
-            # one matrix-core peak
-            mf = "f16" if precision == "fp16x3" else "bf16"
-            r = {"kernel": f"k_gemm_bf16x3 (v_mfma_f32_32x32x16_{mf}, 3 products)",
-                 "bound": "mfma", "achieved": 3 * algo, "peak": PEAK_BF16_MFMA / 1e12,
-                 "unit": "TFLOP/s", "frac": 3 * algo / (PEAK_BF16_MFMA / 1e12),
-                 "algorithmic_tflops": algo}
+        # one v_mfma_f32_32x32x2f32 (or 16x16x4) per complex k: matrix-core flops =
+        # algorithmic flops
+        r = {"kernel": f"{dom} (complex64 on v_mfma_f32)", "bound": "mfma", "achieved": algo,
+             "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s", "frac": algo / (PEAK_FP32_MFMA / 1e12)}
+    elif dom == "k_gemm_bf16x3":
+        # three products (hi*hi, hi*lo, lo*hi) per algorithmic flop; FP16 and BF16 share one
+        # matrix-core peak
+        algo = d["flops"] / (d["ms"] * 1e-3) / 1e12
+        mf = "f16" if precision == "fp16x3" else "bf16"
+        r = {"kernel": f"k_gemm_bf16x3 (v_mfma_f32_32x32x16_{mf}, 3 products)",
+             "bound": "mfma", "achieved": 3 * algo, "peak": PEAK_BF16_MFMA / 1e12,
+             "unit": "TFLOP/s", "frac": 3 * algo / (PEAK_BF16_MFMA / 1e12),
+             "algorithmic_tflops": algo}
     else:
         gbs = d["bytes"] / (d["ms"] * 1e-3) / 1e9
-        r = {"kernel": f"k_{dom}", "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM / 1e9,
+        r = {"kernel": dom, "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM / 1e9,
              "unit": "GB/s", "frac": gbs / (PEAK_HBM / 1e9)}
     r.update({"traffic": traffic, "launches_timed": d["launches"],
               "avg_launch_ms": d["ms"] / per,
               "algorithmic_flops_per_launch": d["flops"] / per,
-              "algorithmic_bytes_per_launch": d["bytes"] / per})
+              "algorithmic_bytes_per_launch": d["bytes"] / per,
+              "time_by_kernel_ms": {k: round(v["ms"], 3) for k, v in
+                                    sorted(fam.items(), key=lambda kv: -kv[1]["ms"])}})
     return r
 
 
 KIND = {1: "gemm", 2: "stream", 3: "slice_leaves", 4: "slice_sum", 5: "splitk_reduce",
         6: "scale_records"}
-TILE = {0: "128x64", 1: "128x16", 2: "64x32", 3: "128x128", 4: "128x32", 5: "128x8"}
+TILE = {0: "128x64", 1: "128x16", 2: "64x32", 3: "128x128", 4: "128x32", 5: "128x8",
+        6: "vector"}
 
 
 def step_classes(c) -> dict:
     """Per launch of the plan (timed launches only): kind, shape, time, algorithmic
-    TFLOP/s and GB/s; summarised by class - GEMMs above the FP32 ridge (MFMA-bound by
+    TFLOP/s and GB/s of the launch (all the slices it processes); summarised by class - GEMMs above the FP32 ridge (MFMA-bound by
     their arithmetic intensity) and the rest (HBM-bound)."""
     rows = []
     infos = c.launches()
@@ -226,8 +250,14 @@ def step_classes(c) -> dict:
             continue
         s = infos[i]
         t = ms / n
+        # per-slice work times the slices one launch processes (a full batch, or one copy
+        # for steps run once per call or per batch)
+        per = c.batch_slices if s.invariant == 0 else 1
+        s.flops *= per
+        s.bytes *= per
         inten = s.flops / max(s.bytes, 1.0)
-        rows.append({"i": i, "kind": KIND.get(s.kind, str(s.kind)), "inv": s.invariant,
+        rows.append({"i": i, "kind": KIND.get(s.kind, str(s.kind)), "kind_id": s.kind,
+                     "config": s.config, "flops": s.flops, "bytes": s.bytes, "inv": s.invariant,
                      "rows": s.rows, "m": s.m, "n": s.n, "k": s.k,
                      "tile": TILE.get(s.config, "-") if s.kind == 1 else "-",
                      "splits": s.k_splits, "row_mode": s.row_mode, "ms": t, "count": n,
@@ -449,7 +479,8 @@ def sliced_extra(args, refs=None) -> dict:
         r = {"ms_per_step": percentiles(ms), "amplitudes_per_s": w.n_amplitudes / (np.median(ms) * 1e-3),
              "tflops": c.work() / (np.median(ms) * 1e-3) / 1e12}
         if name == "c64":
-            r["roofline"] = roofline(c.timing(reset=True), "c64", None)
+            r["roofline"] = roofline(step_classes(c)[1], "c64", None)
+            c.timing(reset=True)
             c.set_timing(False)
         c.contract()
         amps = c.amps.cpu().numpy()[0].copy()
@@ -614,6 +645,35 @@ def write_traffic(args, batch: int, fetch_csv, write_csv):
     print(json.dumps(rec))
 
 
+def summarise_stats(path: str) -> None:
+    """Markdown table of a rocprofv3 --stats kernel summary (kernel_stats.csv), one line per
+    kernel template instance and one per kernel family (template arguments dropped)."""
+    import csv
+    rows = list(csv.DictReader(open(path)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows) or 1.0
+
+    def short(name):
+        # "void tnc::(anonymous namespace)::k_gemm<2, 2, ...>(tnc::GemmArgs)" -> "k_gemm<2, 2, ...>"
+        import re
+        m = re.search(r"(k_\w+|__amd_\w+)(<[^()]*>)?", name)
+        return (m.group(1) + (m.group(2) or "")) if m else name
+
+    fam = {}
+    print("| kernel | calls | total ms | avg us | share % |")
+    print("|---|---|---|---|---|")
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        n, calls, t = short(r["Name"]), int(r["Calls"]), float(r["TotalDurationNs"])
+        f = fam.setdefault(n.split("<")[0].split("(")[0], [0, 0.0])
+        f[0] += calls
+        f[1] += t
+        if t / tot >= 0.001:
+            print(f"| `{n}` | {calls} | {t / 1e6:.2f} | {t / calls / 1e3:.2f} | {100 * t / tot:.2f} |")
+    print("\n| kernel family | calls | total ms | avg us | share % |")
+    print("|---|---|---|---|---|")
+    for n, (calls, t) in sorted(fam.items(), key=lambda kv: -kv[1][1]):
+        print(f"| `{n}` | {calls} | {t / 1e6:.2f} | {t / calls / 1e3:.2f} | {100 * t / tot:.2f} |")
+
+
 def serving_main(args):
     """Poisson request stream through libtnc's server; one JSON line with throughput and
     latency percentiles (latency = server completion time - submission time)."""
@@ -731,6 +791,8 @@ def main():
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE counter files of a run "
                          "with --copy-calibration into the traffic record, then exit")
+    ap.add_argument("--summarise-stats", metavar="KERNEL_STATS_CSV",
+                    help="print a markdown summary of a rocprofv3 --stats kernel file, then exit")
     ap.add_argument("--requests", type=int, default=400, help="serving: requests in the stream")
     ap.add_argument("--templates", type=int, default=16, help="serving: distinct request templates")
     ap.add_argument("--slots", type=int, default=8, help="serving: concurrent requests")
@@ -740,6 +802,8 @@ def main():
                     help="serving: slices per launch sequence (0 = chosen per request)")
     args = ap.parse_args()
     batch = args.batch or {"large": 8 if args.reuse else 1, "sliced": 64, "small": 1}.get(args.workload, 1)
+    if args.summarise_stats:
+        return summarise_stats(args.summarise_stats)
     if args.write_traffic:
         if not args.copy_calibration:
             sys.exit("--write-traffic needs the --copy-calibration size the passes used")
@@ -800,7 +864,7 @@ def main():
     if args.step_table:
         write_step_table(args.step_table, table,
                          f"per-launch times, {args.workload} workload, {args.precision}, batch {batch}")
-    roof = roofline(kt, args.precision, measured_traffic(args, batch))
+    roof = roofline(table, args.precision, measured_traffic(args, batch))
     share = {k: v["ms"] for k, v in kt.items() if v["launches"]}
     tot = sum(share.values()) or 1.0
     aps = w.n_amplitudes / (ms_step * 1e-3)
