@@ -236,7 +236,7 @@ def roofline(rows, precision: str, traffic):
 KIND = {1: "gemm", 2: "stream", 3: "slice_leaves", 4: "slice_sum", 5: "splitk_reduce",
         6: "scale_records"}
 TILE = {0: "128x64", 1: "128x16", 2: "64x32", 3: "128x128", 4: "128x32", 5: "128x8",
-        6: "vector"}
+        6: "vector", 7: "128x128w8", 8: "256x64w8"}
 
 
 def step_classes(c) -> dict:

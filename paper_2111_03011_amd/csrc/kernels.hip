@@ -68,15 +68,14 @@ __device__ __forceinline__ uint32_t amax_read(const uint32_t* slots) {
 // maxima meet in LDS and one atomic maximum goes out per workgroup.  Every thread of the
 // workgroup calls it (it synchronises the workgroup).
 __device__ __forceinline__ void amax_commit_wg(float m, int64_t slice, uint32_t* amax, int64_t step) {
-  __shared__ float red[kThreads / 64];
+  __shared__ float red[16];   // up to 16 waves per workgroup
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
   if (threadIdx.x == 0) {
     float w = red[0];
-#pragma unroll
-    for (int i = 1; i < kThreads / 64; ++i) w = fmaxf(w, red[i]);
+    for (int i = 1; i < int(blockDim.x >> 6); ++i) w = fmaxf(w, red[i]);
     if (w > 0.f)
       atomicMax(amax + slice * step + ((blockIdx.x + 7u * blockIdx.y + 13u * blockIdx.z) & (kAmaxSlots - 1)),
                 __float_as_uint(w));
@@ -349,13 +348,13 @@ __device__ __forceinline__ void rec_scales(const GemmArgs& a, int64_t sl, bool f
   if (writer && threadIdx.x == 0) a.rec_c[sl * a.rec_c_step + kRecExp] = uint32_t(ea + eb - sha - shb);
 }
 
-template <int BM, int BN, int BK, bool A_MFAST, bool B_NFAST, bool LDS_TAB>
+template <int BM, int BN, int BK, bool A_MFAST, bool B_NFAST, bool LDS_TAB, int NT = kThreads>
 struct GemmTile {
-  static constexpr int LBM = (BM == 128) ? 7 : (BM == 64 ? 6 : 5);
+  static constexpr int LBM = (BM == 256) ? 8 : (BM == 128) ? 7 : (BM == 64 ? 6 : 5);
   static constexpr int LBN = (BN == 128) ? 7 : (BN == 64 ? 6 : (BN == 32 ? 5 : (BN == 16 ? 4 : 3)));
   static constexpr int LBK = (BK == 16) ? 4 : (BK == 32 ? 5 : 3);
-  static constexpr int A_LD = BM * BK / kThreads;
-  static constexpr int B_LD = (BK * BN + kThreads - 1) / kThreads;
+  static constexpr int A_LD = BM * BK / NT;
+  static constexpr int B_LD = (BK * BN + NT - 1) / NT;
   static constexpr int kLev = kKLevels;
   static constexpr int kTab = 2 * kLev * 64;   // LDS table entries (A levels, then B levels)
 
@@ -374,23 +373,23 @@ struct GemmTile {
   // consecutive addresses of the operand's fastest index (coalesced loads); when that index
   // is m (n), a thread's slots are consecutive k of one row (column).
   __device__ __forceinline__ static int a_row(int i) {
-    const int q = threadIdx.x + i * kThreads;
+    const int q = threadIdx.x + i * NT;
     return A_MFAST ? int(threadIdx.x) % BM : q / BK;
   }
   __device__ __forceinline__ static int a_col(int i) {
-    const int q = threadIdx.x + i * kThreads;
+    const int q = threadIdx.x + i * NT;
     return A_MFAST ? (int(threadIdx.x) / BM) * A_LD + i : q % BK;
   }
   __device__ __forceinline__ static int b_kr(int i) {
-    const int q = threadIdx.x + i * kThreads;
-    return B_NFAST ? (BK * BN >= kThreads ? (int(threadIdx.x) / BN) * B_LD + i : q / BN) : q % BK;
+    const int q = threadIdx.x + i * NT;
+    return B_NFAST ? (BK * BN >= NT ? (int(threadIdx.x) / BN) * B_LD + i : q / BN) : q % BK;
   }
   __device__ __forceinline__ static int b_n(int i) {
-    const int q = threadIdx.x + i * kThreads;
-    return B_NFAST ? (BK * BN >= kThreads ? int(threadIdx.x) % BN : q % BN) : q / BK;
+    const int q = threadIdx.x + i * NT;
+    return B_NFAST ? (BK * BN >= NT ? int(threadIdx.x) % BN : q % BN) : q / BK;
   }
   __device__ __forceinline__ static bool b_slot(int i) {
-    return BK * BN % kThreads == 0 || threadIdx.x + i * kThreads < BK * BN;
+    return BK * BN % NT == 0 || threadIdx.x + i * NT < BK * BN;
   }
 
   __device__ __forceinline__ bool init(const GemmArgs& a, int32_t* lds_tab = nullptr) {
@@ -441,7 +440,7 @@ struct GemmTile {
     k_end = (k_begin + a.k_chunk < a.K) ? k_begin + a.k_chunk : a.K;
     nlev = a.nk > LBK ? (a.nk - LBK + 5) / 6 : 0;
     if (LDS_TAB && nlev > 0) {
-      for (int e = threadIdx.x; e < kTab; e += kThreads) {
+      for (int e = threadIdx.x; e < kTab; e += NT) {
         const int op = e / (kLev * 64), l = (e / 64) % kLev, d = e % 64;
         const int lo = LBK + 6 * l;
         const int nb = a.nk - lo < 0 ? 0 : (a.nk - lo > 6 ? 6 : a.nk - lo);
@@ -985,13 +984,14 @@ __device__ __forceinline__ void split_pair(float2 x, uint32_t& hi, uint32_t& lo)
 // per slice that brings their largest component to [2^13, 2^14) (scale records: the output
 // keeps the product of the two scales, recorded in its exponent)
 template <int WAVES_M, int WAVES_N, int UM, int UN, bool A_MFAST, bool B_NFAST, int MODE>
-__global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
+__global__ __launch_bounds__(WAVES_M * WAVES_N * 64) void k_gemm_bf16x3(GemmArgs a) {
   constexpr bool F16 = (MODE == 2);
-  static_assert(WAVES_M * WAVES_N == 4, "four waves per workgroup");
+  constexpr int NT = WAVES_M * WAVES_N * 64;   // four or eight waves
+  static_assert(NT == 256 || NT == 512, "four or eight waves per workgroup");
   constexpr int BK = 16;                       // complex k per LDS stage (two MFMA steps)
   constexpr int BM = WAVES_M * UM * 32;
   constexpr int BN = WAVES_N * UN * 16;
-  using Tile = GemmTile<BM, BN, BK, A_MFAST, B_NFAST, false>;
+  using Tile = GemmTile<BM, BN, BK, A_MFAST, B_NFAST, false, NT>;
   constexpr int A_LD = Tile::A_LD, B_LD = Tile::B_LD;
   constexpr int RS = 2 * BK;                   // bf16 per LDS row (32 real k, 64 bytes)
   constexpr int A_PLANE = BM * RS, B_PLANE = 2 * BN * RS;
@@ -1127,33 +1127,33 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16x3(GemmArgs a) {
     const __bf16* bl = bh + B_PLANE;
 #pragma unroll
     for (int kstep = 0; kstep < 2; ++kstep) {
-      bf16x8 xah[UM], xal[UM], xbh[UN], xbl[UN];
-#pragma unroll
-      for (int i = 0; i < UM; ++i) {
-        xah[i] = *reinterpret_cast<const bf16x8*>(&ah[a_rd[kstep][i]]);
-        xal[i] = *reinterpret_cast<const bf16x8*>(&al[a_rd[kstep][i]]);
-      }
+      // B fragments for the whole step, A fragments one tile row at a time (fewer live
+      // registers for the 4 x 4 tiles of the large configuration)
+      bf16x8 xbh[UN], xbl[UN];
 #pragma unroll
       for (int j = 0; j < UN; ++j) {
         xbh[j] = *reinterpret_cast<const bf16x8*>(&bh[b_rd[kstep][j]]);
         xbl[j] = *reinterpret_cast<const bf16x8*>(&bl[b_rd[kstep][j]]);
       }
 #pragma unroll
-      for (int i = 0; i < UM; ++i)
+      for (int i = 0; i < UM; ++i) {
+        const bf16x8 xah = *reinterpret_cast<const bf16x8*>(&ah[a_rd[kstep][i]]);
+        const bf16x8 xal = *reinterpret_cast<const bf16x8*>(&al[a_rd[kstep][i]]);
 #pragma unroll
         for (int j = 0; j < UN; ++j) {
           if constexpr (F16) {
-            const f16x8 ah8 = __builtin_bit_cast(f16x8, xah[i]), al8 = __builtin_bit_cast(f16x8, xal[i]);
+            const f16x8 ah8 = __builtin_bit_cast(f16x8, xah), al8 = __builtin_bit_cast(f16x8, xal);
             const f16x8 bh8 = __builtin_bit_cast(f16x8, xbh[j]), bl8 = __builtin_bit_cast(f16x8, xbl[j]);
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al8, bh8, acc[i][j], 0, 0, 0);
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah8, bl8, acc[i][j], 0, 0, 0);
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah8, bh8, acc[i][j], 0, 0, 0);
           } else {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xal[i], xbh[j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xah[i], xbl[j], acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xah[i], xbh[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xal, xbh[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xah, xbl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xah, xbh[j], acc[i][j], 0, 0, 0);
           }
         }
+      }
     }
     if (more) store(stage ^ 1);
     __syncthreads();
@@ -1647,8 +1647,44 @@ hipError_t launch_gemm_outer(const GemmArgs& a, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+// Configurations 7 and 8: eight-wave workgroups for the split-precision forms, each wave
+// with the 2 x 2 matrix-core tiles of configuration 0, so one workgroup covers 128 x 128
+// (7) or 256 x 64 (8) complex outputs and every staged operand byte feeds more matrix
+// instructions than with 128 x 64; 96 or 80 KB of LDS per workgroup; no row stacking.
+template <int WM, int WN>
+hipError_t launch_gemm_split_big_t(const GemmArgs& a, hipStream_t s) {
+  constexpr int UM = 2, UN = 2;
+  constexpr int BM = WM * UM * 32, BN = WN * UN * 16;
+  const int64_t tiles = ((a.M + BM - 1) / BM) * ((a.N + BN - 1) / BN);
+  const int64_t zs = a.rows * a.nb * a.k_splits;
+  const int64_t gy = zs < 65535 ? zs : 65535;
+  const int64_t gz = (zs + gy - 1) / gy;
+  const dim3 grid{unsigned(tiles), unsigned(gy), unsigned(gz)};
+  const int sel = (a.a_mfast ? 1 : 0) | (a.b_nfast ? 2 : 0);
+  const int mode = a.precision == 1 ? 0 : 2;
+  switch (sel * 3 + mode) {
+#define TNC_BIG_CASE(S, MD, AF, BF)                                                            \
+  case S * 3 + MD:                                                                            \
+    hipLaunchKernelGGL((k_gemm_bf16x3<WM, WN, UM, UN, AF, BF, MD>), grid, dim3(WM * WN * 64), 0, s, a); \
+    break;
+    TNC_BIG_CASE(0, 0, false, false) TNC_BIG_CASE(0, 2, false, false)
+    TNC_BIG_CASE(1, 0, true, false) TNC_BIG_CASE(1, 2, true, false)
+    TNC_BIG_CASE(2, 0, false, true) TNC_BIG_CASE(2, 2, false, true)
+    TNC_BIG_CASE(3, 0, true, true) TNC_BIG_CASE(3, 2, true, true)
+#undef TNC_BIG_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_split_big(const GemmArgs& a, hipStream_t s) {
+  if (a.stk || (a.precision != 1 && a.precision != 3)) return hipErrorInvalidValue;
+  return a.config == 7 ? launch_gemm_split_big_t<2, 4>(a, s) : launch_gemm_split_big_t<4, 2>(a, s);
+}
+
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t s) {
   if (a.config == 6) return launch_gemm_outer(a, s);
+  if (a.config == 7 || a.config == 8) return launch_gemm_split_big(a, s);
   if (a.config == 5) {
     if (a.precision == 0) return launch_gemm_n8(a, s);
     GemmArgs b = a;            // the split-precision kernels have no 8-wide tile

@@ -452,8 +452,8 @@ struct Compiler {
   // Estimated fraction of the MFMA tile work that is useful, for P on the M side
   static double tile_fill(const TState& P, const TState& Q, const TState& C, int nm, int nn) {
     const int64_t M = int64_t(1) << nm, N = int64_t(1) << nn, rows = C.rows();
-    static const int64_t kBM[kConfigs] = {128, 128, 64, 128, 128, 128, 256};
-    static const int64_t kBN[kConfigs] = {64, 16, 32, 128, 32, 8, 512};
+    static const int64_t kBM[kConfigs] = {128, 128, 64, 128, 128, 128, 256, 128, 256};
+    static const int64_t kBN[kConfigs] = {64, 16, 32, 128, 32, 8, 512, 128, 64};
     int64_t m_eff = M;
     if (rows > 1 && Q.rows() == 1 && P.q == C.q && M >= 128) m_eff = M * rows;
     double fm;
@@ -469,16 +469,19 @@ struct Compiler {
     return fm * std::min(1.0, double(N) / double(kBN[cfg_n]));
   }
 
-  // GEMM tile configurations (see launch_gemm); 6 is the short-K vector kernel
-  static constexpr int kConfigs = 7;
+  // GEMM tile configurations (see launch_gemm); 6 is the short-K vector kernel, 7 and 8
+  // the eight-wave 128 x 128 and 256 x 64 tiles of the split-precision forms
+  static constexpr int kConfigs = 9;
 
   static bool stacking_enabled() {
     static const bool on = std::getenv("TNC_NO_STACK") == nullptr;
     return on;
   }
 
-  // the short-K vector kernel (configuration 6) takes K <= 16 without row stacking
+  // the short-K vector kernel (configuration 6) takes K <= 16 without row stacking; the
+  // eight-wave tiles (configurations 7, 8) split-precision products without row stacking
   static bool outer_ok(const GemmArgs& g, bool stacked) { return g.nk <= 4 && !stacked; }
+  static bool big_ok(const GemmArgs& g, bool stacked) { return g.precision != 0 && !stacked; }
 
   static void choose_tiles(GemmArgs& g, int64_t M, int64_t N, int64_t Kd, int64_t rows,
                            bool stacked) {
@@ -493,10 +496,10 @@ struct Compiler {
       g.config = 6;
     if (force) {
       const int f = std::min(kConfigs - 1, std::max(0, std::atoi(force)));
-      if (f != 6 || outer_ok(g, stacked)) g.config = f;
+      if ((f != 6 || outer_ok(g, stacked)) && (f < 7 || big_ok(g, stacked))) g.config = f;
     }
-    static const int64_t kBM[kConfigs] = {128, 128, 64, 128, 128, 128, 256};
-    static const int64_t kBN[kConfigs] = {64, 16, 32, 128, 32, 8, 512};
+    static const int64_t kBM[kConfigs] = {128, 128, 64, 128, 128, 128, 256, 128, 256};
+    static const int64_t kBN[kConfigs] = {64, 16, 32, 128, 32, 8, 512, 128, 64};
     const int64_t BM = kBM[g.config], BN = kBN[g.config];
     const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN) * rows;
     g.k_splits = 1;
@@ -715,6 +718,9 @@ struct Compiler {
     g.K = Kd;
     g.rows = rows;
     g.c_row_stride = c_row_stride;
+    g.precision = 0;
+    if (plan.precision == TNC_FP16X3) g.precision = 3;
+    if (plan.precision == TNC_BF16X3) g.precision = 1;
     choose_tiles(g, M, N, Kd, rows, !stk.empty());
     if (!stk.empty()) {
       g.k_splits = 1;   // the split-K reduce assumes C in the launch's own layout
@@ -722,10 +728,7 @@ struct Compiler {
       L.stk_off = add_const(stk.data(), stk.size() * sizeof(int32_t));
       L.perm_off = add_const(perm.data(), perm.size() * sizeof(int32_t));
     }
-    g.precision = 0;
     if (plan.precision != TNC_C64 && g.config == 5) g.config = 1;   // no 8-wide split tile
-    if (plan.precision == TNC_FP16X3) g.precision = 3;
-    if (plan.precision == TNC_BF16X3) g.precision = 1;
     C.rec = new_rec(inv ? REC_INV : REC_DEP, ps);
     L.rec_in0 = P.rec;
     L.rec_in1 = Q.rec;
@@ -1393,6 +1396,7 @@ int autotune(tnc_plan_s& p, uint8_t* ws, hipStream_t st, int reps) {
         for (int cfg = 0; cfg < Compiler::kConfigs; ++cfg) {
           if (cfg == 5 && L.gm.precision != 0) continue;
           if (cfg == 6 && !Compiler::outer_ok(L.gm, L.stk_off >= 0)) continue;
+          if (cfg >= 7 && !Compiler::big_ok(L.gm, L.stk_off >= 0)) continue;
           for (int sp = 1; sp <= (cfg == 6 ? 1 : L.max_splits); sp *= 2)
             if ((sp == 1 || L.gm.K / sp >= 256) && std::make_pair(cfg, sp) != best)
               cands.push_back({cfg, sp});

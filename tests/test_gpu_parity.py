@@ -381,13 +381,15 @@ def test_degenerate_cases():
 
 
 @pytest.mark.parametrize("precision", [0, 1, 2])
-@pytest.mark.parametrize("config", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("config", [0, 1, 2, 3, 4, 5, 7, 8])
 def test_every_tile_configuration(config, precision):
     """Each GEMM tile configuration (forced with TNC_GEMM_CONFIG), without and with split-K
     (TNC_SPLITK_BLOCKS), on a product whose M and N are smaller than some tiles (partial
     tiles) and whose operands are read in interleaved label orders.  The split-precision
     forms have no 128x8 tile and take 128x16 for it."""
     import os
+    if config >= 7 and precision == 0:
+        pytest.skip("the eight-wave tiles are split-precision configurations")
     log(f"tile configuration {config}, precision {precision}")
     tol = {0: TOL, 1: 1e-5, 2: 1e-3}[precision]
     # A: 6 free labels interleaved with 10 shared; B: 4 free labels after the shared ones
@@ -480,3 +482,39 @@ def test_short_k_vector_kernel_rows_and_fold():
         log(f"  case {case}: rows {g[0].rows} M {g[0].m} N {g[0].n} K {g[0].k} mode {g[0].row_mode}: rel err {err:.3e}")
         c.close()
         assert err <= TOL
+
+
+@pytest.mark.parametrize("config", [7, 8])
+@pytest.mark.parametrize("precision", [2, 1])
+@pytest.mark.parametrize("order", ["plain", "interleaved"])
+def test_split_big_tile_full_and_partial(config, precision, order):
+    """The eight-wave split-precision tiles (7: 128 x 128, 8: 256 x 64 complex) on products
+    spanning several tiles in M and N, operands in plain and interleaved label orders,
+    without and with split-K."""
+    import os
+    shared = 9
+    free_a, free_b = 10, 9          # M = 1024, N = 512 with 10 and 9 free labels
+    k = list(range(shared))
+    fa = list(range(shared, shared + free_a))
+    order_a = None
+    if order == "interleaved":
+        order_a = [x for pair in zip(fa, k) for x in pair] + fa[len(k):]
+    net = random_pair_network(free_a + shared, free_b + shared, shared, 555 + precision, order_a, None)
+    ref = ocontract.contract_path(net.tensors, net.labels, [(0, 1)], net.out_label).reshape(-1)
+    tol = {1: 1e-5, 2: 1e-3}[precision]
+    for blocks in ("1", "1000000"):
+        os.environ["TNC_GEMM_CONFIG"] = str(config)
+        os.environ["TNC_SPLITK_BLOCKS"] = blocks
+        try:
+            c = _contraction(net, [(0, 1)], open_qubits=list(range(net.n_qubits)), closed_bits=[0],
+                             precision=precision)
+        finally:
+            os.environ.pop("TNC_GEMM_CONFIG", None)
+            os.environ.pop("TNC_SPLITK_BLOCKS", None)
+        g = [l for l in c.launches() if l.kind == 1]
+        assert len(g) == 1 and g[0].config == config
+        c.contract()
+        err = metrics.rel_error(c.amps.cpu().numpy()[0], ref)
+        c.close()
+        log(f"  tile {config}, precision {precision}, {order}, split-K {g[0].k_splits}: rel err {err:.3e}")
+        assert err <= tol
