@@ -443,6 +443,51 @@ def large_reuse(args, c64_aps) -> dict:
     return res
 
 
+def large_zigzag(args, tail_start: int = 19, count: int = 4) -> dict:
+    """The zigzag tail order (Method; Appendix E) on the 53-qubit share: the planner's total
+    work of a zigzag plan with its own slicing against the plain plans, and a zigzag plan
+    that slices the plain plan's bonds plus those its bound needs, run with the plain path
+    on that same slicing over the same `count` slices of the jittered twin (their sums must
+    agree; at pi/2 exactly the slices are structural zeros)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2111_03011_amd import planner
+    from paper_2111_03011_amd.workload import config_workload, jittered_twin, zigzag_pair
+    w = config_workload("large")
+    jit = synth.config("large")["parity_jitter"]
+    twin = jittered_twin(w, jit["theta_jitter"], jit["jitter_seed"])
+    zz = planner.zigzag_plan(w.net, w.open_qubits, w.closed_bits, tail_start, 30, trials=4,
+                             seed=1919)
+    wz, wp = zigzag_pair(twin, tail_start, 30, count, 1919)
+    free = planner.find_plan(w.net, w.open_qubits, w.closed_bits, max_log2=30, n_sliced=None,
+                             trials=4, seed=5)
+    res = {"tail_start": tail_start,
+           "planned_total_flops_log2": {"zigzag_own_slicing": float(np.log2(zz.total_flops)),
+                                        "plain_fewest_slices": float(np.log2(free.total_flops)),
+                                        "plain_98_bonds": float(np.log2(w.plan.total_flops))},
+           "sliced_bonds": {"zigzag_own": len(zz.sliced_labels), "plain_fewest": len(free.sliced_labels),
+                            "zigzag_on_plain": len(wz.plan.sliced_labels)},
+           "slices_run": count}
+    sums = {}
+    for tag, ww in (("zigzag", wz), ("plain_path", wp)):
+        c = contraction(ww, "c64", 1)
+        c.contract_range(0, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.contract()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0)
+        sums[tag] = c.amps.cpu().numpy().copy()
+        res[tag] = {"ms_per_slice": ms / count, "planned_flops_per_slice": ww.plan.cost.flops_per_slice,
+                    "peak_log2": ww.plan.cost.peak_log2, "launches": len(c.launches()),
+                    "tflops": c.work() / (ms * 1e-3) / 1e12}
+        c.close()
+        log(f"zigzag extra, {tag}: {ms / count:.1f} ms per slice")
+    res["sum_rel_diff"] = rel_error(sums["zigzag"], sums["plain_path"])
+    return res
+
+
 def xeb_vs_exact(c, w, exact, n_samples: int, seed: int) -> float:
     """Linear XEB (Appendix D) of n_samples draws from the contraction's amplitudes, scored
     with the exact probabilities |psi(s)|^2 of the stored state-vector amplitudes."""
@@ -935,6 +980,8 @@ def main():
         if args.head_reuse:
             out["head_reuse"] = large_reuse(args, aps)
             torch.cuda.empty_cache()
+        out["zigzag_tail"] = large_zigzag(args)
+        torch.cuda.empty_cache()
         out["sliced_5x6_m14"] = sliced_extra(args)
     print(json.dumps(out), flush=True)
 

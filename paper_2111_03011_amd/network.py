@@ -56,6 +56,7 @@ class TensorNetwork:
     labels: list = field(default_factory=list)       # list[list[int]]
     out_label: list = field(default_factory=list)    # [n_qubits]
     bond_label: dict = field(default_factory=dict)   # (q, j) -> label
+    cycle: list = field(default_factory=list)        # per tensor: cycle of its gate (-1: none)
 
     def ranks(self):
         return [len(l) for l in self.labels]
@@ -102,13 +103,13 @@ def circuit_network(circuit: dict, simplify: bool = True) -> TensorNetwork:
         next_label[0] += 1
         return next_label[0] - 1
 
-    tensors, labels = [], []
+    tensors, labels, cycles = [], [], []
     head = [np.array([1.0, 0.0], dtype=np.complex128) for _ in range(n)]  # state before 1st fSim
     pending = [np.eye(2, dtype=np.complex128) for _ in range(n)]          # 1q gates since last fSim
     last = [None] * n          # (tensor index, output label) of the last fSim on q
     n2q = [0] * n
     bond_of = {}               # label -> (q, j)
-    for layer in circuit["layers"]:
+    for cyc, layer in enumerate(circuit["layers"]):
         for q, name in enumerate(layer["oneq"]):
             u = _ONEQ[name]
             if last[q] is None:
@@ -150,6 +151,7 @@ def circuit_network(circuit: dict, simplify: bool = True) -> TensorNetwork:
                     pending[q] = np.eye(2, dtype=np.complex128)
             tensors.append(t)
             labels.append(labs)
+            cycles.append(cyc)
             idx = len(tensors) - 1
             for q, o in ((qa, oa), (qb, ob)):
                 bond_of[o] = (q, n2q[q])
@@ -161,6 +163,7 @@ def circuit_network(circuit: dict, simplify: bool = True) -> TensorNetwork:
             o = new_label()
             tensors.append(head[q].copy())
             labels.append([o])
+            cycles.append(-1)
             out_label[q] = o
         else:
             idx, o = last[q]
@@ -174,10 +177,11 @@ def circuit_network(circuit: dict, simplify: bool = True) -> TensorNetwork:
             scale *= complex(np.asarray(tensors[k]).reshape(()))
     tensors = [tensors[k] for k in keep]
     labels = [labels[k] for k in keep]
+    cycles = [cycles[k] for k in keep]
     if scale != 1.0:
         tensors[0] = tensors[0] * scale
     net = TensorNetwork(n_qubits=n, tensors=tensors, labels=labels, out_label=out_label,
-                        bond_label={v: k for k, v in bond_of.items()})
+                        bond_label={v: k for k, v in bond_of.items()}, cycle=cycles)
     if simplify:
         simplify_low_rank(net)
     return net
@@ -216,3 +220,5 @@ def simplify_low_rank(net: TensorNetwork) -> None:
     keep = [i for i, l in enumerate(net.labels) if l is not None]
     net.tensors = [net.tensors[i] for i in keep]
     net.labels = [list(net.labels[i]) for i in keep]
+    if net.cycle:
+        net.cycle = [net.cycle[i] for i in keep]

@@ -503,6 +503,127 @@ def order_for_reuse(net, plan: Plan, open_qubits, closed_bits, batch: int) -> Pl
     return Plan(path=plan.path, sliced_labels=order, cost=cost, n_slices=plan.n_slices)
 
 
+def zigzag_path(prob: Problem, cycles, tail_start: int, temperature: float = 0.0, seed: int = 0):
+    """Head-tail order with the zigzag tail (Method, zigzag paragraph; Appendix E).
+
+    Leaves of gates before cycle `tail_start` form the head, contracted by the greedy search
+    into one tensor, whose legs toward the tail are the head-tail interface.  The tail's
+    leaves are then absorbed into that tensor one at a time along chains of neighbouring
+    gates: the sweep starts at the interface and moves to a neighbour (a leaf sharing a bond
+    with the leaf absorbed last) at the same or a later cycle, complexity-greedily (fewest
+    multiply-adds, then smallest result), until it reaches the final state; there it turns
+    around and follows neighbours at earlier cycles back toward the interface, turns again,
+    and so on.  Where the leaf absorbed last has no free neighbour in either direction the
+    sweep restarts from the accumulator's cheapest neighbour; tail leaves joined to the
+    accumulator by no bond are absorbed last, smallest first."""
+    n = len(prob.dense)
+    head = [k for k in range(n) if cycles[k] < tail_start]
+    tail = [k for k in range(n) if cycles[k] >= tail_start]
+    leaf_dense = list(prob.dense)
+    dense, qm = list(prob.dense), list(prob.qmask)
+    path = []
+    acc = None
+    if head:
+        sub = Problem(dense=[dense[k] for k in head], qmask=[qm[k] for k in head], rows=prob.rows,
+                      label_ids=prob.label_ids)
+        for i, j in greedy_path(sub, temperature=temperature, seed=seed):
+            a, b = head[i], head[j]
+            path.append((a, b))
+            dense[a] ^= dense[b]
+            qm[a] |= qm[b]
+        alive = set(head)
+        for _, b in path:
+            alive.discard(b)
+        acc = min(alive)
+    rest = set(tail)
+    if acc is None:
+        if not rest:
+            return path
+        acc = min(rest, key=lambda k: (cycles[k], k))
+        rest.discard(acc)
+
+    def cheapest(cands):
+        def key(k):
+            macs = prob.rows(qm[acc] | qm[k]) << _popcount(dense[acc] | dense[k])
+            return (macs, prob.size(dense[acc] ^ dense[k], qm[acc] | qm[k]), k)
+        return min(cands, key=key)
+
+    direction, last = 1, None
+    while rest:
+        step = None
+        if last is not None:
+            for turn in (False, True):
+                d = -direction if turn else direction
+                nb = [k for k in rest if leaf_dense[k] & leaf_dense[last]
+                      and d * (cycles[k] - cycles[last]) >= 0]
+                if nb:
+                    direction, step = d, cheapest(nb)
+                    break
+        if step is None:
+            nb = [k for k in rest if dense[k] & dense[acc]]
+            if nb:
+                # (re)start at the interface side the sweep is heading from
+                edge = min(direction * cycles[k] for k in nb)
+                step = cheapest([k for k in nb if direction * cycles[k] == edge])
+            else:
+                step = min(rest, key=lambda k: (prob.size(dense[k], qm[k]), k))
+        path.append((acc, step))
+        dense[acc] ^= dense[step]
+        qm[acc] |= qm[step]
+        last = step
+        rest.discard(step)
+    return path
+
+
+def zigzag_plan(net, open_qubits, closed_bits, tail_start: int, max_log2: float,
+                base_sliced=(), trials: int = 4, seed: int = 0, temperature: float = 0.1,
+                rounds: int = 3) -> Plan:
+    """Head-tail plan with the zigzag tail (zigzag_path) under the size bound.
+
+    The head becomes one tensor, whose legs include every unsliced bond crossing the
+    head-tail interface, so the bound usually needs interface bonds sliced (the paper's
+    global slicing of the interface, Appendix B.2).  Bonds in `base_sliced` are sliced
+    first and keep the low slice-id bits (so a plan found by find_plan can be refined and
+    its slices compared); further bonds are chosen along the zigzag path as in find_plan
+    (choose_slices, then the path searched again on the sliced network) and take the
+    following bits.  Returns the trial with the lowest total flop count."""
+    n = net.n_qubits
+    base_sliced = list(base_sliced)
+    base = make_problem(net.labels, net.out_label, n, open_qubits, closed_bits, sliced=base_sliced)
+    pos = {x: i for i, x in enumerate(base.label_ids)}
+    bond_bits = 0
+    for x in set(net.bond_label.values()):
+        if x in pos:
+            bond_bits |= 1 << pos[x]
+    forbidden = ((1 << len(base.label_ids)) - 1) & ~bond_bits
+    ids = lambda bits: [base.label_ids[i] for i in range(len(base.label_ids)) if (bits >> i) & 1]
+    best = None
+    for t in range(trials):
+        temp, s = (0.0, seed) if t == 0 else (temperature, seed + 7919 * t)
+        path = zigzag_path(base, net.cycle, tail_start, temperature=temp, seed=s)
+        sliced = base_sliced
+        for _ in range(rounds):
+            extra, _ = choose_slices(base, path, max_log2, forbidden=forbidden)
+            sliced = base_sliced + ids(extra)
+            sp = make_problem(net.labels, net.out_label, n, open_qubits, closed_bits, sliced=sliced)
+            path2 = zigzag_path(sp, net.cycle, tail_start, temperature=temp, seed=s + 1)
+            c1, c2 = path_cost(sp, path), path_cost(sp, path2)
+            if c2.peak_log2 <= max_log2 + 1e-9 and (c1.peak_log2 > max_log2 + 1e-9 or
+                                                   c2.flops_per_slice < c1.flops_per_slice):
+                path = path2
+        sp = make_problem(net.labels, net.out_label, n, open_qubits, closed_bits, sliced=sliced)
+        leaves = {k for k, l in enumerate(net.labels) if any(x in sliced for x in l)}
+        cost = path_cost(sp, path, leaves)
+        if cost.peak_log2 > max_log2 + 1e-9:
+            continue
+        cand = Plan(path=path, sliced_labels=list(sliced), cost=cost, n_slices=1 << len(sliced))
+        if best is None or cand.total_flops < best.total_flops:
+            best = cand
+    if best is None:
+        raise RuntimeError("no zigzag plan met the size bound")
+    return best
+
+
 def validate_path(n_tensors: int, pairs):
     """Check a path in the (i, j) -> i format (Appendix E) against n_tensors leaves: every
     pair names two distinct live tensors.  Returns the ids still alive at the end."""

@@ -9,7 +9,7 @@ import numpy as np
 import synth
 
 from .network import TensorNetwork, circuit_network
-from .planner import Plan, find_plan, order_for_reuse
+from .planner import Plan, find_plan, make_problem, order_for_reuse, path_cost, zigzag_plan
 
 
 @dataclass
@@ -47,6 +47,24 @@ def make_workload(circuit: dict, open_qubits, closed_bits, max_log2: float = 26,
            else np.asarray(slice_ids, dtype=object))
     return Workload(name, circuit, net, list(open_qubits), np.asarray(closed_bits, np.uint64),
                     plan, ids)
+
+
+def make_zigzag_workload(circuit: dict, open_qubits, closed_bits, tail_start: int,
+                         max_log2: float = 26, reuse_batch: int = 1, trials: int = 4,
+                         seed: int = 0, name: str = "zigzag") -> Workload:
+    """Workload along a head-tail plan with the zigzag tail (planner.zigzag_plan), every
+    slice id enumerated.  reuse_batch > 1 then orders its sliced labels for head reuse
+    (order_for_reuse): the log2(reuse_batch) local labels on the low id bits, steps that
+    do not depend on them computed once per batch."""
+    net = circuit_network(circuit)
+    plan = zigzag_plan(net, open_qubits, closed_bits, tail_start, max_log2, trials=trials,
+                       seed=seed)
+    if reuse_batch > 1:
+        plan = order_for_reuse(net, plan, open_qubits, closed_bits, reuse_batch)
+    if len(plan.sliced_labels) > 24:
+        raise ValueError("too many slices to enumerate")
+    return Workload(name, circuit, net, list(open_qubits), np.asarray(closed_bits, np.uint64),
+                    plan, np.arange(plan.n_slices, dtype=np.uint64))
 
 
 def choose_holes(circuit: dict, n_holes: int, open_qubits, closed_bits, max_log2: float = 26,
@@ -159,6 +177,34 @@ def jittered_twin(w: Workload, theta_jitter: float, jitter_seed: int) -> Workloa
     if net.labels != w.net.labels:
         raise RuntimeError("the jittered network's structure differs from the workload's")
     return dataclasses.replace(w, circuit=c, net=net)
+
+
+def zigzag_pair(w: Workload, tail_start: int, max_log2: float, count: int, seed: int,
+                trials: int = 4):
+    """A zigzag plan of the workload's network (planner.zigzag_plan) that slices the
+    workload's bonds first (on the same low id bits) and further bonds as its own bound needs
+    (on the bits above), and the workload's own path put on that same slicing, so that both
+    sum the same slices.  Slice ids: the workload's ids with `count` seeded draws of the
+    further bits.  Returns (zigzag workload, plain-path workload)."""
+    import dataclasses
+    base = list(w.plan.sliced_labels)
+    zz = zigzag_plan(w.net, w.open_qubits, w.closed_bits, tail_start, max_log2,
+                     base_sliced=base, trials=trials, seed=seed)
+    sliced = zz.sliced_labels
+    n_extra = len(sliced) - len(base)
+    net = w.net
+    sp = make_problem(net.labels, net.out_label, net.n_qubits, w.open_qubits, w.closed_bits,
+                      sliced=sliced)
+    leaves = {k for k, l in enumerate(net.labels) if any(x in sliced for x in l)}
+    xs = synth.slice_subset(n_extra, count, seed)
+    ids = [int(w.slice_ids[i % len(w.slice_ids)]) | (int(x) << len(base)) for i, x in enumerate(xs)]
+    ids = np.asarray(ids, dtype=np.uint64 if len(sliced) <= 62 else object)
+    plain = Plan(path=w.plan.path, sliced_labels=sliced, cost=path_cost(sp, w.plan.path, leaves),
+                 n_slices=1 << len(sliced))
+    if plain.cost.peak_log2 > max_log2 + 1e-9:
+        raise RuntimeError("the workload's path exceeds the size bound on the zigzag slicing")
+    return (dataclasses.replace(w, plan=zz, slice_ids=ids),
+            dataclasses.replace(w, plan=plain, slice_ids=ids))
 
 
 def serving_template(seed: int, max_log2: float = 26, work_cap: float = 2e13,
