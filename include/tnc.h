@@ -259,9 +259,16 @@ tnc_status tnc_plan_launch_timing(tnc_plan plan, int32_t i, double* ms, int64_t*
  * alternating between requests), so requests that arrive while others are on the GPU start
  * as soon as room frees up and their kernels overlap on the device.  The amplitudes of a
  * request are the same whether it runs alone or among others (same program, same order of
- * the FP64 sum).  For a given server, calls may come from any host thread.  A request that
- * fails (a HIP error, an invalid argument found late) fails alone.  tnc_server_destroy
- * waits for device work already enqueued, then drops queued requests. */
+ * the FP64 sum).  The end of a request (its draws and the copies of amplitudes and draws to
+ * pinned host staging) is enqueued and polled like its chunks, so the server's thread never
+ * waits on one request while others could be fed.  For a given server, calls may come from
+ * any host thread.  A request that fails (a HIP error, an invalid argument found late)
+ * fails alone: its stream is drained, its arena block freed, and poll returns its status.
+ * Fault injection for tests: with TNC_FAULT=launch:N in the environment when the server is
+ * created, the N-th launch unit it enqueues (one batch of slice steps, eager or a graph
+ * replay, or the slice-invariant phase; counted over all requests) fails with TNC_E_HIP
+ * before anything of it is enqueued.  tnc_server_destroy waits for device work already
+ * enqueued, then drops queued requests. */
 typedef struct tnc_server_s* tnc_server;
 
 typedef struct {

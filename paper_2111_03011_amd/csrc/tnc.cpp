@@ -923,6 +923,16 @@ struct Exec {
   tnc_plan_s& p;
   uint8_t* ws;
   hipStream_t s;
+  // fault injection (servers created with TNC_FAULT=launch:N): launches left before the one
+  // that fails; null when off
+  int64_t* fault = nullptr;
+
+  // one launch unit (a batch of slice steps, eager or a graph replay, or the invariant phase)
+  // is about to be enqueued: the injected fault makes it fail before anything is enqueued
+  void tick() {
+    if (fault && *fault > 0 && --*fault == 0)
+      fail(TNC_E_HIP, "injected launch failure (TNC_FAULT)");
+  }
   float2* ptr(int b) const { return reinterpret_cast<float2*>(ws + p.bufs[b].off); }
   const int32_t* gat(int64_t off) const {
     return off < 0 ? nullptr : reinterpret_cast<const int32_t*>(ws + off);
@@ -1107,8 +1117,10 @@ struct Exec {
     const int64_t n_amp = p.L << p.n_open;
     if (!accumulate) check(launch_fill_zero(amps, 2 * n_amp, s));
     if (count <= 0) return;
-    if (!skip_invariant)
+    if (!skip_invariant) {
+      tick();
       for (auto& L : p.inv) launch(L, 1, amps, s, p.timing);
+    }
     check(launch_set_i64(counter(), first, s));
     const int64_t S = p.batch;
     static const bool no_graph = std::getenv("TNC_NO_GRAPH") != nullptr;
@@ -1125,6 +1137,7 @@ struct Exec {
     for (int64_t pos = 0, b = 0; pos < count; ++b) {
       const int64_t nb = run_length(p, first + pos, count - pos);
       const bool timed = p.timing && (b % stride == 0);
+      tick();
       if (timed || no_graph || nb < S) {
         batch(nb, amps, s, timed);
       } else {
@@ -1160,6 +1173,31 @@ void harvest(tnc_plan_s& p) {
   p.ev_used = 0;
 }
 
+// Launch the draws [done, done + c) of tnc_sample into the plan's sample buffer on `st`
+// (asynchronous) and return c; *d_out receives the buffer.  With several groups all L draws
+// are launched at once (done = 0); with one group at most sample_chunk, and the draw index
+// keeps counting across chunks.
+int64_t launch_draws(tnc_plan_s& p, uint8_t* ws, const double* amps, uint64_t seed, int64_t done,
+                     int64_t n_samples, hipStream_t st, const uint64_t** d_out) {
+  double* cum = reinterpret_cast<double*>(ws + p.bufs[p.b_cum].off);
+  uint64_t* dout = reinterpret_cast<uint64_t*>(ws + p.bufs[p.b_samples].off);
+  const uint64_t* closed = reinterpret_cast<const uint64_t*>(ws + p.closed_off);
+  const int32_t* openq = reinterpret_cast<const int32_t*>(ws + p.open_off);
+  *d_out = dout;
+  int64_t c = p.L;
+  hipError_t err;
+  if (p.L > 1) {
+    err = launch_sample(amps, p.L, p.n_open, closed, openq, p.n_qubits, seed, p.L, cum, dout, st);
+  } else {
+    c = std::min(p.sample_chunk, n_samples - done);
+    // shift the counter: uniform j uses state seed + (j + 1) gamma
+    const uint64_t seed_c = seed + uint64_t(done) * 0x9E3779B97F4A7C15ull;
+    err = launch_sample(amps, 1, p.n_open, closed, openq, p.n_qubits, seed_c, c, cum, dout, st);
+  }
+  if (err != hipSuccess) fail(TNC_E_HIP, hipGetErrorString(err));
+  return c;
+}
+
 // Draws of tnc_sample; synchronous on `st`.
 void sample_into(tnc_plan_s& p, uint8_t* ws, const double* amps, uint64_t seed, int64_t n_samples,
                  uint64_t* h_bits, hipStream_t st) {
@@ -1168,28 +1206,12 @@ void sample_into(tnc_plan_s& p, uint8_t* ws, const double* amps, uint64_t seed, 
     fail(TNC_E_INVALID, "with several groups, n_samples must equal the number of groups");
   Exec e{p, ws, st};
   e.upload();
-  double* cum = reinterpret_cast<double*>(ws + p.bufs[p.b_cum].off);
-  uint64_t* dout = reinterpret_cast<uint64_t*>(ws + p.bufs[p.b_samples].off);
-  const uint64_t* closed = reinterpret_cast<const uint64_t*>(ws + p.closed_off);
-  const int32_t* openq = reinterpret_cast<const int32_t*>(ws + p.open_off);
-  if (p.L > 1) {
-    hipError_t err = launch_sample(amps, p.L, p.n_open, closed, openq, p.n_qubits, seed, p.L, cum,
-                                   dout, st);
-    if (err != hipSuccess) fail(TNC_E_HIP, hipGetErrorString(err));
-    HIPCHK(hipMemcpyAsync(h_bits, dout, uint64_t(p.L) * 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    return;
-  }
-  // one group: draws j = 0..n-1 in chunks (the draw index keeps counting across chunks)
-  for (int64_t done = 0; done < n_samples; done += p.sample_chunk) {
-    const int64_t c = std::min(p.sample_chunk, n_samples - done);
-    // shift the counter: uniform j uses state seed + (j + 1) gamma
-    const uint64_t seed_c = seed + uint64_t(done) * 0x9E3779B97F4A7C15ull;
-    hipError_t err = launch_sample(amps, 1, p.n_open, closed, openq, p.n_qubits, seed_c, c, cum,
-                                   dout, st);
-    if (err != hipSuccess) fail(TNC_E_HIP, hipGetErrorString(err));
+  for (int64_t done = 0; done < n_samples;) {
+    const uint64_t* dout = nullptr;
+    const int64_t c = launch_draws(p, ws, amps, seed, done, n_samples, st, &dout);
     HIPCHK(hipMemcpyAsync(h_bits + done, dout, uint64_t(c) * 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    done += c;
   }
 }
 
@@ -1482,6 +1504,11 @@ struct Request {
   int slot = -1;
   int64_t next = 0, total = 0;
   std::deque<hipEvent_t> chunks;        // chunks in flight, oldest first
+  // end of the request: amplitudes and draws copied to the slot's pinned staging, polled
+  // through `fin` (draws in chunks of the plan's sample_chunk with one group)
+  bool finishing = false, amps_taken = false;
+  int64_t drawn = 0, last_draws = 0;
+  hipEvent_t fin = nullptr;
   ReqState state = R_QUEUED;
   std::vector<double> amps;
   std::vector<uint64_t> bits;
@@ -1503,6 +1530,9 @@ struct tnc_server_s {
   std::vector<hipStream_t> streams;
   std::vector<bool> slot_busy;
   std::vector<hipEvent_t> ev_free;
+  std::vector<uint8_t*> pin;                  // per slot: pinned host staging of results
+  std::vector<uint64_t> pin_cap;
+  int64_t fault_left = 0;                     // TNC_FAULT=launch:N (worker thread only)
   std::mutex mu;
   std::condition_variable cv;
   std::deque<Request*> pending;
@@ -1556,20 +1586,82 @@ struct tnc_server_s {
     return e;
   }
 
-  // enqueue the next chunk of slices, or finish the request once every chunk has completed
+  // pinned host staging of slot k, at least `bytes` (its earlier copies have completed)
+  uint8_t* staging(int k, uint64_t bytes) {
+    if (pin_cap[size_t(k)] < bytes) {
+      if (pin[size_t(k)]) HIPCHK(hipHostFree(pin[size_t(k)]));
+      pin[size_t(k)] = nullptr;
+      pin_cap[size_t(k)] = 0;
+      HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&pin[size_t(k)]), bytes, hipHostMallocDefault));
+      pin_cap[size_t(k)] = bytes;
+    }
+    return pin[size_t(k)];
+  }
+
+  uint64_t amp_bytes(const Request& r) const { return uint64_t(r.plan->L << r.plan->n_open) * 16; }
+
+  // enqueue the amplitudes' copy (first time) and the next chunk of draws with its copy, all
+  // into the slot's staging, and mark their completion with r.fin; nothing waits here
+  void enqueue_finish(Request& r, const double* amps, hipStream_t st) {
+    const int64_t per = r.plan->L > 1 ? r.plan->L : std::min(r.plan->sample_chunk, r.n_samples);
+    const uint64_t ab = amp_bytes(r), off_bits = align_up(ab);
+    uint8_t* h = staging(r.slot, off_bits + uint64_t(std::max<int64_t>(per, 0)) * 8);
+    if (!r.amps_taken) HIPCHK(hipMemcpyAsync(h, amps, ab, hipMemcpyDeviceToHost, st));
+    r.last_draws = 0;
+    if (r.drawn < r.n_samples) {
+      const uint64_t* dout = nullptr;
+      r.last_draws = launch_draws(*r.plan, arena + r.off, amps, r.seed, r.drawn, r.n_samples, st,
+                                  &dout);
+      HIPCHK(hipMemcpyAsync(h + off_bits, dout, uint64_t(r.last_draws) * 8,
+                            hipMemcpyDeviceToHost, st));
+    }
+    if (!r.fin) r.fin = get_event();
+    HIPCHK(hipEventRecord(r.fin, st));
+    r.finishing = true;
+  }
+
+  // enqueue the next chunk of slices; once every chunk has completed, the end of the request
+  // (draws and copies) is enqueued and polled like the chunks: the worker never waits on a
+  // request's stream, so other requests keep being fed meanwhile
   bool step(Request& r) {
+    uint8_t* ws = arena + r.off;
+    double* amps = reinterpret_cast<double*>(ws + align_up(r.ws_bytes));
+    hipStream_t st = streams[size_t(r.slot)];
+    if (r.finishing) {
+      const hipError_t q = hipEventQuery(r.fin);
+      if (q == hipErrorNotReady) return false;
+      if (q != hipSuccess) fail(TNC_E_HIP, std::string("request end: ") + hipGetErrorString(q));
+      const uint8_t* h = pin[size_t(r.slot)];
+      if (!r.amps_taken) {
+        r.amps.resize(amp_bytes(r) / 8);
+        std::memcpy(r.amps.data(), h, amp_bytes(r));
+        double nrm = 0;
+        for (double x : r.amps) nrm += x * x;
+        r.norm = nrm;
+        r.amps_taken = true;
+      }
+      if (r.last_draws > 0) {
+        std::memcpy(r.bits.data() + r.drawn, h + align_up(amp_bytes(r)), size_t(r.last_draws) * 8);
+        r.drawn += r.last_draws;
+      }
+      if (r.drawn < r.n_samples) {
+        enqueue_finish(r, amps, st);
+      } else {
+        r.finishing = false;
+        r.state = R_DONE;
+      }
+      return true;
+    }
     bool did = false;
     while (!r.chunks.empty() && hipEventQuery(r.chunks.front()) == hipSuccess) {
       ev_free.push_back(r.chunks.front());
       r.chunks.pop_front();
       did = true;
     }
-    uint8_t* ws = arena + r.off;
-    double* amps = reinterpret_cast<double*>(ws + align_up(r.ws_bytes));
-    hipStream_t st = streams[r.slot];
     if (r.next < r.total && r.chunks.size() < 2) {
       const int64_t count = std::min<int64_t>(int64_t(chunk_batches) * r.plan->batch, r.total - r.next);
       Exec e{*r.plan, ws, st};
+      if (fault_left > 0) e.fault = &fault_left;
       e.contract(amps, r.next, count, r.next > 0, r.next > 0);
       hipEvent_t ev = get_event();
       HIPCHK(hipEventRecord(ev, st));
@@ -1578,18 +1670,8 @@ struct tnc_server_s {
       did = true;
     }
     if (r.next >= r.total && r.chunks.empty()) {
-      const int64_t n_amp = r.plan->L << r.plan->n_open;
-      r.amps.resize(size_t(2 * n_amp));
-      if (r.n_samples > 0) {
-        r.bits.resize(size_t(r.n_samples));
-        sample_into(*r.plan, ws, amps, r.seed, r.n_samples, r.bits.data(), st);
-      }
-      HIPCHK(hipMemcpyAsync(r.amps.data(), amps, uint64_t(n_amp) * 16, hipMemcpyDeviceToHost, st));
-      HIPCHK(hipStreamSynchronize(st));
-      double nrm = 0;
-      for (double x : r.amps) nrm += x * x;
-      r.norm = nrm;
-      r.state = R_DONE;
+      if (r.n_samples > 0) r.bits.resize(size_t(r.n_samples));
+      enqueue_finish(r, amps, st);
       did = true;
     }
     return did;
@@ -1601,6 +1683,9 @@ struct tnc_server_s {
     slot_busy[r->slot] = false;
     for (auto e : r->chunks) ev_free.push_back(e);
     r->chunks.clear();
+    if (r->fin) ev_free.push_back(r->fin);
+    r->fin = nullptr;
+    r->finishing = false;
     r->t_done = now();
     active.erase(std::find(active.begin(), active.end(), r));
   }
@@ -1669,6 +1754,8 @@ struct tnc_server_s {
     if (worker.joinable()) worker.join();
     for (auto& kv : all) delete kv.second;
     for (auto e : ev_free) (void)hipEventDestroy(e);
+    for (auto h : pin)
+      if (h) (void)hipHostFree(h);
     for (auto st : streams) (void)hipStreamDestroy(st);
   }
 };
@@ -2097,6 +2184,16 @@ tnc_status tnc_server_create(int device, void* d_arena, uint64_t arena_bytes, in
       s->chunk_batches = chunk_batches;
       s->free_list[0] = s->arena_bytes;
       s->slot_busy.assign(size_t(max_slots), false);
+      s->pin.assign(size_t(max_slots), nullptr);
+      s->pin_cap.assign(size_t(max_slots), 0);
+      // TNC_FAULT=launch:N: the N-th launch unit this server enqueues (counted over all its
+      // requests) fails before it is enqueued; for tests of failure isolation
+      if (const char* f = std::getenv("TNC_FAULT")) {
+        long long n = 0;
+        if (std::sscanf(f, "launch:%lld", &n) != 1 || n < 1)
+          fail(TNC_E_INVALID, "TNC_FAULT must read launch:N with N >= 1");
+        s->fault_left = n;
+      }
       for (int k = 0; k < max_slots; ++k) {
         hipStream_t st;
         HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));

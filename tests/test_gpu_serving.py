@@ -1,7 +1,9 @@
 """Serving (continuous batching) on the GPU: every request's amplitudes and samples are the
-same when it runs alone as when it runs in a mix of concurrent requests; admission waits
-for arena room; a request that can never fit is refused at submission."""
+same when it runs alone as when it runs in a mix of concurrent requests (draws copied back
+in several chunks included); admission waits for arena room; a request that can never fit
+is refused at submission; a request whose launch fails fails alone."""
 
+import os
 import time
 
 import numpy as np
@@ -29,6 +31,7 @@ def _requests():
         (4, 5, 10, 104, [1, 7, 18], 8, 10, 8),
         (4, 4, 12, 105, [0, 15], 1, 8, 500),
         (3, 5, 10, 106, [4, 10], 16, 8, 0),
+        (3, 4, 8, 107, [0, 3, 6, 9], 1, 7, 150000),   # draws in three chunks of <= 65536
     ]
     for r, c, m, seed, open_q, L, bound, k in specs:
         circ = synth.make_circuit(r, c, m, seed)
@@ -117,3 +120,50 @@ def test_admission_waits_for_room_and_refuses_what_never_fits():
         _submit(small, *reqs[0])
     assert e.value.code == tnc.TNC_E_OOM
     small.close()
+
+
+def test_a_failed_launch_fails_one_request_and_spares_the_others():
+    """TNC_FAULT=launch:N makes the N-th launch unit the server enqueues fail before it is
+    enqueued (forced from the host; no kernel faults).  Exactly one request reports the
+    failure; every other request of the mix returns the same bits as when run alone, and the
+    server keeps serving afterwards."""
+    from paper_2111_03011_amd import tnc
+    from paper_2111_03011_amd.serving import Server
+    reqs = _requests()
+    alone = [_alone(*r) for r in reqs]
+    os.environ["TNC_FAULT"] = "launch:4"
+    try:
+        srv = Server(arena_bytes=256 << 20, max_slots=3, chunk_batches=1)
+    finally:
+        os.environ.pop("TNC_FAULT")
+    ids = [_submit(srv, *r) for r in reqs]
+    failed, t0 = [], time.time()
+    res = {}
+    while len(res) + len(failed) < len(ids):
+        for rid in ids:
+            if rid in res or rid in failed:
+                continue
+            try:
+                r = srv.poll(rid)
+            except tnc.TncError as e:
+                assert e.code == tnc.TNC_E_HIP and "TNC_FAULT" in str(e)
+                failed.append(rid)
+                continue
+            if r is not None:
+                res[rid] = r
+        assert time.time() - t0 < 120, "requests did not finish"
+        time.sleep(0.002)
+    log(f"  failed: {failed}; finished: {sorted(res)}")
+    assert len(failed) == 1
+    for (w, k, seed), (a_amps, a_bits), rid in zip(reqs, alone, ids):
+        if rid in failed:
+            continue
+        assert np.array_equal(res[rid]["amps"], a_amps), f"request {rid} differs"
+        if k:
+            assert np.array_equal(res[rid]["bits"], a_bits)
+    # the failed request again, on the same server: it runs through
+    k = ids.index(failed[0])
+    rid = _submit(srv, *reqs[k])
+    again = _wait(srv, [rid])[rid]
+    assert np.array_equal(again["amps"], alone[k][0])
+    srv.close()
