@@ -50,6 +50,33 @@ def fsim_tensor(theta: float, phi: float) -> np.ndarray:
     return fsim(theta, phi).reshape(2, 2, 2, 2)
 
 
+def companion_cut(theta: float, phi: float, pinned: int) -> np.ndarray:
+    """fSim with the companion-edge rank-one approximation (Method, low-rank case (ii);
+    Appendix C), as a four-way tensor G[out_a, out_b, in_a, in_b].
+
+    `pinned` (0 = q_a, 1 = q_b) is the input whose edge is fixed by slicing.  For each
+    value v of that input the gate is a three-way tensor; grouping the pinned qubit's output
+    with the other input against the other qubit's output (the companion edge) gives a 4 x 2
+    matrix whose squared singular values are 1 + sin^2(theta) and cos^2(theta).  Each such
+    matrix is replaced by its best rank-one approximation (largest singular triplet of its
+    SVD), and the two slices are put back together."""
+    g = fsim_tensor(theta, phi)
+    other = 1 - pinned
+    out = np.zeros_like(g)
+    for v in (0, 1):
+        t = g[:, :, v, :] if pinned == 0 else g[:, :, :, v]      # [out_a, out_b, in_other]
+        # rows (out_pinned, in_other), columns out_other
+        m = np.moveaxis(t, other, -1).reshape(4, 2)
+        u, sv, vh = np.linalg.svd(m)
+        r1 = sv[0] * np.outer(u[:, 0], vh[0, :])
+        t1 = np.moveaxis(r1.reshape(2, 2, 2), -1, other)
+        if pinned == 0:
+            out[:, :, v, :] = t1
+        else:
+            out[:, :, :, v] = t1
+    return out
+
+
 def gate_thetas(circuit: dict) -> list:
     """The angle of every two-qubit gate in circuit order: the per-gate list
     circuit["fsim"]["thetas"] when present (calibrated gates: angles near, not at, one

@@ -18,6 +18,14 @@ gate with both inputs projected is |00><00|, so the simulator applies the projec
 |0><0| to both qubits in place of the gate.  The result is the unnormalised approximate
 state psi_hat of the perturbed network.
 
+Companion-edge cuts (Method, low-rank case (ii); Appendix C): a circuit may list `cuts`,
+pairs [g, q] naming a two-qubit gate g (circuit order) and one of its qubits q whose input
+edge slicing fixes.  The gate is then replaced by gates.companion_cut: for each value of
+that input, its best rank-one approximation across the other qubit's output (the
+companion edge).  Summed over the fixed value, that is one 4 x 4 (non-unitary) operator in
+place of fSim, so the simulator applies it like any gate; the result is the unnormalised
+state of the approximated network.
+
 The gate arithmetic has two interchangeable backends with the same pins: "numpy"
 (tensordot per gate, new arrays) and "c" (sv.c: the same updates as in-place loops over
 the amplitudes on every host core, for states of up to 30 qubits = 16 GiB).
@@ -31,7 +39,7 @@ import subprocess
 
 import numpy as np
 
-from .gates import ONEQ, fsim_tensor, gate_thetas
+from .gates import ONEQ, companion_cut, fsim_tensor, gate_thetas
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SV_SRC = os.path.join(_HERE, "sv.c")
@@ -139,6 +147,7 @@ def simulate(circuit: dict, projectors: dict | None = None, backend: str = "nump
     thetas = gate_thetas(circuit)
     phi = circuit["fsim"]["phi"]
     holes = set(int(h) for h in circuit.get("holes", ()))
+    cuts = {int(g): int(q) for g, q in circuit.get("cuts", ())}
     n2q = [0] * n
     gate = 0
     for layer in circuit["layers"]:
@@ -148,6 +157,10 @@ def simulate(circuit: dict, projectors: dict | None = None, backend: str = "nump
             if gate in holes:
                 st.project(qa, 0)
                 st.project(qb, 0)
+            elif gate in cuts:
+                if cuts[gate] not in (qa, qb):
+                    raise ValueError(f"cut names qubit {cuts[gate]}, not one of gate {gate}'s")
+                st.apply_2q(companion_cut(thetas[gate], phi, 0 if cuts[gate] == qa else 1), qa, qb)
             else:
                 st.apply_2q(fsim_tensor(thetas[gate], phi), qa, qb)
             gate += 1

@@ -82,6 +82,44 @@ def test_one_input_pinned_singular_values(theta):
                 pytest.fail(f"no grouping gives {want} for input {pinned_input}={v}")
 
 
+@pytest.mark.parametrize("theta", [np.pi / 2, 1.45, 1.2, 0.9])
+@pytest.mark.parametrize("pinned", [0, 1])
+def test_companion_cut_keeps_the_dominant_column(theta, pinned):
+    # Appendix C lists the four pinned matrices explicitly: for input value v their columns
+    # (the companion output) are orthogonal, and the one of squared norm 1 + sin^2 theta is
+    # the companion output equal to v.  So the rank-one cut keeps exactly the entries whose
+    # other-qubit output equals the pinned input, and drops cos^2 theta per value.
+    g = gates.fsim_tensor(theta, 0.7)                # [oa, ob, ia, ib]
+    cut = gates.companion_cut(theta, 0.7, pinned)
+    mask = np.zeros((2, 2, 2, 2))
+    for oa in (0, 1):
+        for ob in (0, 1):
+            for ia in (0, 1):
+                for ib in (0, 1):
+                    pin_in, other_out = (ia, ob) if pinned == 0 else (ib, oa)
+                    mask[oa, ob, ia, ib] = float(other_out == pin_in)
+    assert np.allclose(cut, g * mask, atol=1e-12)
+    assert np.isclose(np.sum(np.abs(g - cut) ** 2), 2 * np.cos(theta) ** 2)
+    assert np.isclose(np.sum(np.abs(cut) ** 2), 2 * (1 + np.sin(theta) ** 2))
+    if theta == np.pi / 2:                           # nothing is dropped at pi/2
+        assert np.allclose(cut, g, atol=1e-15)
+
+
+def test_companion_cut_in_the_state_vector():
+    # one cut gate on a two-qubit register: the simulator applies the cut operator in place
+    # of fSim (|psi> after the 1q layer, then G~), checked by hand here
+    circ = {"n_qubits": 2, "fsim": {"theta": 1.1, "phi": 0.3},
+            "layers": [{"oneq": ["sqrt_x", "sqrt_y"], "couplers": [[0, 1]]}], "cuts": [[0, 1]]}
+    from oracle import statevector
+    psi = statevector.simulate(circ)
+    start = np.kron(gates.ONEQ["sqrt_x"][:, 0], gates.ONEQ["sqrt_y"][:, 0])
+    want = gates.companion_cut(1.1, 0.3, 1).reshape(4, 4) @ start
+    assert np.allclose(psi, want, atol=1e-14)
+    assert not np.allclose(psi, gates.fsim(1.1, 0.3) @ start)
+    with pytest.raises(ValueError):
+        statevector.simulate(dict(circ, cuts=[[0, 5]]))
+
+
 def test_edge_breaking_matrix():
     # Method: E = (1,0)^T (1,0) = I/2 + sigma_z/2
     e = np.outer([1, 0], [1, 0])

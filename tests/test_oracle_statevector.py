@@ -113,6 +113,36 @@ def test_per_gate_angles_match_brute_force(backend):
     assert not np.allclose(got, statevector.simulate(c2, backend=backend), atol=1e-6)
 
 
+@pytest.mark.parametrize("backend", BACKENDS)
+def test_companion_cuts_match_brute_force(backend):
+    """Companion-edge cuts (Appendix C): a cut gate is the fSim matrix with the entries whose
+    other-qubit output differs from the pinned qubit's input set to zero (the explicit
+    pinned matrices of Appendix C), written here as a basis loop."""
+    layers = [(["sqrt_y", "sqrt_w", "sqrt_x"], [(0, 1)]), (["sqrt_x", "sqrt_y", "sqrt_w"], [(1, 2)]),
+              (["sqrt_w", "sqrt_x", "sqrt_y"], [(0, 2)])]
+    c = _circuit(3, layers)
+    c["fsim"]["thetas"] = [1.3, 1.45, 1.1]
+    c["cuts"] = [[0, 0], [2, 2]]
+    n = 3
+    u = np.eye(8, dtype=complex)
+    gate = 0
+    for oneq, couplers in layers:
+        u = _full_oneq_layer(oneq) @ u
+        for qa, qb in couplers:
+            f = gates.fsim(c["fsim"]["thetas"][gate], c["fsim"]["phi"]).copy()
+            pin = dict(c["cuts"]).get(gate)
+            if pin is not None:
+                for ao, bo, ai, bi in itertools.product((0, 1), repeat=4):
+                    pin_in, other_out = (ai, bo) if pin == qa else (bi, ao)
+                    if other_out != pin_in:
+                        f[2 * ao + bo, 2 * ai + bi] = 0
+            u = _full_two_qubit(n, qa, qb, f) @ u
+            gate += 1
+    got = statevector.simulate(c, backend=backend)
+    assert np.allclose(got, u[:, 0], atol=1e-14)
+    assert not np.allclose(got, _brute(c), atol=1e-3)
+
+
 def test_jittered_circuit_angles():
     """The jitter flag draws one angle per two-qubit gate around theta (seeded, circuit
     order) and leaves the single-qubit gates as they were."""
