@@ -719,6 +719,51 @@ def summarise_stats(path: str) -> None:
         print(f"| `{n}` | {calls} | {t / 1e6:.2f} | {t / calls / 1e3:.2f} | {100 * t / tot:.2f} |")
 
 
+def xeb_vs_group_size(args) -> dict:
+    """Linear XEB of one draw per group against the group size l (Appendix D): the 5x6-grid,
+    14-cycle circuit, 2048 seeded groups whose l = 2^j amplitudes vary the last j qubits,
+    contracted on the GPU (complex64, all slices) and sampled with the GPU samplers (inverse
+    CDF inside each group, Metropolis chains of 100 steps, frugal rejection with m = 10).
+    Draws are scored with the contraction's own amplitudes, p(s) = |psi(s)|^2 (the circuit
+    is unitary, so no normalisation).  'in_group_exact' is the expectation of inverse-CDF
+    sampling computed from the amplitudes; for Porter-Thomas amplitudes it is near
+    (l - 1) / (l + 1)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2111_03011_amd.workload import config_workload, make_workload
+    base = config_workload("sliced")
+    circ, n, L = base.circuit, base.circuit["n_qubits"], 2048
+    res = {"workload": "5x6 grid, 14 cycles (30 qubits), 2048 groups, complex64", "rows": []}
+    for j in range(7):
+        open_q = list(range(n - j, n))
+        closed = synth.group_targets(n, open_q, L, 2002)
+        w = make_workload(circ, open_q, closed, max_log2=28, trials=4, seed=2005)
+        c = contraction(w, "c64", 8)
+        t0 = time.perf_counter()
+        c.contract()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0)
+        amps = c.amps.cpu().numpy().reshape(L, -1)
+        p = np.abs(amps) ** 2
+        row = {"l": 1 << j, "sliced": len(w.plan.sliced_labels), "contract_ms": ms,
+               "tflops": c.work() / (ms * 1e-3) / 1e12,
+               "in_group_exact": float(2.0 ** n * np.mean((p ** 2).sum(1) / p.sum(1)) - 1.0),
+               "porter_thomas": ((1 << j) - 1) / ((1 << j) + 1)}
+        draws = {"inverse_cdf": c.sample(11, L), "metropolis_100": c.sample_metropolis(12, L, 100),
+                 "frugal_m10": c.sample_frugal(13, L, 10.0, 64)}
+        for name, bits in draws.items():
+            mu = np.zeros(L, dtype=np.int64)
+            for t, q in enumerate(open_q):
+                mu |= ((bits.astype(np.int64) >> (n - 1 - q)) & 1) << (len(open_q) - 1 - t)
+            row[name] = float(2.0 ** n * p[np.arange(L), mu].mean() - 1.0)
+        c.close()
+        res["rows"].append(row)
+        log(f"XEB vs l: l={1 << j}: " + ", ".join(f"{k} {v:.3f}" for k, v in row.items()
+                                                  if isinstance(v, float)))
+    return res
+
+
 def serving_main(args):
     """Poisson request stream through libtnc's server; one JSON line with throughput and
     latency percentiles (latency = server completion time - submission time)."""
@@ -838,6 +883,8 @@ def main():
                          "with --copy-calibration into the traffic record, then exit")
     ap.add_argument("--summarise-stats", metavar="KERNEL_STATS_CSV",
                     help="print a markdown summary of a rocprofv3 --stats kernel file, then exit")
+    ap.add_argument("--xeb-vs-l", action="store_true",
+                    help="print the XEB-against-group-size study of the 5x6 network, then exit")
     ap.add_argument("--requests", type=int, default=400, help="serving: requests in the stream")
     ap.add_argument("--templates", type=int, default=16, help="serving: distinct request templates")
     ap.add_argument("--slots", type=int, default=8, help="serving: concurrent requests")
@@ -860,6 +907,9 @@ def main():
         sys.exit(2)
     if args.workload == "serving":
         return serving_main(args)
+    if args.xeb_vs_l:
+        print(json.dumps(xeb_vs_group_size(args)), flush=True)
+        return
 
     import dataclasses
 

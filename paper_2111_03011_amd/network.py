@@ -57,6 +57,7 @@ class TensorNetwork:
     out_label: list = field(default_factory=list)    # [n_qubits]
     bond_label: dict = field(default_factory=dict)   # (q, j) -> label
     cycle: list = field(default_factory=list)        # per tensor: cycle of its gate (-1: none)
+    cut_pairs: list = field(default_factory=list)    # (sliced label, companion label) per cut
 
     def ranks(self):
         return [len(l) for l in self.labels]
@@ -84,17 +85,34 @@ def circuit_network(circuit: dict, simplify: bool = True) -> TensorNetwork:
     Method): E = |0><0| on each input wire makes the fSim gate |00><00|, so the gate is
     dropped, the incoming wire is closed with <0| (after its pending single-qubit gates)
     and the outgoing wire starts again from |0>.  The perturbed network's amplitudes are
-    those of psi_hat, with fidelity about 2^-K for K = 2 per hole."""
+    those of psi_hat, with fidelity about 2^-K for K = 2 per hole.
+
+    `circuit["cuts"]` (optional) lists companion-edge cuts [g, q] (Method, low-rank case
+    (ii); Appendix C): the input edge of gate g on qubit q is sliced, and for each value v
+    the gate's rank-one approximation keeps exactly the entries whose output on the other
+    qubit equals v (the other singular vector, of weight cos^2 theta, is dropped).  Here the
+    single-qubit gates between the previous two-qubit gate on q and g are folded into the
+    previous gate's output instead of g's input, so that the bond (q, j) entering g is g's
+    own input; the cut is then realised by slicing that bond and g's output bond on the
+    other qubit (the companion edge) with one shared slice bit.  The pair of labels is kept
+    in `cut_pairs`; the network itself stays exact (its full slice sum is the circuit's
+    amplitude), the approximation is in summing only the slices where both bits agree."""
     n = circuit["n_qubits"]
     holes = set(int(h) for h in circuit.get("holes", ()))
+    cuts = {}
+    for g, q in circuit.get("cuts", ()):
+        if int(g) in cuts or int(g) in holes:
+            raise ValueError(f"gate {g} is cut twice or also drilled")
+        cuts[int(g)] = int(q)
+    cut_pairs, companions = [], set()
     n2 = sum(len(layer["couplers"]) for layer in circuit["layers"])
     # one angle for every gate, or calibrated per-gate angles ("thetas", circuit order)
     thetas = circuit["fsim"].get("thetas", [circuit["fsim"]["theta"]] * n2)
     if len(thetas) != n2:
         raise ValueError(f"fsim thetas lists {len(thetas)} angles for {n2} two-qubit gates")
     phi = circuit["fsim"]["phi"]
-    if any(h < 0 or h >= n2 for h in holes):
-        raise ValueError(f"hole indices must name one of the {n2} two-qubit gates")
+    if any(h < 0 or h >= n2 for h in holes) or any(g < 0 or g >= n2 for g in cuts):
+        raise ValueError(f"hole and cut indices must name one of the {n2} two-qubit gates")
     gate = 0
     scale = complex(1.0)
     next_label = [0]
@@ -138,6 +156,22 @@ def circuit_network(circuit: dict, simplify: bool = True) -> TensorNetwork:
             t = _fsim4(theta, phi)
             oa, ob = new_label(), new_label()
             labs = [oa, ob, -1, -2]
+            pin = cuts.get(gate - 1)
+            if pin is not None:
+                if pin not in (qa, qb):
+                    raise ValueError(f"cut of gate {gate - 1} names qubit {pin}, not one of its own")
+                if last[pin] is None:
+                    raise ValueError(f"cut of gate {gate - 1}: no earlier two-qubit gate on qubit "
+                                     f"{pin}, its input is not a bond")
+                pidx, pout = last[pin]
+                if pout in companions:
+                    raise ValueError(f"cut of gate {gate - 1} pins the companion edge of another cut")
+                # the pending single-qubit gates move to the previous gate's output
+                tensors[pidx] = _apply_matrix(tensors[pidx], labels[pidx], pout, pending[pin], "out")
+                pending[pin] = np.eye(2, dtype=np.complex128)
+                comp = ob if pin == qa else oa
+                cut_pairs.append((pout, comp))
+                companions.add(comp)
             # fold the inputs: initial vectors or the pending gates of each wire
             for q, slot in ((qa, -1), (qb, -2)):
                 if last[q] is None:
@@ -180,10 +214,20 @@ def circuit_network(circuit: dict, simplify: bool = True) -> TensorNetwork:
     cycles = [cycles[k] for k in keep]
     if scale != 1.0:
         tensors[0] = tensors[0] * scale
+    pinned = {b for b, _ in cut_pairs}
+    for b, c in cut_pairs:
+        if c not in bond_of:
+            raise ValueError("a cut gate's other output must feed a later two-qubit gate")
+        if c in pinned:
+            raise ValueError("a cut's companion edge is the pinned edge of another cut")
     net = TensorNetwork(n_qubits=n, tensors=tensors, labels=labels, out_label=out_label,
-                        bond_label={v: k for k, v in bond_of.items()}, cycle=cycles)
+                        bond_label={v: k for k, v in bond_of.items()}, cycle=cycles,
+                        cut_pairs=cut_pairs)
     if simplify:
         simplify_low_rank(net)
+        present = {x for l in net.labels for x in l}
+        if any(b not in present or c not in present for b, c in cut_pairs):
+            raise ValueError("simplification contracted a cut's edge away")
     return net
 
 

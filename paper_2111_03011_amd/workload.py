@@ -207,6 +207,83 @@ def zigzag_pair(w: Workload, tail_start: int, max_log2: float, count: int, seed:
             dataclasses.replace(w, plan=plain, slice_ids=ids))
 
 
+def companion_cuts(circuit: dict, sliced_bonds, max_cuts: int | None = None) -> list:
+    """Companion-edge cuts [g, q] for sliced bonds (Method, low-rank case (ii)): a sliced
+    bond (q, j) is the input on q of the next two-qubit gate g on q; its companion edge is
+    g's output on the other qubit, which must be a bond (a later gate on that qubit) and not
+    sliced itself.  Bonds are taken in the given order; a cut whose edges would collide with
+    an earlier cut's (one's pinned edge the other's companion), or that simplification of
+    the network would contract away, is skipped."""
+    layers = circuit["layers"]
+    holes = set(int(h) for h in circuit.get("holes", ()))
+    on = {}                     # qubit -> gate indices in order
+    pair = []
+    g = 0
+    for layer in layers:
+        for qa, qb in layer["couplers"]:
+            on.setdefault(qa, []).append(g)
+            on.setdefault(qb, []).append(g)
+            pair.append((qa, qb))
+            g += 1
+    sliced = {tuple(b) for b in sliced_bonds}
+    cuts, pinned, comps = [], set(), set()
+    for q, j in sliced_bonds:
+        if max_cuts is not None and len(cuts) >= max_cuts:
+            break
+        if j + 1 >= len(on.get(q, ())):
+            continue
+        gate = on[q][j + 1]
+        qa, qb = pair[gate]
+        other = qb if q == qa else qa
+        jo = on[other].index(gate)
+        comp = (other, jo)
+        if gate in holes or any(c[0] == gate for c in cuts) or jo + 1 >= len(on[other]):
+            continue
+        if comp in sliced or comp in pinned or (q, j) in comps:
+            continue
+        trial = cuts + [[gate, q]]
+        try:
+            circuit_network(dict(circuit, cuts=trial))
+        except ValueError:
+            continue
+        cuts = trial
+        pinned.add((q, j))
+        comps.add(comp)
+    return cuts
+
+
+def companion_workload(w: Workload, cuts) -> Workload:
+    """The workload with companion-edge cuts: the circuit lists `cuts`, the network folds
+    the pinned bonds' single-qubit gates into the earlier gate, and each cut's companion
+    label is sliced on a new high slice-id bit that copies its pinned bond's bit in every
+    id (so each slice fixes both edges to the same value, and the slice set is the same
+    size).  Same path; the planner's cost counts both edges as sliced."""
+    import dataclasses
+    circ = dict(w.circuit, cuts=[list(c) for c in cuts])
+    net = circuit_network(circ)
+    if net.labels != w.net.labels:
+        raise RuntimeError("the cut network's structure differs from the workload's")
+    base = list(w.plan.sliced_labels)
+    pos = {x: i for i, x in enumerate(base)}
+    if any(b not in pos for b, _ in net.cut_pairs):
+        raise ValueError("every cut must pin one of the plan's sliced bonds")
+    k = len(base)
+    sliced = base + [c for _, c in net.cut_pairs]
+    ids = []
+    for sid in w.slice_ids:
+        x = int(sid)
+        for t, (b, _) in enumerate(net.cut_pairs):
+            x |= ((x >> pos[b]) & 1) << (k + t)
+        ids.append(x)
+    ids = np.asarray(ids, dtype=np.uint64 if len(sliced) <= 62 else object)
+    sp = make_problem(net.labels, net.out_label, net.n_qubits, w.open_qubits, w.closed_bits,
+                      sliced=sliced)
+    leaves = {i for i, l in enumerate(net.labels) if any(x in sliced for x in l)}
+    plan = Plan(path=w.plan.path, sliced_labels=sliced, cost=path_cost(sp, w.plan.path, leaves),
+                n_slices=len(ids))
+    return dataclasses.replace(w, circuit=circ, net=net, plan=plan, slice_ids=ids)
+
+
 def serving_template(seed: int, max_log2: float = 26, work_cap: float = 2e13,
                      max_tries: int = 50):
     """One request of the serving stream, planned by the client ahead of time.

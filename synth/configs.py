@@ -38,6 +38,9 @@ CONFIGS = {
         "plan_trials": 64,
         "reuse_batch": 64,        # head-reuse plan: steps above global labels once per 64
         "holes": 2,               # perturbed-network mode: drilled two-qubit gates (K = 4)
+        # fidelity study of the approximations (holes, companion-edge cuts): the same circuit
+        # with per-gate angles theta ~ pi/2 +- 0.1 (at pi/2 exactly a cut drops nothing)
+        "fidelity_jitter": {"theta_jitter": 0.1, "jitter_seed": 3003},
     },
     "precision": {
         "name": "precision",
