@@ -69,3 +69,46 @@ def large_pairs():
     for q in pairs:
         q.amps = np.asarray(q.amps)
     return pairs, bonds, jitter
+
+
+@dataclass
+class FidelityRow:
+    K: int               # broken edges (2 per hole)
+    k: int               # companion-edge cuts
+    f_est: float
+    f: float
+    xeb: float
+    xeb_draws: float
+    holes: list
+    cuts: list           # [gate, pinned qubit]
+
+
+def fidelity_table():
+    """(rows, (theta_jitter, jitter_seed)) of tests/golden/fidelity_5x6_m14.txt."""
+    p = _path("fidelity_5x6_m14.txt")
+    rows, jitter = [], None
+    for line in open(p):
+        if line.startswith("#"):
+            if "theta_jitter" in line:
+                f = line.replace(",", " ").split()
+                jitter = (float(f[f.index("theta_jitter") + 1]), int(f[f.index("jitter_seed") + 1]))
+            continue
+        f = line.split()
+        holes = [] if f[6] == "-" else [int(x) for x in f[6].split(",")]
+        cuts = [] if f[7] == "-" else [[int(a) for a in c.split(":")] for c in f[7:]]
+        rows.append(FidelityRow(int(f[0]), int(f[1]), float(f[2]), float(f[3]), float(f[4]),
+                                float(f[5]), holes, cuts))
+    return rows, jitter
+
+
+def sliced_cut_group():
+    """(cuts, amplitudes) of tests/golden/sliced_5x6_m14_cut_group.txt: the 4096 oracle
+    amplitudes of the sliced configuration's group on the jittered circuit with cuts."""
+    p = _path("sliced_5x6_m14_cut_group.txt")
+    cuts = None
+    for line in open(p):
+        if line.startswith("# and companion-edge cuts"):
+            body = line.split("cuts", 1)[1].split("(")[0].split()
+            cuts = [[int(a) for a in c.split(",")] for c in body]
+    v = np.loadtxt(p, comments="#")
+    return cuts, v[:, 0] + 1j * v[:, 1]
