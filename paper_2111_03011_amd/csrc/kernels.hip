@@ -15,6 +15,8 @@
 //   k_sample_*     inverse-CDF sampling with SplitMix64 uniforms
 #include "tnc_kernels.h"
 
+#include <cstdlib>
+
 namespace tnc {
 
 namespace {
@@ -937,6 +939,134 @@ __global__ __launch_bounds__(kThreads) void k_gemm_outer(GemmArgs a) {
   if (a.rec_c) amax_commit_wg(mx, sl, a.rec_c, a.rec_c_step);
 }
 
+// The same short-K product on the FP32 matrix cores, for K = 2^NK = 16 and N >= 64 JB,
+// where the vector form above is bound by its 4 K FMAs per complex output (64 at K = 16, at
+// half the FP32 rate without packed instructions) rather than by writing C.  A workgroup
+// owns 64 JB columns x a range of rows set by the launch (the grid's row blocks split M);
+// wave w takes 16 JB complex columns as JB 32 x 32 real blocks of v_mfma_f32_32x32x2f32
+// (JB = 4: 2 waves per SIMD), each instruction consuming one complex k through
+// the real embedding of B ([[Re, Im], [-Im, Re]], as in k_gemm).  The B fragments of every
+// k stay in registers; 32 rows of A at a time are staged in LDS (two buffers, so the next
+// rows are loaded while the current ones feed the matrix cores).  Each wave passes its
+// 32 x 128 real results through its own LDS patch (row stride 136 floats: the accumulator
+// writes, rows r and r + 4 per instruction, and the 16-byte reads, 64 consecutive floats
+// per 16 lanes, are free of bank conflicts on a 64-bank LDS) and writes every row's 512
+// contiguous bytes with 32 lanes of 16-byte stores.
+constexpr int kOmRows = 32;
+
+template <int NK, int JB>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(JB == 4 ? 2 : 3))) void k_gemm_outer_mfma(GemmArgs a) {
+  constexpr int KS = 1 << NK;
+  constexpr int kOmCols = 64 * JB, kOmRs = 32 * JB + 8;
+  __shared__ float2 As[2][kOmRows * KS];
+  __shared__ __align__(16) float Cs[4][kOmRows * kOmRs];
+  const int64_t M = a.M, N = a.N;
+  const int64_t col_blocks = N / kOmCols;
+  const int64_t row_blocks = int64_t(gridDim.x) / col_blocks;
+  const int64_t mrows = (M + row_blocks - 1) / row_blocks;
+  const int64_t cb = int64_t(blockIdx.x) % col_blocks, mb = int64_t(blockIdx.x) / col_blocks;
+  const int64_t n0 = cb * kOmCols, mw0 = mb * mrows;
+  const int64_t z = int64_t(blockIdx.y) + int64_t(blockIdx.z) * gridDim.y;
+  if (z >= a.rows * a.nb) return;
+  const int64_t sl = z / a.rows, r = z - sl * a.rows;
+  const int64_t ar = a.ga ? a.ga[r] : (a.a_rows == 1 ? 0 : r);
+  const int64_t br = a.gb ? a.gb[r] : (a.b_rows == 1 ? 0 : r);
+  const float2* A = a.A + sl * a.a_slice_stride + ar * a.a_row_stride;
+  const float2* B = a.B + sl * a.b_slice_stride + br * a.b_row_stride;
+  float* C = reinterpret_cast<float*>(a.C + sl * a.c_slice_stride + r * a.c_row_stride);
+  float sa = 1.f, sb = 1.f;
+  if (a.rec_c) {
+    int sha, shb, ea, eb;
+    rec_load(a.rec_a, a.rec_a_step, sl, false, sha, ea);
+    rec_load(a.rec_b, a.rec_b_step, sl, false, shb, eb);
+    sa = pow2f(sha);
+    sb = pow2f(shb);
+    if (blockIdx.x == 0 && r == 0 && threadIdx.x == 0)
+      a.rec_c[sl * a.rec_c_step + kRecExp] = uint32_t(ea + eb - sha - shb);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int half = lane >> 5, j32 = lane & 31;
+  // B fragments: real k row `half` of the embedding, real column j32 of block j
+  float bf[JB][KS];
+#pragma unroll
+  for (int j = 0; j < JB; ++j) {
+    const int64_t n = n0 + wave * 16 * JB + j * 16 + (j32 >> 1);
+    const int64_t on = scatter_u<kMaxRank>(n, a.b_npos, a.nn);
+    const bool take_im = (half != (j32 & 1));
+    const float sign = (half == 1 && (j32 & 1) == 0) ? -sb : sb;
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const float2 v = B[on + scatter_u<NK>(k, a.b_kpos, NK)];
+      bf[j][k] = (take_im ? v.y : v.x) * sign;
+    }
+  }
+  const int64_t mloc_mask = (int64_t(1) << a.nm) - 1;
+  const int64_t m_end = (mw0 + mrows < M) ? mw0 + mrows : M;
+  // staging: 32 rows x KS values of A, zero past m_end
+  auto stage = [&](int buf, int64_t m0) {
+    for (int e = threadIdx.x; e < kOmRows * KS; e += kThreads) {
+      const int i = e / KS, k = e % KS;
+      const int64_t m = m0 + i;
+      float2 v = make_float2(0.f, 0.f);
+      if (m < m_end) {
+        const int64_t mo = (a.fold ? (m >> a.nm) * a.fold_stride : 0) +
+                           scatter_u<kMaxRank>(m & mloc_mask, a.a_mpos, a.nm);
+        v = A[mo + scatter_u<NK>(k, a.a_kpos, NK)];
+      }
+      As[buf][e] = make_float2(v.x * sa, v.y * sa);
+    }
+  };
+  float* patch = Cs[wave];
+  float mx = 0.f;
+  int buf = 0;
+  stage(0, mw0);
+  __syncthreads();
+  for (int64_t m0 = mw0; m0 < m_end; m0 += kOmRows) {
+    if (m0 + kOmRows < m_end) stage(buf ^ 1, m0 + kOmRows);   // read after the next barrier
+    f32x16 acc[JB];
+#pragma unroll
+    for (int j = 0; j < JB; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[j][v] = 0.f;
+    const float2* as = As[buf] + j32 * KS;
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const float2 av = as[k];
+      const float af = half ? av.y : av.x;
+#pragma unroll
+      for (int j = 0; j < JB; ++j)
+        acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af, bf[j][k], acc[j], 0, 0, 0);
+    }
+    // accumulators -> this wave's patch (row 8 (v/4) + 4 half + v%4, real column 32 j + j32)
+#pragma unroll
+    for (int j = 0; j < JB; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        mx = fmaxf(mx, fabsf(acc[j][v]));   // rows past m_end hold exact zeros
+        patch[(8 * (v >> 2) + 4 * half + (v & 3)) * kOmRs + 32 * j + j32] = acc[j][v];
+      }
+    // the patch is this wave's alone: its LDS operations complete in order
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // 16 bytes per lane, 8 JB lanes per row: each row's 128 JB contiguous bytes in one piece
+    constexpr int LPR = 8 * JB, RPI = 64 / LPR;   // lanes per row, rows per instruction
+    const int rows_left = int(m_end - m0 < kOmRows ? m_end - m0 : kOmRows);
+    const int rl = lane / LPR, cl = lane % LPR;
+    float* cm = C + m0 * N * 2 + (n0 + wave * 16 * JB) * 2 + 4 * cl;
+#pragma unroll
+    for (int t = 0; t < kOmRows / RPI; ++t) {
+      const int row = RPI * t + rl;
+      const float4 x = *reinterpret_cast<const float4*>(&patch[row * kOmRs + 4 * cl]);
+      if (row < rows_left) *reinterpret_cast<float4*>(cm + row * int(N) * 2) = x;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __syncthreads();   // the staged rows have been read and the next ones written
+    buf ^= 1;
+  }
+  if (a.rec_c) amax_commit_wg(mx, sl, a.rec_c, a.rec_c_step);
+}
+
 // ---------------------------------------------------------------------------------
 // split-precision complex GEMM: every FP32 operand value x is split while it is staged
 // into LDS as hi = bf16(x), lo = bf16(x - hi); the product is hi*hi + hi*lo + lo*hi with
@@ -1622,6 +1752,24 @@ hipError_t launch_gemm_n8(const GemmArgs& a, hipStream_t s) {
 
 template <int NK>
 hipError_t launch_gemm_outer_k(const GemmArgs& a, hipStream_t s) {
+  static const bool valu_only = std::getenv("TNC_OUTER_VALU") != nullptr;
+  if constexpr (NK >= 4) {
+    constexpr int JB = 4;
+    if (a.N >= 64 * JB && !valu_only) {
+      // rows per workgroup: up to 1024 (fewer workgroups amortise the B fragments), halved
+      // while the grid would hold fewer than 512 workgroups
+      const int64_t col_blocks = a.N / (64 * JB), zs = a.rows * a.nb;
+      int64_t R = 1024;
+      while (R > kOmRows && col_blocks * ((a.M + R - 1) / R) * zs < 512) R /= 2;
+      const int64_t mrows = a.M < R ? a.M : R;
+      const int64_t blocks = col_blocks * ((a.M + mrows - 1) / mrows);
+      const int64_t gy = zs < 65535 ? zs : 65535;
+      const int64_t gz = (zs + gy - 1) / gy;
+      const dim3 grid{unsigned(blocks), unsigned(gy), unsigned(gz)};
+      hipLaunchKernelGGL((k_gemm_outer_mfma<NK, JB>), grid, dim3(kThreads), 0, s, a);
+      return hipGetLastError();
+    }
+  }
   const int64_t cols = a.N < kOuterCols ? a.N : kOuterCols;
   const int64_t mrows = a.M < kOuterRows ? a.M : kOuterRows;
   const int64_t blocks = (a.N / cols) * ((a.M + mrows - 1) / mrows);

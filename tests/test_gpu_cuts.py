@@ -53,3 +53,28 @@ def test_cut_network_against_oracle(holes, precision):
         f"{metrics.rel_error(ref, uncut):.3e}")
     assert err <= TOLS[precision]
     assert metrics.rel_error(ref, uncut) > 10 * TOLS[precision]
+
+
+def test_cut_network_30_qubits_against_stored_oracle():
+    """The 30-qubit workload (5x6 grid, 14 cycles, all 1024 slices) on its circuit with
+    jittered angles and the 8 companion-edge cuts of its plan's sliced bonds, against the
+    oracle's state vector of the same approximated circuit (stored group of 4096
+    amplitudes, tests/golden)."""
+    from paper_2111_03011_amd.workload import (companion_cuts, companion_workload,
+                                               config_workload, jittered_twin)
+    from tests.golden_data import fidelity_table, sliced_cut_group
+    _, (sigma, seed) = fidelity_table()
+    cuts_ref, ref = sliced_cut_group()
+    twin = jittered_twin(config_workload("sliced"), sigma, seed)
+    cuts = companion_cuts(twin.circuit, twin.sliced_bonds)
+    assert cuts == cuts_ref
+    cw = companion_workload(twin, cuts)
+    c = _contraction(cw, max_batch_slices=64)
+    c.contract()
+    got = c.amps.cpu().numpy()[0]
+    c.close()
+    err = metrics.rel_error(got, ref)
+    log(f"30-qubit cut network ({len(cuts)} cuts, {len(cw.slice_ids)} slices): rel err {err:.3e}, "
+        f"planned flops per slice {cw.plan.cost.flops_per_slice:.3e} "
+        f"(uncut {twin.plan.cost.flops_per_slice:.3e})")
+    assert err <= 1e-5

@@ -422,11 +422,14 @@ def test_every_tile_configuration(config, precision):
     (11, 8, 1, True),     # K = 2, N = 128 (several output rows per pass)
     (9, 6, 0, False),     # K = 1: an outer product
     (8, 7, 2, True),      # K = 4, N = 32, M = 64 (one partial stage)
+    (9, 12, 4, False),    # K = 16 on the matrix cores: M = 32 (one 32-row chunk), N = 256
+    (13, 12, 4, True),    # K = 16 on the matrix cores: N = 256 (one column block), M = 512
+    (10, 10, 4, True),    # K = 16, N = 64: below a 256-column block, vector ALUs
 ])
 def test_short_k_vector_kernel(rank_a, rank_b, shared, interleave, precision):
-    """Configuration 6 (products with K <= 16 on the vector ALUs, chosen for wide outputs)
-    forced on pair products of several shapes, operands read in interleaved label orders;
-    every form computes it in FP32."""
+    """Configuration 6 (products with K <= 16, chosen for wide outputs: on the vector ALUs,
+    or on the FP32 matrix cores for K = 16 and N >= 256) forced on pair products of several
+    shapes, operands read in interleaved label orders; every form computes it in FP32."""
     import os
     log(f"short-K kernel: ranks {rank_a}, {rank_b}, K 2^{shared}, precision {precision}")
     fa = rank_a - shared
@@ -465,7 +468,7 @@ def test_short_k_vector_kernel_rows_and_fold():
     rows folded into M, against the oracle's per-group contraction."""
     import os
     log("short-K kernel with rows")
-    for case in [(3, 7, 1, 6, 3, 12), (3, 7, 0, 6, 3, 8)]:
+    for case in [(3, 7, 1, 6, 3, 12), (3, 7, 0, 6, 3, 8), (3, 7, 1, 8, 4, 12), (3, 7, 0, 8, 4, 8)]:
         net, open_q, closed = _grouped_pair(*case, seed=77)
         ref = _grouped_reference(net, open_q, closed)
         os.environ["TNC_GEMM_CONFIG"] = "6"
