@@ -9,7 +9,7 @@ taken and bitstrings are drawn (one per group, or 1000 from a single group).  Pl
 Default workload (the headline line): the 53-qubit share - 6x9 grid minus site (0,4),
 20 cycles, ABCDCDAB, fSim(pi/2, pi/6), 98 sliced bonds, a fixed 256-slice subset, 2^14
 groups x 6 open qubits (2^20 amplitudes), largest intermediate 2^30 complex64 (8 GiB),
-one slice per launch sequence.  `--workload sliced` runs the 5x6-grid, 14-cycle network
+four slices per launch sequence (109 GB of workspace).  `--workload sliced` runs the 5x6-grid, 14-cycle network
 (1024 slices, 4096 amplitudes) as the line instead; by default it runs as extra keys of
 the headline line together with the split-precision forms, head reuse and the perturbed
 network.
@@ -373,8 +373,8 @@ def pair_errors(c, w, pairs) -> dict:
 
 
 def twin_pair_errors(w, name, pairs) -> dict:
-    """pair_errors on the jittered twin of the workload (same plan, slices and launch
-    configuration, per-gate angles near pi/2)."""
+    """pair_errors on the jittered twin of the workload (same plan and slices, per-gate
+    angles near pi/2), one slice contracted at a time (results do not depend on the batch)."""
     import synth
     from paper_2111_03011_amd.workload import jittered_twin
     j = synth.config("large")["parity_jitter"]
@@ -386,7 +386,7 @@ def twin_pair_errors(w, name, pairs) -> dict:
     return res
 
 
-def large_forms(args, c64_amps, c64_aps, pairs) -> dict:
+def large_forms(args, c64_amps, c64_aps, pairs, batch: int) -> dict:
     """The split-precision forms of the 53-qubit share (same plan, slices, batch): one timed
     whole pass each, amplitudes/s, difference from the complex64 sum, error against the
     stored oracle pairs."""
@@ -395,10 +395,10 @@ def large_forms(args, c64_amps, c64_aps, pairs) -> dict:
     w = config_workload("large")
     res = {}
     for name in ("bf16x3", "fp16x3"):
-        c = contraction(w, name, 1)
+        c = contraction(w, name, batch)
         if args.autotune:
             c.autotune(reps=1)
-        c.contract_range(0, 1)
+        c.contract_range(0, batch)
         torch.cuda.synchronize()
         ms, _ = timed_steps(c, w, args, 1, 0, f"large {name}")
         amps = c.amps.cpu().numpy().copy()
@@ -860,7 +860,7 @@ def main():
     ap.add_argument("--workload", default="large", choices=["large", "sliced", "small", "serving"])
     ap.add_argument("--precision", default="c64", choices=["c64", "bf16x3", "fp16x3"])
     ap.add_argument("--batch", type=int, default=0,
-                    help="slices per launch sequence (0 = the workload's own: 1 for large, "
+                    help="slices per launch sequence (0 = the workload's own: 4 for large, "
                          "8 for large --reuse, 64 for sliced)")
     ap.add_argument("--reuse", action="store_true",
                     help="large: the head-reuse mode (32 subtasks x 8 local slices)")
@@ -893,7 +893,7 @@ def main():
     ap.add_argument("--serving-batch", type=int, default=0,
                     help="serving: slices per launch sequence (0 = chosen per request)")
     args = ap.parse_args()
-    batch = args.batch or {"large": 8 if args.reuse else 1, "sliced": 64, "small": 1}.get(args.workload, 1)
+    batch = args.batch or {"large": 8 if args.reuse else 4, "sliced": 64, "small": 1}.get(args.workload, 1)
     if args.summarise_stats:
         return summarise_stats(args.summarise_stats)
     if args.write_traffic:
@@ -1025,7 +1025,7 @@ def main():
             out["vs_oracle_pairs_jittered_twin"] = twin_pair_errors(w, args.precision, pairs)
     if args.extras and args.workload == "large" and args.precision == "c64" and not args.reuse \
             and not args.max_slices:
-        out["split_precision"] = large_forms(args, main_amps, aps, load_large_golden())
+        out["split_precision"] = large_forms(args, main_amps, aps, load_large_golden(), batch)
         torch.cuda.empty_cache()
         if args.head_reuse:
             out["head_reuse"] = large_reuse(args, aps)
