@@ -1266,13 +1266,22 @@ void log_plan(const tnc_plan_s& p) {
       }
       if (L.kind != K_GEMM) continue;
       const GemmArgs& g = L.gm;
+      // bit positions of the m, k (A) and k, n (B) indices in the operands' dense index
+      std::string pos = " | A m";
+      for (int j = 0; j < g.nm; ++j) pos += " " + std::to_string(g.a_mpos[j]);
+      pos += " k";
+      for (int j = 0; j < g.nk; ++j) pos += " " + std::to_string(g.a_kpos[j]);
+      pos += " | B k";
+      for (int j = 0; j < g.nk; ++j) pos += " " + std::to_string(g.b_kpos[j]);
+      pos += " n";
+      for (int j = 0; j < g.nn; ++j) pos += " " + std::to_string(g.b_npos[j]);
       std::fprintf(stderr,
                    "[tnc plan] %s gemm rows %lld M %lld N %lld K %lld | launch M %lld rows %lld "
-                   "config %d splits %d fold %d stacked %d | a_rows %lld b_rows %lld | %.3g GF\n",
+                   "config %d splits %d fold %d stacked %d | a_rows %lld b_rows %lld | %.3g GF%s\n",
                    phase == 0 ? "inv" : "dep", (long long)L.info.rows, (long long)L.info.m,
                    (long long)L.info.n, (long long)L.info.k, (long long)g.M, (long long)g.rows,
                    g.config, g.k_splits, g.fold, L.stk_off >= 0 ? 1 : 0, (long long)g.a_rows,
-                   (long long)g.b_rows, L.info.flops / 1e9);
+                   (long long)g.b_rows, L.info.flops / 1e9, pos.c_str());
     }
 }
 
