@@ -15,6 +15,7 @@
 #include "tnc.h"
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <climits>
 #include <condition_variable>
@@ -422,30 +423,47 @@ struct Compiler {
   // Tile configuration and split-K.  Debug overrides: TNC_GEMM_CONFIG forces a tile
   // configuration, TNC_SPLITK_BLOCKS sets the workgroup count split-K aims for.
   // Row stacking of output rows that share one Q row: perm sorts the output rows by their
-  // Q row; each 128-row block holds up to 128 / M rows of one Q row (start, count, Q row).
+  // Q row, and within one Q row by their P row; each 128-row block holds up to 128 / M rows
+  // of one Q row (start, count, Q row).  The blocks are then ordered by the P row of their
+  // first output row, so that blocks of different Q rows that read the same P rows are
+  // numbered, hence placed on one XCD and run, close together (a P row used by several
+  // output rows is then read from HBM about once and served from that XCD's L2).
   // Returns the fraction of the stacked M extent that holds real rows.
-  static double stack_rows(const TState& Q, const TState& C, int64_t M, std::vector<int32_t>& stk,
-                           std::vector<int32_t>& perm) {
+  static double stack_rows(const TState& P, const TState& Q, const TState& C, int64_t M,
+                           std::vector<int32_t>& stk, std::vector<int32_t>& perm) {
     const int64_t rows = C.rows();
-    std::vector<int32_t> qrow(size_t(rows), 0);
-    if (Q.q != 0)
+    auto row_of = [&](const TState& S, std::vector<int32_t>& out) {
+      out.assign(size_t(rows), 0);
+      if (S.q == 0) return;
       for (int64_t r = 0; r < rows; ++r) {
-        const uint64_t k = C.keys[size_t(r)] & Q.q;
-        qrow[size_t(r)] = int32_t(std::lower_bound(Q.keys.begin(), Q.keys.end(), k) - Q.keys.begin());
+        const uint64_t k = C.keys[size_t(r)] & S.q;
+        out[size_t(r)] = int32_t(std::lower_bound(S.keys.begin(), S.keys.end(), k) - S.keys.begin());
       }
+    };
+    std::vector<int32_t> qrow, prow;
+    row_of(Q, qrow);
+    row_of(P, prow);
     perm.resize(size_t(rows));
     for (int64_t r = 0; r < rows; ++r) perm[size_t(r)] = int32_t(r);
-    std::stable_sort(perm.begin(), perm.end(),
-                     [&](int32_t x, int32_t y) { return qrow[size_t(x)] < qrow[size_t(y)]; });
-    stk.clear();
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t x, int32_t y) {
+      return qrow[size_t(x)] != qrow[size_t(y)] ? qrow[size_t(x)] < qrow[size_t(y)]
+                                                : prow[size_t(x)] < prow[size_t(y)];
+    });
+    std::vector<std::array<int32_t, 3>> blocks;
     const int64_t per = 128 / M;
     for (int64_t i = 0; i < rows;) {
       int64_t j = i;
       const int32_t q0 = qrow[size_t(perm[size_t(i)])];
       while (j < rows && j - i < per && qrow[size_t(perm[size_t(j)])] == q0) ++j;
-      stk.insert(stk.end(), {int32_t(i), int32_t(j - i), q0});
+      blocks.push_back({int32_t(i), int32_t(j - i), q0});
       i = j;
     }
+    std::stable_sort(blocks.begin(), blocks.end(),
+                     [&](const std::array<int32_t, 3>& x, const std::array<int32_t, 3>& y) {
+                       return prow[size_t(perm[size_t(x[0])])] < prow[size_t(perm[size_t(y[0])])];
+                     });
+    stk.clear();
+    for (const auto& b : blocks) stk.insert(stk.end(), {b[0], b[1], b[2]});
     return double(rows * M) / (double(stk.size() / 3) * 128.0);
   }
 
@@ -461,7 +479,7 @@ struct Compiler {
     fm = std::min(1.0, double(m_eff) / double(kBM[cfg]));
     if (m_eff < 128 && rows > 1 && Q.rows() < rows && stacking_enabled()) {
       std::vector<int32_t> stk, perm;
-      fm = std::max(fm, stack_rows(Q, C, M, stk, perm));
+      fm = std::max(fm, stack_rows(P, Q, C, M, stk, perm));
     }
     // an N <= 8 step is charged as a 16-wide tile: its 16x16x4 tiles reuse operands less
     // than a stacked orientation of the same step would
@@ -703,7 +721,7 @@ struct Compiler {
     std::vector<int32_t> stk, perm;
     if (!g.fold && rows > 1 && M < 128 && Q.rows() < rows && stacking_enabled() &&
         double(P.elems()) < 2147483648.0) {
-      const double fill_stacked = stack_rows(Q, C, M, stk, perm);
+      const double fill_stacked = stack_rows(P, Q, C, M, stk, perm);
       const double fill_plain = double(M) / (M <= 64 ? 64.0 : 128.0);
       if (fill_stacked > 1.25 * fill_plain) {
         M = int64_t(stk.size() / 3) * 128;
