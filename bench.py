@@ -354,6 +354,8 @@ def cpu_baseline_large(w, flops_per_slice: float, pos: int = 0, group: int = 0):
                       f"oracle an estimated {est:.0f} s",
             "oracle_pair_seconds": sec, "estimated_seconds_per_slice": est,
             "estimated_amplitudes_per_s": w.n_amplitudes / (est * len(w.slice_ids)),
+            # as the oracle computes them: one group's 64 amplitudes of one slice per pair
+            "oracle_pair_amplitudes_per_s": out.size / sec,
             "host": hi}, {(pos, group): out.reshape(-1)}
 
 

@@ -37,8 +37,9 @@ from oracle import contract, network, statevector  # noqa: E402
 
 SLICED_FILE = os.path.join(HERE, "sliced_5x6_m14_full_sum.txt")
 LARGE_FILE = os.path.join(HERE, "large_53q_m20_slice_group.txt")
-# (position in the 256-slice subset, group index) pairs of the 53-qubit share
-LARGE_PAIRS = [(0, 0), (137, 9001)]
+# (position in the 256-slice subset, group index) pairs of the 53-qubit share: two spread
+# pairs, and group 0 of the first four positions (one whole launch sequence of four slices)
+LARGE_PAIRS = [(0, 0), (137, 9001), (1, 0), (2, 0), (3, 0)]
 LARGE_PATH_SEED = 5101
 
 

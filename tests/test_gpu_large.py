@@ -5,7 +5,9 @@ Oracle parity at full size: stored oracle amplitudes of single (slice, group) pa
 (tests/golden, the oracle's own network for one group with the slice's bonds fixed,
 contracted along its seeded random-greedy path, which keeps every intermediate <= 2^26)
 against the same group inside the library's 2^14-group sparse state, contracted in the
-launch configuration bench.py times (one slice per launch sequence, autotuned tiles).
+launch configuration bench.py times (four slices per launch sequence, autotuned tiles): one
+slice at a time, and a whole launch sequence of four slices through a captured graph,
+first and replayed pass, against the sum of the four stored slices.
 Properties that hold at any size complete it: a group inside the sparse state equals a
 separate contraction with that group alone, and head reuse equals the plain plan."""
 
@@ -41,8 +43,9 @@ def test_large_pairs_match_stored_oracle(form):
     w = jittered_twin(config_workload("large"), *jitter)
     assert [tuple(b) for b in w.sliced_bonds] == bonds, "the stored pairs were made for another slicing"
     c = Contraction(w.net, w.plan.path, sliced_labels=w.plan.sliced_labels, slice_ids=w.slice_ids,
-                    open_qubits=w.open_qubits, closed_bits=w.closed_bits, max_batch_slices=1,
+                    open_qubits=w.open_qubits, closed_bits=w.closed_bits, max_batch_slices=4,
                     precision=prec)
+    assert c.batch_slices == 4
     c.autotune(reps=1)
     for p in pairs:
         assert int(w.slice_ids[p.pos]) == p.slice_id and int(w.closed_bits[p.group]) == p.closed
@@ -53,6 +56,16 @@ def test_large_pairs_match_stored_oracle(form):
         mx = metrics.max_error_over_rms(got, p.amps)
         log(f"  rel err {err:.3e}, max err / rms {mx:.3e}, |amp| ~ {np.abs(p.amps).max():.1e}")
         assert err <= tol and mx <= 10 * tol
+    # one whole launch sequence: slice positions 0..3, captured and replayed
+    batch = [p for p in pairs if p.group == 0 and p.pos < 4]
+    assert sorted(p.pos for p in batch) == [0, 1, 2, 3]
+    ref = sum(p.amps for p in batch)
+    for rep in range(2):
+        c.contract_range(0, 4)
+        got = c.amps[0].cpu().numpy()
+        err = metrics.rel_error(got, ref)
+        log(f"  slices 0..3 as one launch sequence (pass {rep}): rel err {err:.3e}")
+        assert err <= tol
     c.close()
 
 
