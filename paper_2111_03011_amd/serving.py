@@ -39,11 +39,16 @@ class Server:
         return rid
 
     def poll(self, rid: int):
-        """None while the request runs, else a dict with amplitudes, bitstrings and times."""
+        """None while the request runs, else a dict with amplitudes, bitstrings and times;
+        raises TncError with the request's status if it failed."""
         L, l, k = self._shape[rid]
         amps = np.zeros((L, l), dtype=np.complex128)
         bits = np.zeros(k, dtype=np.uint64) if k else None
-        st, info = tnc.tnc_server_poll(self._h, rid, amps.view(np.float64), bits)
+        try:
+            st, info = tnc.tnc_server_poll(self._h, rid, amps.view(np.float64), bits)
+        except tnc.TncError:
+            self._shape.pop(rid, None)     # the failed request is retired; its status raises
+            raise
         if st == tnc.TNC_E_BUSY:
             return None
         del self._shape[rid]
