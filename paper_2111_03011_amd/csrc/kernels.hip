@@ -939,6 +939,100 @@ __global__ __launch_bounds__(kThreads) void k_gemm_outer(GemmArgs a) {
   if (a.rec_c) amax_commit_wg(mx, sl, a.rec_c, a.rec_c_step);
 }
 
+// Sparse-state steps whose rows each hold a small product (M x N <= 128, N <= 4, M >= 8)
+// over a long contraction (64 <= K <= 4096), e.g. 16384 rows of 32 x 2 x 512: the tiles of
+// the matrix-core kernels would be mostly empty and their loads mostly masked.  One wave
+// per (slice, row): lane l takes k = 16 k_hi + l % 16 and the rows m = 4 m_hi + l / 16, so
+// one load instruction reads 16 consecutive k of 4 rows of A (whole 128-byte pieces when
+// A's lowest index bits are k bits); each lane accumulates its share of k for its M/4 x N
+// outputs in registers, and the 16 lanes of one row group are summed with cross-lane
+// shuffles.  Offsets of A's and B's k indices sit in LDS tables (dynamic shared memory,
+// 8 bytes per k), those of m and n in small static ones.  Operands are rescaled by their
+// records while loaded, as everywhere; the output's largest component is committed per
+// wave (a workgroup's waves may belong to two slices).
+template <int MH, int NN>
+__global__ __launch_bounds__(kThreads) void k_gemm_rows_narrow(GemmArgs a) {
+  constexpr int NS = 1 << NN, MR = 4 * MH;
+  extern __shared__ int32_t ktabs[];   // [K] A offsets of k, then [K] B offsets of k
+  __shared__ int32_t moff[MR], noff[NS];
+  const int K = int(a.K);
+  int32_t* koa = ktabs;
+  int32_t* kob = ktabs + K;
+  for (int k = threadIdx.x; k < K; k += kThreads) {
+    koa[k] = int32_t(scatter_u<kMaxRank>(k, a.a_kpos, a.nk));
+    kob[k] = int32_t(scatter_u<kMaxRank>(k, a.b_kpos, a.nk));
+  }
+  for (int m = threadIdx.x; m < MR; m += kThreads) moff[m] = int32_t(scatter_u<kMaxRank>(m, a.a_mpos, a.nm));
+  for (int n = threadIdx.x; n < NS; n += kThreads) noff[n] = int32_t(scatter_u<kMaxRank>(n, a.b_npos, a.nn));
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kl = lane & 15, ms = lane >> 4;
+  const int64_t z = (int64_t(blockIdx.x) + int64_t(blockIdx.y) * gridDim.x) * 4 + wave;
+  float mx = 0.f;
+  if (z < a.rows * a.nb) {
+    const int64_t sl = z / a.rows, r = z - sl * a.rows;
+    const int64_t ar = a.ga ? a.ga[r] : (a.a_rows == 1 ? 0 : r);
+    const int64_t br = a.gb ? a.gb[r] : (a.b_rows == 1 ? 0 : r);
+    const float2* A = a.A + sl * a.a_slice_stride + ar * a.a_row_stride;
+    const float2* B = a.B + sl * a.b_slice_stride + br * a.b_row_stride;
+    float sa = 1.f, sb = 1.f;
+    if (a.rec_c) {
+      int sha, shb, ea, eb;
+      rec_load(a.rec_a, a.rec_a_step, sl, false, sha, ea);
+      rec_load(a.rec_b, a.rec_b_step, sl, false, shb, eb);
+      sa = pow2f(sha);
+      sb = pow2f(shb);
+      if (r == 0 && lane == 0) a.rec_c[sl * a.rec_c_step + kRecExp] = uint32_t(ea + eb - sha - shb);
+    }
+    int32_t mo[MH];
+#pragma unroll
+    for (int mh = 0; mh < MH; ++mh) mo[mh] = moff[4 * mh + ms];
+    float2 acc[MH][NS];
+#pragma unroll
+    for (int mh = 0; mh < MH; ++mh)
+#pragma unroll
+      for (int n = 0; n < NS; ++n) acc[mh][n] = make_float2(0.f, 0.f);
+#pragma unroll 2
+    for (int k = kl; k < K; k += 16) {
+      const int32_t ka = koa[k], kb = kob[k];
+      float2 bv[NS];
+#pragma unroll
+      for (int n = 0; n < NS; ++n) {
+        const float2 v = B[kb + noff[n]];
+        bv[n] = make_float2(v.x * sb, v.y * sb);
+      }
+#pragma unroll
+      for (int mh = 0; mh < MH; ++mh) {
+        const float2 v = A[mo[mh] + ka];
+        const float2 av = make_float2(v.x * sa, v.y * sa);
+#pragma unroll
+        for (int n = 0; n < NS; ++n) {
+          acc[mh][n].x += av.x * bv[n].x - av.y * bv[n].y;
+          acc[mh][n].y += av.x * bv[n].y + av.y * bv[n].x;
+        }
+      }
+    }
+    float2* C = a.C + sl * a.c_slice_stride + r * a.c_row_stride;
+#pragma unroll
+    for (int mh = 0; mh < MH; ++mh)
+#pragma unroll
+      for (int n = 0; n < NS; ++n) {
+        float re = acc[mh][n].x, im = acc[mh][n].y;
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+          re += __shfl_xor(re, off);
+          im += __shfl_xor(im, off);
+        }
+        if (kl == 0) {
+          C[(4 * mh + ms) * NS + n] = make_float2(re, im);
+          mx = fmaxf(mx, fmaxf(fabsf(re), fabsf(im)));
+        }
+      }
+  }
+  // the four waves of a workgroup may hold rows of two slices: one commit per wave
+  if (a.rec_c && z < a.rows * a.nb) amax_commit(mx, z / a.rows, a.rec_c, a.rec_c_step);
+}
+
 // The same short-K product on the FP32 matrix cores, for K = 2^NK = 16 and N >= 64 JB,
 // where the vector form above is bound by its 4 K FMAs per complex output (64 at K = 16, at
 // half the FP32 rate without packed instructions) rather than by writing C.  A workgroup
@@ -1735,7 +1829,44 @@ hipError_t launch_stream(const StreamArgs& a, hipStream_t s) {
 // 1 = 128 x 16 (4x1 waves, one MFMA tile each), 2 = 64 x 32 (2x2 waves, one tile each),
 // 3 = 128 x 128 (2x2 waves, 2x4 MFMA tiles each), 4 = 128 x 32 (4x1 waves, 1x2 tiles each),
 // 5 = 128 x 8 on 16x16x4 MFMA tiles (complex64 only; split precision uses 1).
+template <int MH, int NN>
+hipError_t launch_rows_narrow_t(const GemmArgs& a, hipStream_t s) {
+  const int64_t waves = a.rows * a.nb, blocks = (waves + 3) / 4;
+  const int64_t gx = blocks < 65535 ? blocks : 65535;
+  const int64_t gy = (blocks + gx - 1) / gx;
+  hipLaunchKernelGGL((k_gemm_rows_narrow<MH, NN>), dim3(unsigned(gx), unsigned(gy)), dim3(kThreads),
+                     size_t(2 * a.K) * sizeof(int32_t), s, a);
+  return hipGetLastError();
+}
+
+// k_gemm_rows_narrow for its shapes (see there), or an error when none applies
+hipError_t launch_rows_narrow(const GemmArgs& a, hipStream_t s) {
+  const int mh = int(a.M / 4);
+  switch (mh * 8 + a.nn) {
+    case 2 * 8 + 0: return launch_rows_narrow_t<2, 0>(a, s);
+    case 2 * 8 + 1: return launch_rows_narrow_t<2, 1>(a, s);
+    case 2 * 8 + 2: return launch_rows_narrow_t<2, 2>(a, s);
+    case 4 * 8 + 0: return launch_rows_narrow_t<4, 0>(a, s);
+    case 4 * 8 + 1: return launch_rows_narrow_t<4, 1>(a, s);
+    case 4 * 8 + 2: return launch_rows_narrow_t<4, 2>(a, s);
+    case 8 * 8 + 0: return launch_rows_narrow_t<8, 0>(a, s);
+    case 8 * 8 + 1: return launch_rows_narrow_t<8, 1>(a, s);
+    case 8 * 8 + 2: return launch_rows_narrow_t<8, 2>(a, s);
+    case 16 * 8 + 0: return launch_rows_narrow_t<16, 0>(a, s);
+    case 16 * 8 + 1: return launch_rows_narrow_t<16, 1>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+static bool rows_narrow_fits(const GemmArgs& a) {
+  static const bool off = std::getenv("TNC_NO_NARROW") != nullptr;
+  return !off && a.precision == 0 && !a.stk && !a.fold && a.k_splits == 1 &&
+         a.M == (int64_t(1) << a.nm) && a.M >= 8 && a.M <= 64 && a.nn <= 2 &&
+         a.M * a.N <= 128 && a.K >= 64 && a.K <= 4096;
+}
+
 hipError_t launch_gemm_n8(const GemmArgs& a, hipStream_t s) {
+  if (rows_narrow_fits(a)) return launch_rows_narrow(a, s);
   const int64_t tiles = ((a.M + 127) / 128) * ((a.N + 7) / 8);
   const int64_t zs = a.rows * a.nb * a.k_splits;
   const int64_t gy = zs < 65535 ? zs : 65535;

@@ -487,6 +487,37 @@ def test_short_k_vector_kernel_rows_and_fold():
         assert err <= TOL
 
 
+@pytest.mark.parametrize("case", [
+    (3, 5, 2, 1, 9, 24),    # rows of M 32, N 2, K 512 (the 53-qubit share's narrow step)
+    (3, 4, 2, 2, 7, 12),    # M 16, N 4, K 128
+    (3, 3, 2, 0, 10, 12),   # M 8, N 1, K 1024
+    (3, 6, 2, 1, 7, 16),    # M 64, N 2, K 128
+    (2, 4, 3, 1, 11, 12),   # oriented M 2, N 16: the 16x16x4 matrix-core kernel instead
+])
+def test_rows_of_narrow_long_k_products(case):
+    """Sparse-state steps whose rows are small products over a long contraction (one wave
+    per row, k spread over the lanes and summed across them), forced through configuration
+    5, against the oracle's per-group contraction."""
+    import os
+    net, open_q, closed = _grouped_pair(*case, seed=91)
+    ref = _grouped_reference(net, open_q, closed)
+    os.environ["TNC_GEMM_CONFIG"] = "5"
+    try:
+        c = _contraction(net, [(0, 1)], open_qubits=open_q, closed_bits=closed)
+    finally:
+        os.environ.pop("TNC_GEMM_CONFIG", None)
+    g = [l for l in c.launches() if l.kind == 1]
+    if not g or g[0].config != 5:
+        c.close()
+        pytest.skip("the planner took another form for this product")
+    log(f"narrow rows {case}: rows {g[0].rows} M {g[0].m} N {g[0].n} K {g[0].k}")
+    c.contract()
+    err = metrics.rel_error(c.amps.cpu().numpy(), ref)
+    c.close()
+    log(f"  rel err {err:.3e}")
+    assert err <= TOL
+
+
 @pytest.mark.parametrize("config", [7, 8])
 @pytest.mark.parametrize("precision", [2, 1])
 @pytest.mark.parametrize("order", ["plain", "interleaved"])
