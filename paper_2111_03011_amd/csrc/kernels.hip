@@ -639,11 +639,12 @@ struct GemmTile {
 };
 
 template <int WAVES_M, int WAVES_N, int UM, int UN, int BK, bool A_MFAST, bool B_NFAST>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_gemm(GemmArgs a) {
-  static_assert(WAVES_M * WAVES_N == 4, "four waves per workgroup");
+__global__ __launch_bounds__(WAVES_M * WAVES_N * 64) __attribute__((amdgpu_waves_per_eu(WAVES_M * WAVES_N == 4 ? 3 : 2))) void k_gemm(GemmArgs a) {
+  constexpr int NT = WAVES_M * WAVES_N * 64;   // four or eight waves
+  static_assert(NT == 256 || NT == 512, "four or eight waves per workgroup");
   constexpr int BM = WAVES_M * UM * 32;
   constexpr int BN = WAVES_N * UN * 16;
-  using Tile = GemmTile<BM, BN, BK, A_MFAST, B_NFAST, true>;
+  using Tile = GemmTile<BM, BN, BK, A_MFAST, B_NFAST, true, NT>;
   constexpr int A_LD = Tile::A_LD, B_LD = Tile::B_LD;
   constexpr int AS = 2 * BK + 2;       // floats per LDS row of A (m-major)
   constexpr int BS = 2 * BN;           // floats per LDS row of B (k-major; reads are broadcasts)
@@ -681,7 +682,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
       *reinterpret_cast<float2*>(&as[Tile::a_row(i) * AS + 2 * Tile::a_col(i)]) = ra[i];
 #pragma unroll
     for (int i = 0; i < B_LD; ++i)
-      if (BK * BN % kThreads == 0 || threadIdx.x + i * kThreads < BK * BN)
+      if (BK * BN % NT == 0 || threadIdx.x + i * NT < BK * BN)
         *reinterpret_cast<float2*>(&bs[Tile::b_kr(i) * BS + 2 * Tile::b_n(i)]) = rb[i];
   };
 
@@ -1926,10 +1927,11 @@ hipError_t launch_gemm_outer(const GemmArgs& a, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-// Configurations 7 and 8: eight-wave workgroups for the split-precision forms, each wave
-// with the 2 x 2 matrix-core tiles of configuration 0, so one workgroup covers 128 x 128
-// (7) or 256 x 64 (8) complex outputs and every staged operand byte feeds more matrix
-// instructions than with 128 x 64; 96 or 80 KB of LDS per workgroup; no row stacking.
+// Configurations 7 and 8: eight-wave workgroups, each wave with the 2 x 2 matrix-core
+// tiles of configuration 0, so one workgroup covers 128 x 128 (7) or 256 x 64 (8) complex
+// outputs and every staged operand byte feeds more matrix instructions than with 128 x 64;
+// split precision (96 or 80 KB of LDS per workgroup) and complex64 (k_gemm with eight
+// waves, 68 or 86 KB); no row stacking.
 template <int WM, int WN>
 hipError_t launch_gemm_split_big_t(const GemmArgs& a, hipStream_t s) {
   constexpr int UM = 2, UN = 2;
@@ -1940,6 +1942,15 @@ hipError_t launch_gemm_split_big_t(const GemmArgs& a, hipStream_t s) {
   const int64_t gz = (zs + gy - 1) / gy;
   const dim3 grid{unsigned(tiles), unsigned(gy), unsigned(gz)};
   const int sel = (a.a_mfast ? 1 : 0) | (a.b_nfast ? 2 : 0);
+  if (a.precision == 0) {      // complex64: the FP32 kernel with eight waves
+    switch (sel) {
+      case 0: hipLaunchKernelGGL((k_gemm<WM, WN, UM, UN, 16, false, false>), grid, dim3(WM * WN * 64), 0, s, a); break;
+      case 1: hipLaunchKernelGGL((k_gemm<WM, WN, UM, UN, 16, true, false>), grid, dim3(WM * WN * 64), 0, s, a); break;
+      case 2: hipLaunchKernelGGL((k_gemm<WM, WN, UM, UN, 16, false, true>), grid, dim3(WM * WN * 64), 0, s, a); break;
+      default: hipLaunchKernelGGL((k_gemm<WM, WN, UM, UN, 16, true, true>), grid, dim3(WM * WN * 64), 0, s, a); break;
+    }
+    return hipGetLastError();
+  }
   const int mode = a.precision == 1 ? 0 : 2;
   switch (sel * 3 + mode) {
 #define TNC_BIG_CASE(S, MD, AF, BF)                                                            \
@@ -1957,7 +1968,7 @@ hipError_t launch_gemm_split_big_t(const GemmArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_gemm_split_big(const GemmArgs& a, hipStream_t s) {
-  if (a.stk || (a.precision != 1 && a.precision != 3)) return hipErrorInvalidValue;
+  if (a.stk || (a.precision != 0 && a.precision != 1 && a.precision != 3)) return hipErrorInvalidValue;
   return a.config == 7 ? launch_gemm_split_big_t<2, 4>(a, s) : launch_gemm_split_big_t<4, 2>(a, s);
 }
 

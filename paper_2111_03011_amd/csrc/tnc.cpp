@@ -496,10 +496,10 @@ struct Compiler {
     return on;
   }
 
-  // the short-K vector kernel (configuration 6) takes K <= 16 without row stacking; the
-  // eight-wave tiles (configurations 7, 8) split-precision products without row stacking
+  // the short-K kernel (configuration 6) takes K <= 16 without row stacking; the eight-wave
+  // tiles (configurations 7, 8) any precision without row stacking
   static bool outer_ok(const GemmArgs& g, bool stacked) { return g.nk <= 4 && !stacked; }
-  static bool big_ok(const GemmArgs& g, bool stacked) { return g.precision != 0 && !stacked; }
+  static bool big_ok(const GemmArgs& g, bool stacked) { (void)g; return !stacked; }
 
   static void choose_tiles(GemmArgs& g, int64_t M, int64_t N, int64_t Kd, int64_t rows,
                            bool stacked) {
