@@ -1829,7 +1829,8 @@ hipError_t launch_stream(const StreamArgs& a, hipStream_t s) {
 // Tile configurations (complex elements): 0 = 128 x 64 (2x2 waves, 2x2 MFMA tiles each),
 // 1 = 128 x 16 (4x1 waves, one MFMA tile each), 2 = 64 x 32 (2x2 waves, one tile each),
 // 3 = 128 x 128 (2x2 waves, 2x4 MFMA tiles each), 4 = 128 x 32 (4x1 waves, 1x2 tiles each),
-// 5 = 128 x 8 on 16x16x4 MFMA tiles (complex64 only; split precision uses 1).
+// 5 = 128 x 8 on 16x16x4 MFMA tiles (complex64 only; split precision uses 1), or, for rows
+// of narrow long-K products, k_gemm_rows_narrow in every form.
 template <int MH, int NN>
 hipError_t launch_rows_narrow_t(const GemmArgs& a, hipStream_t s) {
   const int64_t waves = a.rows * a.nb, blocks = (waves + 3) / 4;
@@ -1859,12 +1860,16 @@ hipError_t launch_rows_narrow(const GemmArgs& a, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-static bool rows_narrow_fits(const GemmArgs& a) {
+// Shapes k_gemm_rows_narrow takes (every form: it computes in FP32, as the short-K kernel
+// does for split plans); TNC_NO_NARROW=1 turns it off.
+bool gemm_rows_narrow_fits(const GemmArgs& a, bool stacked) {
   static const bool off = std::getenv("TNC_NO_NARROW") != nullptr;
-  return !off && a.precision == 0 && !a.stk && !a.fold && a.k_splits == 1 &&
+  return !off && !stacked && !a.fold && a.k_splits == 1 &&
          a.M == (int64_t(1) << a.nm) && a.M >= 8 && a.M <= 64 && a.nn <= 2 &&
          a.M * a.N <= 128 && a.K >= 64 && a.K <= 4096;
 }
+
+static bool rows_narrow_fits(const GemmArgs& a) { return gemm_rows_narrow_fits(a, a.stk != nullptr); }
 
 hipError_t launch_gemm_n8(const GemmArgs& a, hipStream_t s) {
   if (rows_narrow_fits(a)) return launch_rows_narrow(a, s);
@@ -1976,7 +1981,7 @@ hipError_t launch_gemm(const GemmArgs& a, hipStream_t s) {
   if (a.config == 6) return launch_gemm_outer(a, s);
   if (a.config == 7 || a.config == 8) return launch_gemm_split_big(a, s);
   if (a.config == 5) {
-    if (a.precision == 0) return launch_gemm_n8(a, s);
+    if (a.precision == 0 || rows_narrow_fits(a)) return launch_gemm_n8(a, s);
     GemmArgs b = a;            // the split-precision kernels have no 8-wide tile
     b.config = 1;
     return launch_gemm(b, s);

@@ -491,10 +491,8 @@ struct Compiler {
   // the eight-wave 128 x 128 and 256 x 64 tiles of the split-precision forms
   static constexpr int kConfigs = 9;
 
-  static bool stacking_enabled() {
-    static const bool on = std::getenv("TNC_NO_STACK") == nullptr;
-    return on;
-  }
+  // read at every plan compile, so that one process can build plans both ways
+  static bool stacking_enabled() { return std::getenv("TNC_NO_STACK") == nullptr; }
 
   // the short-K kernel (configuration 6) takes K <= 16 without row stacking; the eight-wave
   // tiles (configurations 7, 8) any precision without row stacking
@@ -746,7 +744,9 @@ struct Compiler {
       L.stk_off = add_const(stk.data(), stk.size() * sizeof(int32_t));
       L.perm_off = add_const(perm.data(), perm.size() * sizeof(int32_t));
     }
-    if (plan.precision != TNC_C64 && g.config == 5) g.config = 1;   // no 8-wide split tile
+    // no 8-wide split tile; rows of narrow long-K products keep the FP32 narrow-row kernel
+    if (plan.precision != TNC_C64 && g.config == 5 && !gemm_rows_narrow_fits(g, !stk.empty()))
+      g.config = 1;
     C.rec = new_rec(inv ? REC_INV : REC_DEP, ps);
     L.rec_in0 = P.rec;
     L.rec_in1 = Q.rec;
@@ -1442,8 +1442,11 @@ int autotune(tnc_plan_s& p, uint8_t* ws, hipStream_t st, int reps) {
       } else {
         // the planned choice is timed first, so that it survives ties
         std::vector<std::pair<int, int>> cands{best};
+        GemmArgs one = L.gm;
+        one.k_splits = 1;
+        const bool narrow = gemm_rows_narrow_fits(one, L.stk_off >= 0);
         for (int cfg = 0; cfg < Compiler::kConfigs; ++cfg) {
-          if (cfg == 5 && L.gm.precision != 0) continue;
+          if (cfg == 5 && L.gm.precision != 0 && !narrow) continue;
           if (cfg == 6 && !Compiler::outer_ok(L.gm, L.stk_off >= 0)) continue;
           if (cfg >= 7 && !Compiler::big_ok(L.gm, L.stk_off >= 0)) continue;
           for (int sp = 1; sp <= (cfg == 6 ? 1 : L.max_splits); sp *= 2)

@@ -152,6 +152,9 @@ struct SliceSumArgs {
 // Launchers (return hipError_t of the launch).
 hipError_t launch_stream(const StreamArgs& a, hipStream_t s);
 hipError_t launch_gemm(const GemmArgs& a, hipStream_t s);
+// whether configuration 5 runs a launch on the narrow-row kernel (k_gemm_rows_narrow),
+// which computes in FP32 in every form
+bool gemm_rows_narrow_fits(const GemmArgs& a, bool stacked);
 // p[0..n) = 0 (clears scale records before their producers fold into them)
 hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);

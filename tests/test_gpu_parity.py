@@ -490,25 +490,31 @@ def test_short_k_vector_kernel_rows_and_fold():
     (3, 4, 2, 2, 7, 12),    # M 16, N 4, K 128
     (3, 3, 2, 0, 10, 12),   # M 8, N 1, K 1024
     (3, 6, 2, 1, 7, 16),    # M 64, N 2, K 128
-    (2, 4, 3, 1, 11, 12),   # oriented M 2, N 16: the 16x16x4 matrix-core kernel instead
+    (2, 4, 3, 1, 11, 12),   # M 16, N 2, K 2048
 ])
-def test_rows_of_narrow_long_k_products(case):
+@pytest.mark.parametrize("precision", [0, 2, 1])
+def test_rows_of_narrow_long_k_products(case, precision):
     """Sparse-state steps whose rows are small products over a long contraction (one wave
-    per row, k spread over the lanes and summed across them), forced through configuration
-    5, against the oracle's per-group contraction."""
+    per row, k spread over the lanes and summed across them, in FP32 in every form), forced
+    through configuration 5, against the oracle's per-group contraction."""
     import os
     net, open_q, closed = _grouped_pair(*case, seed=91)
     ref = _grouped_reference(net, open_q, closed)
     os.environ["TNC_GEMM_CONFIG"] = "5"
+    # neither split-K nor row stacking: the narrow-row kernel takes the step
+    os.environ["TNC_SPLITK_BLOCKS"] = "1"
+    os.environ["TNC_NO_STACK"] = "1"
     try:
-        c = _contraction(net, [(0, 1)], open_qubits=open_q, closed_bits=closed)
+        c = _contraction(net, [(0, 1)], open_qubits=open_q, closed_bits=closed, precision=precision)
     finally:
-        os.environ.pop("TNC_GEMM_CONFIG", None)
+        for k in ("TNC_GEMM_CONFIG", "TNC_SPLITK_BLOCKS", "TNC_NO_STACK"):
+            os.environ.pop(k, None)
     g = [l for l in c.launches() if l.kind == 1]
     if not g or g[0].config != 5:
         c.close()
-        pytest.skip("the planner took another form for this product")
-    log(f"narrow rows {case}: rows {g[0].rows} M {g[0].m} N {g[0].n} K {g[0].k}")
+        pytest.skip("this product runs on another kernel in this form")
+    assert g[0].k_splits == 1
+    log(f"narrow rows {case}, precision {precision}: rows {g[0].rows} M {g[0].m} N {g[0].n} K {g[0].k}")
     c.contract()
     err = metrics.rel_error(c.amps.cpu().numpy(), ref)
     c.close()
