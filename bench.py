@@ -394,7 +394,7 @@ def large_forms(args, c64_amps, c64_aps, pairs, batch: int) -> dict:
     stored oracle pairs."""
     import torch
     from paper_2111_03011_amd.workload import config_workload
-    w = config_workload("large")
+    w = config_workload("large", mode="default" if args.plain_path else "branch")
     res = {}
     for name in ("bf16x3", "fp16x3"):
         c = contraction(w, name, batch)
@@ -442,6 +442,35 @@ def large_reuse(args, c64_aps) -> dict:
                      "workspace_gb": c.ws_bytes / 1e9}
         c.close()
         log(f"large reuse {name}: {aps:.0f} amplitudes/s ({aps / c64_aps:.2f}x plain c64)")
+    return res
+
+
+def large_plain_path(args, merged_aps, batch: int) -> dict:
+    """The 53-qubit share on the plain path (the planner's path before branch merging; same
+    sliced bonds and slices): one timed whole pass per form, against the branch-merged
+    complex64 rate of the headline."""
+    import torch
+    from paper_2111_03011_amd.workload import config_workload
+    w0 = config_workload("large")
+    w = config_workload("large", mode="branch")
+    res = {"flops_per_slice_plain": w0.plan.cost.flops_per_slice,
+           "flops_per_slice_branch_merged": w.plan.cost.flops_per_slice}
+    for name in ("c64", "bf16x3", "fp16x3"):
+        c = contraction(w0, name, batch)
+        if args.autotune:
+            c.autotune(reps=1)
+        c.contract_range(0, batch)
+        torch.cuda.synchronize()
+        ms, _ = timed_steps(c, w0, args, 1, 0, f"large plain path {name}")
+        aps = w0.n_amplitudes / (ms[0] * 1e-3)
+        res[name] = {"amplitudes_per_s": aps, "ms_per_step": ms[0],
+                     "ms_per_slice": ms[0] / len(w0.slice_ids),
+                     "tflops": c.work() / (ms[0] * 1e-3) / 1e12,
+                     "branch_merged_c64_speedup": merged_aps / aps,
+                     "workspace_gb": c.ws_bytes / 1e9}
+        c.close()
+        log(f"large plain path {name}: {ms[0] / len(w0.slice_ids):.2f} ms per slice")
+        torch.cuda.empty_cache()
     return res
 
 
@@ -634,6 +663,18 @@ def kernels_sha256():
     return hashlib.sha256(src).hexdigest()
 
 
+def headline_mode(args) -> str:
+    """Workload mode of the timed run: the 53-qubit share runs its branch-merged path
+    (planner.merge_branches) unless --plain-path or --reuse asks otherwise."""
+    if args.workload == "small":
+        return "samples"
+    if args.reuse:
+        return "reuse"
+    if args.workload == "large" and not args.plain_path:
+        return "branch"
+    return "default"
+
+
 def measured_traffic(args, batch: int):
     """HBM bytes per launch of the dominant GEMM kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE passes (calibrated against a plain device copy), or None when
@@ -645,7 +686,8 @@ def measured_traffic(args, batch: int):
     except OSError:
         return None
     if (rec.get("kernels_hip_sha256") != sha or rec.get("workload") != args.workload or
-            rec.get("precision") != args.precision or rec.get("batch") != batch):
+            rec.get("precision") != args.precision or rec.get("batch") != batch or
+            rec.get("mode", "default") != headline_mode(args)):
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -677,6 +719,7 @@ def write_traffic(args, batch: int, fetch_csv, write_csv):
     f_fac, w_fac = kib / f_copy, kib / w_copy
     rec = {
         "kernel": name.strip(":<"), "workload": args.workload, "precision": args.precision,
+        "mode": headline_mode(args),
         "batch": batch, "kernels_hip_sha256": kernels_sha256(),
         "slices_profiled": args.max_slices or "all", "dispatches": [n_f, n_w],
         "fetch_kib_per_launch_raw": round(f_kib, 2), "write_kib_per_launch_raw": round(w_kib, 2),
@@ -873,6 +916,8 @@ def main():
                          "share, and the 5x6-grid network in every form (1/0)")
     ap.add_argument("--head-reuse", type=int, default=1, help="5x6 network: also the reuse plan")
     ap.add_argument("--perturbed", type=int, default=1, help="5x6 network: also the drilled one")
+    ap.add_argument("--plain-path", action="store_true",
+                    help="large: time the plain path instead of the branch-merged one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--step-table", metavar="PATH", help="write the per-launch timing table")
     ap.add_argument("--max-slices", type=int, default=0,
@@ -922,7 +967,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     t_plan = time.perf_counter()
-    mode = "samples" if args.workload == "small" else ("reuse" if args.reuse else "default")
+    mode = headline_mode(args)
     w = config_workload(args.workload, mode=mode)
     if args.max_slices:
         w = dataclasses.replace(w, slice_ids=w.slice_ids[:args.max_slices])
@@ -980,7 +1025,8 @@ def main():
         "data": "synthetic (seeded Sycamore-like circuit; random gates, no dataset)",
         "config": {
             "workload": WORKLOAD_TEXT[args.workload]
-                        + (" (head reuse: 32 subtasks x 8 local slices)" if args.reuse else ""),
+                        + (" (head reuse: 32 subtasks x 8 local slices)" if args.reuse else "")
+                        + (" (branch-merged path)" if mode == "branch" else ""),
             "slices": int(len(w.slice_ids)),
             "amplitudes": int(w.n_amplitudes),
             "largest_intermediate_log2": float(w.plan.cost.peak_log2),
@@ -1031,6 +1077,9 @@ def main():
         torch.cuda.empty_cache()
         if args.head_reuse:
             out["head_reuse"] = large_reuse(args, aps)
+            torch.cuda.empty_cache()
+        if mode == "branch":
+            out["plain_path"] = large_plain_path(args, aps, batch)
             torch.cuda.empty_cache()
         out["zigzag_tail"] = large_zigzag(args)
         torch.cuda.empty_cache()

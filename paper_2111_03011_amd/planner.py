@@ -27,6 +27,16 @@ minimise the per-slice work when every step that depends on global labels only i
 computed once per batch of B slices.  Local labels take the low bits of the slice id, so
 consecutive slice ids differ only in them and the library shares those steps.
 
+Branch merging (Results, the contraction of the 53-qubit circuits; Table I's two T_c
+columns).  Along a stem (a chain of steps in which one large tensor absorbs smaller ones),
+consecutive absorbed tensors are first contracted with each other into a branch, which
+the stem then absorbs in one step.  The stem is read and written once per branch instead
+of once per absorbed tensor, at the price of more flops (each merged step has larger K
+and N): worth it where the separate steps are bound by memory bandwidth.  branch_merge
+chooses the groups by dynamic programming over each stem against a roofline time model
+of one step; the intermediates of the stem that remain are the original ones and branches
+stay under their own size bound, so the plan's peak never grows.
+
 Path format (Appendix E): pairs (i, j); the result is stored at position i.
 """
 
@@ -622,6 +632,146 @@ def zigzag_plan(net, open_qubits, closed_bits, tail_start: int, max_log2: float,
     if best is None:
         raise RuntimeError("no zigzag plan met the size bound")
     return best
+
+
+@dataclass
+class StepModel:
+    """Roofline time of one step: the larger of its flops (8 per complex multiply-add) at
+    the rate the matrix-core GEMM kernels reach and its complex64 bytes (A, B and C once
+    each) at the rate the memory-bound kernels reach.  The defaults are what the 53-qubit
+    workload's step table shows on one MI355X: about 100 TFLOP/s (two thirds of the FP32
+    matrix-core peak) and 5 TB/s (of 8)."""
+    flop_rate: float = 100e12
+    byte_rate: float = 5e12
+
+    def time(self, macs: float, elems: float) -> float:
+        return max(8.0 * macs / self.flop_rate, 8.0 * elems / self.byte_rate)
+
+
+def branch_merge(prob: Problem, path, branch_log2: float, max_group: int = 6,
+                 model: StepModel | None = None):
+    """Branch merging of a path (module docstring): returns the new path.
+
+    The path is read as a tree.  A stem starts at a root or at the smaller operand of a
+    step and follows the larger operand of each step down to a leaf; the smaller operands
+    b_1 .. b_m it absorbs (bottom up) are themselves processed first.  Consecutive
+    b_s .. b_e (at most `max_group`) may be contracted into one branch (b_s (x) (b_s+1 (x)
+    ... b_e)), every intermediate of which has at most 2^branch_log2 elements; the stem
+    then absorbs the branch in one step.  Groups are chosen by dynamic programming to
+    minimise the modelled time of the stem's steps plus the branches' own; a group of one
+    is the original step, so the path only changes where the model says it gains.  Each
+    step of the new path keeps its larger operand at position i."""
+    model = model or StepModel()
+    n = len(prob.dense)
+    alive = validate_path(n, path)
+    dense = list(prob.dense)
+    qm = list(prob.qmask)
+    ch = []
+    slot = list(range(n))
+    for i, j in path:
+        a, b = slot[i], slot[j]
+        ch.append((a, b))
+        dense.append(dense[a] ^ dense[b])
+        qm.append(qm[a] | qm[b])
+        slot[i] = n + len(ch) - 1
+    roots = [slot[k] for k in alive]
+    size = lambda d, q: prob.size(d, q)
+
+    def step_time(da, qa, db, qb):
+        q = qa | qb
+        macs = float(prob.rows(q)) * float(1 << _popcount(da | db))
+        return model.time(macs, size(da, qa) + size(db, qb) + size(da ^ db, q))
+
+    def big_small(v):
+        a, b = ch[v - n]
+        return (a, b) if size(dense[a], qm[a]) >= size(dense[b], qm[b]) else (b, a)
+
+    heads = set(roots) | {big_small(v)[1] for v in range(n, n + len(ch))}
+    limit = 2.0 ** branch_log2
+    new_id = {}
+    nch = {}
+
+    def make(a, b):
+        v = len(dense)
+        dense.append(dense[a] ^ dense[b])
+        qm.append(qm[a] | qm[b])
+        nch[v] = (a, b)
+        return v
+
+    # a head's absorbed operands are heads with smaller ids: increasing order sees them first
+    for h in sorted(heads):
+        if h < n:
+            new_id[h] = h
+            continue
+        smalls = []
+        u = h
+        while u >= n:
+            big, small = big_small(u)
+            smalls.append(small)
+            u = big
+        smalls.reverse()
+        bs = [new_id[b] for b in smalls]
+        m = len(bs)
+        sd, sq = [dense[u]], [qm[u]]
+        for b in bs:
+            sd.append(sd[-1] ^ dense[b])
+            sq.append(sq[-1] | qm[b])
+        best = [0.0] + [math.inf] * m
+        arg = list(range(m + 1))
+        for e in range(1, m + 1):
+            bd, bq, build = 0, 0, 0.0
+            for s_ in range(e, max(0, e - max_group), -1):
+                b = bs[s_ - 1]
+                if s_ < e:
+                    build += step_time(dense[b], qm[b], bd, bq)
+                bd, bq = bd ^ dense[b], bq | qm[b]
+                if s_ < e and size(bd, bq) > limit:
+                    break
+                t = best[s_ - 1] + build + step_time(sd[s_ - 1], sq[s_ - 1], bd, bq)
+                if t < best[e] * (1.0 - 1e-9) or s_ == e:
+                    best[e], arg[e] = t, s_
+        groups = []
+        e = m
+        while e > 0:
+            groups.append((arg[e], e))
+            e = arg[e] - 1
+        cur = u
+        for s_, e in reversed(groups):
+            br = bs[e - 1]
+            for t in range(e - 1, s_ - 1, -1):
+                br = make(bs[t - 1], br)
+            cur = make(cur, br)
+        new_id[h] = cur
+    pos = list(range(len(dense)))
+    out = []
+    for r in roots:
+        stack = [(new_id[r], False)]
+        while stack:
+            v, done = stack.pop()
+            if v < n:
+                continue
+            a, b = nch[v]
+            if done:
+                out.append((pos[a], pos[b]))
+                pos[v] = pos[a]
+            else:
+                stack += [(v, True), (b, False), (a, False)]
+    return out
+
+
+def merge_branches(net, plan: Plan, open_qubits, closed_bits, branch_log2: float | None = None,
+                   max_group: int = 6, model: StepModel | None = None) -> Plan:
+    """The plan with its path branch-merged (branch_merge) on its sliced network; the
+    sliced bonds are unchanged.  branch_log2 defaults to 4 below the plan's peak."""
+    sp = make_problem(net.labels, net.out_label, net.n_qubits, open_qubits, closed_bits,
+                      sliced=plan.sliced_labels)
+    if branch_log2 is None:
+        branch_log2 = plan.cost.peak_log2 - 4.0
+    path = branch_merge(sp, plan.path, branch_log2, max_group=max_group, model=model)
+    leaves = {k for k, l in enumerate(net.labels) if any(x in plan.sliced_labels for x in l)}
+    cost = path_cost(sp, path, leaves)
+    return Plan(path=path, sliced_labels=list(plan.sliced_labels), cost=cost,
+                n_slices=plan.n_slices)
 
 
 def validate_path(n_tensors: int, pairs):

@@ -9,7 +9,8 @@ import numpy as np
 import synth
 
 from .network import TensorNetwork, circuit_network
-from .planner import Plan, find_plan, make_problem, order_for_reuse, path_cost, zigzag_plan
+from .planner import (Plan, find_plan, make_problem, merge_branches, order_for_reuse, path_cost,
+                      zigzag_plan)
 
 
 @dataclass
@@ -113,7 +114,9 @@ def config_workload(name: str, mode: str = "default", trials: int | None = None)
     for head reuse (bound-driven global slices, cheap local ones on the low slice-id bits,
     steps above global labels once per batch of the configuration's reuse_batch), and mode
     'holes' drills the configuration's number of holes (chosen by choose_holes) into the
-    circuit, a perturbed network with fidelity about 2^-K (K = 2 per hole).  trials
+    circuit, a perturbed network with fidelity about 2^-K (K = 2 per hole).  For sliced and
+    large, mode 'branch' is the default plan with its path branch-merged (merge_branches;
+    same sliced bonds and slices).  trials
     defaults to the configuration's plan_trials.  Plans are deterministic and memoised per
     process."""
     key = (name, mode, trials)
@@ -148,6 +151,8 @@ def _config_workload(name: str, mode: str, trials: int | None) -> Workload:
     plan = find_plan(net, open_q, closed, max_log2=cfg["max_log2_size"],
                      n_sliced=cfg.get("sliced_labels"), trials=trials, seed=cfg["path_seed"],
                      reuse_batch=cfg.get("reuse_batch", 1) if mode == "reuse" else 1)
+    if mode == "branch":
+        plan = merge_branches(net, plan, open_q, closed)
     k = len(plan.sliced_labels)
     if "slice_subset" in cfg and mode == "reuse":
         # subtasks (Method): count / B random assignments of the global labels, each with all

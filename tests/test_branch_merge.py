@@ -1,0 +1,173 @@
+"""Branch merging (Results, the 53-qubit contraction; Table I's two T_c columns): runs of
+small tensors absorbed by a stem are contracted into one branch first, which the stem
+absorbs in one step.  The rewritten path must contract the same network, never raise the
+plan's peak, and change the tree only where the step model gains."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import contract as ocontract
+from oracle import statevector
+from paper_2111_03011_amd import planner
+from paper_2111_03011_amd.network import circuit_network
+
+BANDWIDTH_ONLY = planner.StepModel(flop_rate=1e30, byte_rate=1.0)
+FLOPS_ONLY = planner.StepModel(flop_rate=1.0, byte_rate=1e30)
+
+
+def _steps_as_leaf_sets(n, path):
+    """The tree of a path: for every step, the unordered pair of its operands' leaf sets."""
+    leaves = [frozenset([k]) for k in range(n)]
+    out = set()
+    for i, j in path:
+        out.add(frozenset([leaves[i], leaves[j]]))
+        leaves[i] = leaves[i] | leaves[j]
+    return out
+
+
+def _intermediate_sizes(prob, path):
+    """log2 size of every intermediate, keyed by its leaf set."""
+    d, q = list(prob.dense), list(prob.qmask)
+    leaves = [frozenset([k]) for k in range(len(d))]
+    out = {}
+    for i, j in path:
+        d[i] ^= d[j]
+        q[i] |= q[j]
+        leaves[i] = leaves[i] | leaves[j]
+        out[leaves[i]] = np.log2(prob.size(d[i], q[i]))
+    return out
+
+
+def _chain_problem():
+    """A stem S over 20 labels and two 2-leg tensors each turning one of S's labels into a
+    new open label (b1: l0 -> m0, b2: l1 -> m1); they share nothing with each other."""
+    ids = list(range(22))                   # l0..l19 = 0..19, m0 = 20, m1 = 21
+    bit = lambda xs: sum(1 << x for x in xs)
+    rows = planner.RowCounter(1, [0])
+    return planner.Problem(dense=[bit(range(20)), bit([0, 20]), bit([1, 21])],
+                           qmask=[0, 0, 0], rows=rows, label_ids=ids)
+
+
+def test_hand_built_chain_merges_when_bandwidth_bound():
+    """With time set by bytes alone the two passes over the 2^20-element stem become one
+    pass (b1 (x) b2 first: 16 elements), and the exact new path is known; with time set by
+    flops alone the merge adds 16 multiply-adds to 2^22 and the path is left as it was."""
+    prob = _chain_problem()
+    path = [(0, 1), (0, 2)]
+    assert planner.branch_merge(prob, path, 10, model=BANDWIDTH_ONLY) == [(1, 2), (0, 1)]
+    assert planner.branch_merge(prob, path, 10, model=FLOPS_ONLY) == path
+    # the branch bound excludes it: 2^4 elements > 2^3
+    assert planner.branch_merge(prob, path, 3, model=BANDWIDTH_ONLY) == path
+    # merged cost: one step of 2^22 multiply-adds against two of 2^21 each, plus the branch
+    base, merged = (planner.path_cost(prob, p) for p in (path, [(1, 2), (0, 1)]))
+    assert base.flops_invariant == 8.0 * 2 * 2 ** 21
+    assert merged.flops_invariant == 8.0 * (2 ** 22 + 2 ** 4)
+
+
+@pytest.mark.parametrize("seed,tail_start", [(3, 3), (4, 5)])
+def test_merged_path_contracts_the_network_exactly(seed, tail_start):
+    """A zigzag path (its accumulator absorbs the tail's leaves one at a time) merged
+    wherever the branch bound allows (bytes-only model): the oracle's pairwise contractor
+    along the new path returns the state vector's amplitudes."""
+    c = synth.make_circuit(3, 4, 8, seed)
+    net = circuit_network(c)
+    n = net.n_qubits
+    prob = planner.make_problem(net.labels, net.out_label, n, list(range(n)), [0])
+    path = planner.zigzag_path(prob, net.cycle, tail_start)
+    merged = planner.branch_merge(prob, path, 8, model=BANDWIDTH_ONLY)
+    assert len(merged) == len(path)
+    assert len(planner.validate_path(len(net.tensors), merged)) == 1
+    t0, t1 = (_steps_as_leaf_sets(len(net.tensors), p) for p in (path, merged))
+    assert t0 != t1                          # the tree did change
+    res = ocontract.contract_path(net.tensors, net.labels, merged, net.out_label).reshape(-1)
+    assert np.allclose(res, statevector.simulate(c), atol=1e-12)
+
+
+def test_groups_of_one_keep_the_tree_and_the_model_never_loses():
+    c = synth.make_circuit(4, 4, 14, 44)
+    net = circuit_network(c)
+    open_q = list(range(10, 16))
+    closed = synth.group_targets(16, open_q, 4, 45)
+    plan = planner.find_plan(net, open_q, closed, max_log2=14, n_sliced=6, trials=2, seed=44)
+    sp = planner.make_problem(net.labels, net.out_label, net.n_qubits, open_q, closed,
+                              sliced=plan.sliced_labels)
+    n = len(net.tensors)
+    same = planner.branch_merge(sp, plan.path, 12, max_group=1)
+    assert _steps_as_leaf_sets(n, same) == _steps_as_leaf_sets(n, plan.path)
+    for model in (planner.StepModel(), BANDWIDTH_ONLY, FLOPS_ONLY):
+        merged = planner.branch_merge(sp, plan.path, 12, model=model)
+
+        def modelled(p):
+            d, q, t = list(sp.dense), list(sp.qmask), 0.0
+            for i, j in p:
+                qc = q[i] | q[j]
+                macs = float(sp.rows(qc)) * 2.0 ** planner._popcount(d[i] | d[j])
+                t += model.time(macs, sp.size(d[i], q[i]) + sp.size(d[j], q[j])
+                                + sp.size(d[i] ^ d[j], qc))
+                d[i] ^= d[j]
+                q[i] = qc
+            return t
+        assert modelled(merged) <= modelled(plan.path) * (1 + 1e-12)
+
+
+def test_peak_kept_and_new_intermediates_bounded():
+    """Stem intermediates that remain are original ones; every new one (a branch) stays at
+    or below 2^branch_log2, so the plan's peak never grows."""
+    c = synth.make_circuit(4, 5, 12, 21)
+    net = circuit_network(c)
+    open_q = list(range(14, 20))
+    closed = synth.group_targets(20, open_q, 8, 22)
+    plan = planner.find_plan(net, open_q, closed, max_log2=16, trials=2, seed=21)
+    sp = planner.make_problem(net.labels, net.out_label, net.n_qubits, open_q, closed,
+                              sliced=plan.sliced_labels)
+    for b in (6, 10):
+        merged = planner.branch_merge(sp, plan.path, b, model=BANDWIDTH_ONLY)
+        old = _intermediate_sizes(sp, plan.path)
+        new = _intermediate_sizes(sp, merged)
+        added = {k: v for k, v in new.items() if k not in old}
+        assert added, "nothing merged"
+        assert max(added.values()) <= b + 1e-9
+        assert max(new.values()) <= max(old.values()) + 1e-9
+
+
+def test_merge_branches_keeps_slices_and_recosts():
+    c = synth.make_circuit(4, 4, 14, 44)
+    net = circuit_network(c)
+    open_q = list(range(10, 16))
+    closed = synth.group_targets(16, open_q, 4, 45)
+    plan = planner.find_plan(net, open_q, closed, max_log2=14, n_sliced=6, trials=2, seed=44)
+    m = planner.merge_branches(net, plan, open_q, closed, model=BANDWIDTH_ONLY)
+    assert m.sliced_labels == plan.sliced_labels and m.n_slices == plan.n_slices
+    sp = planner.make_problem(net.labels, net.out_label, net.n_qubits, open_q, closed,
+                              sliced=plan.sliced_labels)
+    leaves = {k for k, l in enumerate(net.labels) if any(x in plan.sliced_labels for x in l)}
+    again = planner.path_cost(sp, m.path, leaves)
+    assert again.flops_per_slice == m.cost.flops_per_slice
+    assert m.cost.peak_log2 <= plan.cost.peak_log2 + 1e-9
+
+
+def test_53q_share_branch_merged_plan():
+    """The 53-qubit share's branch-merged plan: same sliced bonds, slices and size bound,
+    a complete path, and a lower modelled time per slice than the plain path."""
+    from paper_2111_03011_amd.workload import config_workload
+    w0 = config_workload("large")
+    w = config_workload("large", mode="branch")
+    assert w.plan.sliced_labels == w0.plan.sliced_labels
+    assert np.array_equal(np.asarray(w.slice_ids), np.asarray(w0.slice_ids))
+    assert w.plan.cost.peak_log2 <= 30 + 1e-9
+    assert len(planner.validate_path(len(w.net.tensors), w.plan.path)) == 1
+    sp = planner.make_problem(w.net.labels, w.net.out_label, w.net.n_qubits, w.open_qubits,
+                              w.closed_bits, sliced=w.plan.sliced_labels)
+    model = planner.StepModel()
+
+    def modelled(p):
+        d, q, t = list(sp.dense), list(sp.qmask), 0.0
+        for i, j in p:
+            qc = q[i] | q[j]
+            macs = float(sp.rows(qc)) * 2.0 ** planner._popcount(d[i] | d[j])
+            t += model.time(macs, sp.size(d[i], q[i]) + sp.size(d[j], q[j]) + sp.size(d[i] ^ d[j], qc))
+            d[i] ^= d[j]
+            q[i] = qc
+        return t
+    assert modelled(w.plan.path) < modelled(w0.plan.path)

@@ -5,9 +5,10 @@ Oracle parity at full size: stored oracle amplitudes of single (slice, group) pa
 (tests/golden, the oracle's own network for one group with the slice's bonds fixed,
 contracted along its seeded random-greedy path, which keeps every intermediate <= 2^26)
 against the same group inside the library's 2^14-group sparse state, contracted in the
-launch configuration bench.py times (four slices per launch sequence, autotuned tiles): one
-slice at a time, and a whole launch sequence of four slices through a captured graph,
-first and replayed pass, against the sum of the four stored slices.
+launch configuration bench.py times (four slices per launch sequence, autotuned tiles), on
+the plain path and on the branch-merged one: one slice at a time, and a whole launch
+sequence of four slices through a captured graph, first and replayed pass, against the sum
+of the four stored slices.
 Properties that hold at any size complete it: a group inside the sparse state equals a
 separate contraction with that group alone, and head reuse equals the plain plan."""
 
@@ -33,14 +34,25 @@ def test_large_pairs_match_stored_oracle(form):
     exactly most slices are exact zeros): each stored pair against its group inside the
     2^14-group sparse state.  The amplitudes lie far below FP32's normal range, reached
     through the per-slice scale records."""
+    _pairs_against_stored_oracle("default", *form)
+
+
+@pytest.mark.parametrize("form", [("c64", 0, 1e-5), ("bf16x3", 2, 1e-3), ("fp16x3", 1, 1e-5)],
+                         ids=["c64", "bf16x3", "fp16x3"])
+def test_large_branch_merged_pairs_match_stored_oracle(form):
+    """The same stored pairs through the branch-merged path that bench.py times (same sliced
+    bonds and slices, a different tree, intermediates in other label orders)."""
+    _pairs_against_stored_oracle("branch", *form)
+
+
+def _pairs_against_stored_oracle(mode, name, prec, tol):
     from paper_2111_03011_amd.contractor import Contraction
     from paper_2111_03011_amd.workload import config_workload, jittered_twin
     from tests.golden_data import large_pairs
-    name, prec, tol = form
     pairs, bonds, jitter = large_pairs()
     j = synth.config("large")["parity_jitter"]
     assert jitter == (j["theta_jitter"], j["jitter_seed"])
-    w = jittered_twin(config_workload("large"), *jitter)
+    w = jittered_twin(config_workload("large", mode=mode), *jitter)
     assert [tuple(b) for b in w.sliced_bonds] == bonds, "the stored pairs were made for another slicing"
     c = Contraction(w.net, w.plan.path, sliced_labels=w.plan.sliced_labels, slice_ids=w.slice_ids,
                     open_qubits=w.open_qubits, closed_bits=w.closed_bits, max_batch_slices=4,
@@ -49,7 +61,7 @@ def test_large_pairs_match_stored_oracle(form):
     c.autotune(reps=1)
     for p in pairs:
         assert int(w.slice_ids[p.pos]) == p.slice_id and int(w.closed_bits[p.group]) == p.closed
-        log(f"large {name}: slice position {p.pos}, group {p.group} of 2^14")
+        log(f"large {name} ({mode} path): slice position {p.pos}, group {p.group} of 2^14")
         c.contract_range(p.pos, 1)
         got = c.amps[p.group].cpu().numpy()
         err = metrics.rel_error(got, p.amps)
