@@ -312,21 +312,22 @@ def cpu_baseline_sliced(w, flops_per_slice: float, budget_s: float = 20.0):
             break
     per_slice = (time.perf_counter() - t0) / done
     hi = host_info()
-    return {"value": flops_per_slice / per_slice / 1e12, "unit": "TFLOP/s",
+    return {"value": w.n_amplitudes / (per_slice * len(w.slice_ids)), "unit": "amplitudes/s",
             "cores": hi.get("blas_threads") or hi["nproc"], "kind": "oracle",
             "sample": f"{done} slice(s) of the same workload, numpy complex128 tensordot along "
                       f"the oracle's own greedy path, {per_slice:.2f} s per slice; value = the "
-                      "library's algorithmic flops per slice / oracle seconds per slice",
-            "amplitudes_per_s": w.n_amplitudes / (per_slice * len(w.slice_ids)),
+                      "workload's amplitudes / (oracle seconds per slice x its slices)",
+            "seconds_per_slice": per_slice,
+            "tflops_equivalent": flops_per_slice / per_slice / 1e12,
             "host": hi}, refs
 
 
 def cpu_baseline_large(w, flops_per_slice: float, pos: int = 0, group: int = 0):
     """The oracle, as it stands, on one (slice, group) pair of the 53-qubit share: its own
     network for that group (closed outputs fixed), the pair's slice fixed, its own seeded
-    random-greedy path (path search not timed), numpy complex128 tensordot.  Its measured
-    rate (oracle multiply-adds x 8 / seconds) prices the library's algorithmic flops per
-    slice: the per-slice time and the amplitudes/s are estimates."""
+    random-greedy path (path search not timed), numpy complex128 tensordot.  Every pair has
+    the same structure, so the oracle's rate in the bench's unit is the pair's amplitudes
+    over (its time x the number of slices summed); its flop rate is reported beside it."""
     from oracle import contract as ocontract
     from oracle import network as onetwork
     circ, n = w.circuit, w.circuit["n_qubits"]
@@ -344,18 +345,14 @@ def cpu_baseline_large(w, flops_per_slice: float, pos: int = 0, group: int = 0):
     out = ocontract.contract_path(tensors, labels, path, [net.out_label[q] for q in w.open_qubits])
     sec = time.perf_counter() - t0
     rate = 8.0 * macs / sec
-    est = flops_per_slice / rate
     hi = host_info()
-    return {"value": rate / 1e12, "unit": "TFLOP/s", "cores": hi.get("blas_threads") or hi["nproc"],
-            "kind": "oracle", "estimated": True,
+    return {"value": out.size / (sec * len(w.slice_ids)), "unit": "amplitudes/s",
+            "cores": hi.get("blas_threads") or hi["nproc"], "kind": "oracle",
             "sample": f"one (slice, group) pair of the same workload (slice position {pos}, group "
-                      f"{group}): {8 * macs:.3e} oracle flops in {sec:.1f} s; value = that measured "
-                      "oracle rate, so one slice of the library's algorithmic flops would take the "
-                      f"oracle an estimated {est:.0f} s",
-            "oracle_pair_seconds": sec, "estimated_seconds_per_slice": est,
-            "estimated_amplitudes_per_s": w.n_amplitudes / (est * len(w.slice_ids)),
-            # as the oracle computes them: one group's 64 amplitudes of one slice per pair
-            "oracle_pair_amplitudes_per_s": out.size / sec,
+                      f"{group}): its {out.size} amplitudes of one slice in {sec:.1f} s "
+                      f"({8 * macs:.3e} oracle flops); value = {out.size} / ({sec:.1f} s x "
+                      f"{len(w.slice_ids)} slices), amplitudes summed over the slice subset",
+            "oracle_pair_seconds": sec, "oracle_tflops": rate / 1e12,
             "host": hi}, {(pos, group): out.reshape(-1)}
 
 
@@ -420,9 +417,10 @@ def large_forms(args, c64_amps, c64_aps, pairs, batch: int) -> dict:
 
 
 def large_reuse(args, c64_aps) -> dict:
-    """Head reuse on the 53-qubit share (Method; Appendix B.2): the plain plan's sliced
-    bonds, the three cheapest on the low slice-id bits, 256 slices as 32 subtasks x 8 local
-    values; every step above the 95 global labels runs once per batch of 8."""
+    """Head reuse on the 53-qubit share (Method; Appendix B.2): the branch-merged path and
+    the plan's sliced bonds, the three cheapest on the low slice-id bits, 256 slices as 32
+    subtasks x 8 local values; every step above the 95 global labels runs once per batch of
+    8."""
     import torch
     from paper_2111_03011_amd.workload import config_workload
     w = config_workload("large", mode="reuse")
@@ -445,10 +443,11 @@ def large_reuse(args, c64_aps) -> dict:
     return res
 
 
-def large_plain_path(args, merged_aps, batch: int) -> dict:
+def large_plain_path(args, merged_aps, batch: int = 4) -> dict:
     """The 53-qubit share on the plain path (the planner's path before branch merging; same
-    sliced bonds and slices): one timed whole pass per form, against the branch-merged
-    complex64 rate of the headline."""
+    sliced bonds and slices; four slices per launch sequence, as its 2^30 intermediates
+    allow): one timed whole pass per form, against the branch-merged complex64 rate of the
+    headline."""
     import torch
     from paper_2111_03011_amd.workload import config_workload
     w0 = config_workload("large")
@@ -905,8 +904,8 @@ def main():
     ap.add_argument("--workload", default="large", choices=["large", "sliced", "small", "serving"])
     ap.add_argument("--precision", default="c64", choices=["c64", "bf16x3", "fp16x3"])
     ap.add_argument("--batch", type=int, default=0,
-                    help="slices per launch sequence (0 = the workload's own: 4 for large, "
-                         "8 for large --reuse, 64 for sliced)")
+                    help="slices per launch sequence (0 = the workload's own: 64 for large, "
+                         "4 for large --plain-path, 8 for large --reuse, 64 for sliced)")
     ap.add_argument("--reuse", action="store_true",
                     help="large: the head-reuse mode (32 subtasks x 8 local slices)")
     ap.add_argument("--samples", type=int, default=1000)
@@ -940,7 +939,8 @@ def main():
     ap.add_argument("--serving-batch", type=int, default=0,
                     help="serving: slices per launch sequence (0 = chosen per request)")
     args = ap.parse_args()
-    batch = args.batch or {"large": 8 if args.reuse else 4, "sliced": 64, "small": 1}.get(args.workload, 1)
+    large_batch = 8 if args.reuse else (4 if args.plain_path else 64)
+    batch = args.batch or {"large": large_batch, "sliced": 64, "small": 1}.get(args.workload, 1)
     if args.summarise_stats:
         return summarise_stats(args.summarise_stats)
     if args.write_traffic:
@@ -1012,8 +1012,8 @@ def main():
     aps = w.n_amplitudes / (ms_step * 1e-3)
     out = {
         "metric": "contraction TFLOP/s & MFMA util; amplitudes/s; p50/p99 request latency",
-        "value": flops_step / (ms_step * 1e-3) / 1e12,
-        "unit": "TFLOP/s",
+        "value": aps,
+        "unit": "amplitudes/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -1037,7 +1037,7 @@ def main():
             "workspace_gb": c.ws_bytes / 1e9,
         },
         "step_ms": percentiles(ms),
-        "amplitudes_per_s": aps,
+        "contraction_tflops": flops_step / (ms_step * 1e-3) / 1e12,
         "slices_per_s": len(w.slice_ids) / (ms_step * 1e-3),
         "ms_per_slice": ms_step / len(w.slice_ids),
         "autotuned_launches": tuned,
@@ -1079,7 +1079,7 @@ def main():
             out["head_reuse"] = large_reuse(args, aps)
             torch.cuda.empty_cache()
         if mode == "branch":
-            out["plain_path"] = large_plain_path(args, aps, batch)
+            out["plain_path"] = large_plain_path(args, aps)
             torch.cuda.empty_cache()
         out["zigzag_tail"] = large_zigzag(args)
         torch.cuda.empty_cache()

@@ -30,12 +30,12 @@ consecutive slice ids differ only in them and the library shares those steps.
 Branch merging (Results, the contraction of the 53-qubit circuits; Table I's two T_c
 columns).  Along a stem (a chain of steps in which one large tensor absorbs smaller ones),
 consecutive absorbed tensors are first contracted with each other into a branch, which
-the stem then absorbs in one step.  The stem is read and written once per branch instead
+the stem then absorbs in one step (neighbouring absorptions may also trade places first).  The stem is read and written once per branch instead
 of once per absorbed tensor, at the price of more flops (each merged step has larger K
 and N): worth it where the separate steps are bound by memory bandwidth.  branch_merge
 chooses the groups by dynamic programming over each stem against a roofline time model
 of one step; the intermediates of the stem that remain are the original ones and branches
-stay under their own size bound, so the plan's peak never grows.
+stay under their own size bound (by default the plan's peak), so the peak never grows.
 
 Path format (Appendix E): pairs (i, j); the result is stored at position i.
 """
@@ -638,29 +638,36 @@ def zigzag_plan(net, open_qubits, closed_bits, tail_start: int, max_log2: float,
 class StepModel:
     """Roofline time of one step: the larger of its flops (8 per complex multiply-add) at
     the rate the matrix-core GEMM kernels reach and its complex64 bytes (A, B and C once
-    each) at the rate the memory-bound kernels reach.  The defaults are what the 53-qubit
-    workload's step table shows on one MI355X: about 100 TFLOP/s (two thirds of the FP32
-    matrix-core peak) and 5 TB/s (of 8)."""
-    flop_rate: float = 100e12
-    byte_rate: float = 5e12
+    each) at the rate the memory-bound kernels reach.  The flop rate falls with a short
+    contraction: flop_rate * K / (K + k_half) for contracted dimension K (a tile's operand
+    loads and result stores are amortised over K).  The defaults fit the per-launch table of
+    the 53-qubit workload on one MI355X: about 120 TFLOP/s for long K, half that at K = 32,
+    and 3.5 TB/s (of 8) averaged over the memory-bound steps."""
+    flop_rate: float = 120e12
+    byte_rate: float = 3.5e12
+    k_half: float = 32.0
 
-    def time(self, macs: float, elems: float) -> float:
-        return max(8.0 * macs / self.flop_rate, 8.0 * elems / self.byte_rate)
+    def time(self, macs: float, elems: float, k: float = math.inf) -> float:
+        rate = self.flop_rate if math.isinf(k) else self.flop_rate * k / (k + self.k_half)
+        return max(8.0 * macs / rate, 8.0 * elems / self.byte_rate)
 
 
 def branch_merge(prob: Problem, path, branch_log2: float, max_group: int = 6,
-                 model: StepModel | None = None):
+                 model: StepModel | None = None, reorder: bool = True):
     """Branch merging of a path (module docstring): returns the new path.
 
     The path is read as a tree.  A stem starts at a root or at the smaller operand of a
     step and follows the larger operand of each step down to a leaf; the smaller operands
-    b_1 .. b_m it absorbs (bottom up) are themselves processed first.  Consecutive
-    b_s .. b_e (at most `max_group`) may be contracted into one branch (b_s (x) (b_s+1 (x)
-    ... b_e)), every intermediate of which has at most 2^branch_log2 elements; the stem
-    then absorbs the branch in one step.  Groups are chosen by dynamic programming to
-    minimise the modelled time of the stem's steps plus the branches' own; a group of one
-    is the original step, so the path only changes where the model says it gains.  Each
-    step of the new path keeps its larger operand at position i."""
+    b_1 .. b_m it absorbs (bottom up) are themselves processed first.  With `reorder`, two
+    neighbouring absorptions first trade places wherever that lowers the modelled time of
+    their two steps and keeps the stem's intermediate between them at or below
+    2^branch_log2 elements (passes until nothing moves).  Then consecutive b_s .. b_e (at
+    most `max_group`) may be contracted into one branch (b_s (x) (b_s+1 (x) ... b_e)),
+    every intermediate of which has at most 2^branch_log2 elements; the stem absorbs the
+    branch in one step.  Groups are chosen by dynamic programming to minimise the modelled
+    time of the stem's steps plus the branches' own; a group of one is the original step,
+    so the path only changes where the model says it gains.  Each step of the new path
+    keeps its larger operand at position i."""
     model = model or StepModel()
     n = len(prob.dense)
     alive = validate_path(n, path)
@@ -680,7 +687,8 @@ def branch_merge(prob: Problem, path, branch_log2: float, max_group: int = 6,
     def step_time(da, qa, db, qb):
         q = qa | qb
         macs = float(prob.rows(q)) * float(1 << _popcount(da | db))
-        return model.time(macs, size(da, qa) + size(db, qb) + size(da ^ db, q))
+        return model.time(macs, size(da, qa) + size(db, qb) + size(da ^ db, q),
+                          float(1 << _popcount(da & db)))
 
     def big_small(v):
         a, b = ch[v - n]
@@ -712,6 +720,20 @@ def branch_merge(prob: Problem, path, branch_log2: float, max_group: int = 6,
         smalls.reverse()
         bs = [new_id[b] for b in smalls]
         m = len(bs)
+        moved, passes = reorder, 0
+        while moved and passes < m:
+            moved, passes = False, passes + 1
+            d_, q_ = dense[u], qm[u]
+            for k in range(m - 1):
+                b1, b2 = bs[k], bs[k + 1]
+                keep = (step_time(d_, q_, dense[b1], qm[b1]) +
+                        step_time(d_ ^ dense[b1], q_ | qm[b1], dense[b2], qm[b2]))
+                md, mq = d_ ^ dense[b2], q_ | qm[b2]
+                swap = step_time(d_, q_, dense[b2], qm[b2]) + step_time(md, mq, dense[b1], qm[b1])
+                if swap < keep * (1.0 - 1e-9) and size(md, mq) <= limit:
+                    bs[k], bs[k + 1] = b2, b1
+                    moved = True
+                d_, q_ = d_ ^ dense[bs[k]], q_ | qm[bs[k]]
         sd, sq = [dense[u]], [qm[u]]
         for b in bs:
             sd.append(sd[-1] ^ dense[b])
@@ -760,14 +782,24 @@ def branch_merge(prob: Problem, path, branch_log2: float, max_group: int = 6,
 
 
 def merge_branches(net, plan: Plan, open_qubits, closed_bits, branch_log2: float | None = None,
-                   max_group: int = 6, model: StepModel | None = None) -> Plan:
+                   max_group: int = 6, model: StepModel | None = None,
+                   reorder: bool = True, passes: int = 4) -> Plan:
     """The plan with its path branch-merged (branch_merge) on its sliced network; the
-    sliced bonds are unchanged.  branch_log2 defaults to 4 below the plan's peak."""
+    sliced bonds are unchanged.  branch_log2 defaults to the plan's peak, so the merged plan
+    keeps the space complexity of the original.  Each pass sees the stems the previous one
+    left (a merged or reordered stem is a new chain); passes stop once one changes
+    nothing."""
     sp = make_problem(net.labels, net.out_label, net.n_qubits, open_qubits, closed_bits,
                       sliced=plan.sliced_labels)
     if branch_log2 is None:
-        branch_log2 = plan.cost.peak_log2 - 4.0
-    path = branch_merge(sp, plan.path, branch_log2, max_group=max_group, model=model)
+        branch_log2 = plan.cost.peak_log2
+    path = plan.path
+    for _ in range(passes):
+        new = branch_merge(sp, path, branch_log2, max_group=max_group, model=model,
+                           reorder=reorder)
+        if new == path:
+            break
+        path = new
     leaves = {k for k, l in enumerate(net.labels) if any(x in plan.sliced_labels for x in l)}
     cost = path_cost(sp, path, leaves)
     return Plan(path=path, sliced_labels=list(plan.sliced_labels), cost=cost,

@@ -116,7 +116,8 @@ def config_workload(name: str, mode: str = "default", trials: int | None = None)
     'holes' drills the configuration's number of holes (chosen by choose_holes) into the
     circuit, a perturbed network with fidelity about 2^-K (K = 2 per hole).  For sliced and
     large, mode 'branch' is the default plan with its path branch-merged (merge_branches;
-    same sliced bonds and slices).  trials
+    same sliced bonds and slices); large's 'reuse' mode starts from that merged path too.
+    trials
     defaults to the configuration's plan_trials.  Plans are deterministic and memoised per
     process."""
     key = (name, mode, trials)
@@ -151,7 +152,7 @@ def _config_workload(name: str, mode: str, trials: int | None) -> Workload:
     plan = find_plan(net, open_q, closed, max_log2=cfg["max_log2_size"],
                      n_sliced=cfg.get("sliced_labels"), trials=trials, seed=cfg["path_seed"],
                      reuse_batch=cfg.get("reuse_batch", 1) if mode == "reuse" else 1)
-    if mode == "branch":
+    if mode == "branch" or (mode == "reuse" and name == "large"):
         plan = merge_branches(net, plan, open_q, closed)
     k = len(plan.sliced_labels)
     if "slice_subset" in cfg and mode == "reuse":

@@ -12,8 +12,8 @@ from oracle import statevector
 from paper_2111_03011_amd import planner
 from paper_2111_03011_amd.network import circuit_network
 
-BANDWIDTH_ONLY = planner.StepModel(flop_rate=1e30, byte_rate=1.0)
-FLOPS_ONLY = planner.StepModel(flop_rate=1.0, byte_rate=1e30)
+BANDWIDTH_ONLY = planner.StepModel(flop_rate=1e30, byte_rate=1.0, k_half=0.0)
+FLOPS_ONLY = planner.StepModel(flop_rate=1.0, byte_rate=1e30, k_half=0.0)
 
 
 def _steps_as_leaf_sets(n, path):
@@ -65,6 +65,25 @@ def test_hand_built_chain_merges_when_bandwidth_bound():
     assert merged.flops_invariant == 8.0 * (2 ** 22 + 2 ** 4)
 
 
+def test_hand_built_chain_reorders_absorptions():
+    """A stem over 10 labels absorbs B (2 shared labels, 6 new) and then C (2 shared, none
+    new).  Absorbing C first shrinks the stem to 2^8 before B widens it.  With the bound
+    at 2^8 (the branch B (x) C would have 2^10 elements, so no branch forms) only the
+    order changes, to the known path; without reordering the path stays."""
+    bit = lambda xs: sum(1 << x for x in xs)
+    prob = planner.Problem(dense=[bit(range(10)), bit([0, 1] + list(range(10, 16))), bit([2, 3])],
+                           qmask=[0, 0, 0], rows=planner.RowCounter(1, [0]),
+                           label_ids=list(range(16)))
+    path = [(0, 1), (0, 2)]
+    assert planner.branch_merge(prob, path, 8, model=BANDWIDTH_ONLY) == [(0, 2), (0, 1)]
+    assert planner.branch_merge(prob, path, 8, model=BANDWIDTH_ONLY, reorder=False) == path
+    # the stem's intermediate between the two steps: 2^14 elements before, 2^8 after
+    assert planner.path_cost(prob, path).peak_log2 == 14
+    assert planner.path_cost(prob, [(0, 2), (0, 1)]).peak_log2 == 12
+    # a stem bound below 2^8 forbids the new intermediate: the order stays
+    assert planner.branch_merge(prob, [(0, 1), (0, 2)], 7, model=BANDWIDTH_ONLY) == path
+
+
 @pytest.mark.parametrize("seed,tail_start", [(3, 3), (4, 5)])
 def test_merged_path_contracts_the_network_exactly(seed, tail_start):
     """A zigzag path (its accumulator absorbs the tail's leaves one at a time) merged
@@ -93,10 +112,11 @@ def test_groups_of_one_keep_the_tree_and_the_model_never_loses():
     sp = planner.make_problem(net.labels, net.out_label, net.n_qubits, open_q, closed,
                               sliced=plan.sliced_labels)
     n = len(net.tensors)
-    same = planner.branch_merge(sp, plan.path, 12, max_group=1)
+    same = planner.branch_merge(sp, plan.path, 12, max_group=1, reorder=False)
     assert _steps_as_leaf_sets(n, same) == _steps_as_leaf_sets(n, plan.path)
-    for model in (planner.StepModel(), BANDWIDTH_ONLY, FLOPS_ONLY):
-        merged = planner.branch_merge(sp, plan.path, 12, model=model)
+    for model, reorder in ((planner.StepModel(), True), (planner.StepModel(), False),
+                           (BANDWIDTH_ONLY, True), (FLOPS_ONLY, True)):
+        merged = planner.branch_merge(sp, plan.path, 12, model=model, reorder=reorder)
 
         def modelled(p):
             d, q, t = list(sp.dense), list(sp.qmask), 0.0
@@ -104,7 +124,7 @@ def test_groups_of_one_keep_the_tree_and_the_model_never_loses():
                 qc = q[i] | q[j]
                 macs = float(sp.rows(qc)) * 2.0 ** planner._popcount(d[i] | d[j])
                 t += model.time(macs, sp.size(d[i], q[i]) + sp.size(d[j], q[j])
-                                + sp.size(d[i] ^ d[j], qc))
+                                + sp.size(d[i] ^ d[j], qc), 2.0 ** planner._popcount(d[i] & d[j]))
                 d[i] ^= d[j]
                 q[i] = qc
             return t

@@ -5,10 +5,10 @@ Oracle parity at full size: stored oracle amplitudes of single (slice, group) pa
 (tests/golden, the oracle's own network for one group with the slice's bonds fixed,
 contracted along its seeded random-greedy path, which keeps every intermediate <= 2^26)
 against the same group inside the library's 2^14-group sparse state, contracted in the
-launch configuration bench.py times (four slices per launch sequence, autotuned tiles), on
-the plain path and on the branch-merged one: one slice at a time, and a whole launch
-sequence of four slices through a captured graph, first and replayed pass, against the sum
-of the four stored slices.
+launch configuration bench.py times (autotuned tiles; four slices per launch sequence on
+the plain path, 64 on the branch-merged one): one slice at a time, and slices 0..3 in
+one launch sequence through a captured graph, first and replayed pass, against the sum of
+the four stored slices.
 Properties that hold at any size complete it: a group inside the sparse state equals a
 separate contraction with that group alone, and head reuse equals the plain plan."""
 
@@ -54,10 +54,11 @@ def _pairs_against_stored_oracle(mode, name, prec, tol):
     assert jitter == (j["theta_jitter"], j["jitter_seed"])
     w = jittered_twin(config_workload("large", mode=mode), *jitter)
     assert [tuple(b) for b in w.sliced_bonds] == bonds, "the stored pairs were made for another slicing"
+    batch = 64 if mode == "branch" else 4      # slices per launch sequence, as bench.py takes
     c = Contraction(w.net, w.plan.path, sliced_labels=w.plan.sliced_labels, slice_ids=w.slice_ids,
-                    open_qubits=w.open_qubits, closed_bits=w.closed_bits, max_batch_slices=4,
+                    open_qubits=w.open_qubits, closed_bits=w.closed_bits, max_batch_slices=batch,
                     precision=prec)
-    assert c.batch_slices == 4
+    assert c.batch_slices == batch
     c.autotune(reps=1)
     for p in pairs:
         assert int(w.slice_ids[p.pos]) == p.slice_id and int(w.closed_bits[p.group]) == p.closed
@@ -68,10 +69,11 @@ def _pairs_against_stored_oracle(mode, name, prec, tol):
         mx = metrics.max_error_over_rms(got, p.amps)
         log(f"  rel err {err:.3e}, max err / rms {mx:.3e}, |amp| ~ {np.abs(p.amps).max():.1e}")
         assert err <= tol and mx <= 10 * tol
-    # one whole launch sequence: slice positions 0..3, captured and replayed
-    batch = [p for p in pairs if p.group == 0 and p.pos < 4]
-    assert sorted(p.pos for p in batch) == [0, 1, 2, 3]
-    ref = sum(p.amps for p in batch)
+    # slice positions 0..3 in one launch sequence (the whole sequence at four slices per
+    # launch, the first four of 64 otherwise), captured and replayed
+    first = [p for p in pairs if p.group == 0 and p.pos < 4]
+    assert sorted(p.pos for p in first) == [0, 1, 2, 3]
+    ref = sum(p.amps for p in first)
     for rep in range(2):
         c.contract_range(0, 4)
         got = c.amps[0].cpu().numpy()
