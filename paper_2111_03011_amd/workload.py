@@ -291,14 +291,16 @@ def companion_workload(w: Workload, cuts) -> Workload:
 
 
 def serving_template(seed: int, max_log2: float = 26, work_cap: float = 2e13,
-                     max_tries: int = 50):
+                     max_tries: int = 50, branch_merge: bool = True):
     """One request of the serving stream, planned by the client ahead of time.
 
     Draws (seeded) n in [20, 36] qubits on a near-square grid (floor(sqrt n) rows, trailing
     sites of the last row removed), m in [10, 16] cycles, a kind (amplitudes: 2^[8, 16]
     bitstrings as groups of 64; samples: k in [1e3, 1e5], one group of 64 per sample) and
     2^[4, 12] slices; draws are repeated until a plan meets the size bound with that slice
-    count and its total work stays below `work_cap` flops.  Returns (Workload, n_samples).
+    count and its total work stays below `work_cap` flops.  The accepted plan's path is then
+    branch-merged (merge_branches; same slices), unless `branch_merge` is false, so the
+    stream's requests do not depend on it.  Returns (Workload, n_samples).
     """
     import math
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -325,5 +327,8 @@ def serving_template(seed: int, max_log2: float = 26, work_cap: float = 2e13,
         except RuntimeError:
             continue
         if w.plan.total_flops <= work_cap:
+            if branch_merge:
+                import dataclasses
+                w = dataclasses.replace(w, plan=merge_branches(w.net, w.plan, open_q, closed))
             return w, k
     raise RuntimeError("no request met the size bound and the work cap")
