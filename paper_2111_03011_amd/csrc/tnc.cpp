@@ -582,9 +582,14 @@ struct Compiler {
     const int nk = int(K.size());
     const double macs = double(C.rows()) * std::ldexp(1.0, int(MA.size() + NB.size() + K.size()));
 
-    // fused stream: one operand small enough to sit in registers/LDS
+    // fused stream: one operand small enough to sit in registers/LDS.  K up to 16 by
+    // default: from K = 32 on, the matrix-core GEMM is faster on the 53-qubit share's
+    // row steps (K = 64 ran at about 27 TFLOP/s as a stream); TNC_STREAM_MAX_NK (up to 6,
+    // read at every compile) moves the limit
+    const char* snk = std::getenv("TNC_STREAM_MAX_NK");
+    const int stream_max_nk = snk ? std::min(6, std::atoi(snk)) : 4;
     auto stream_ok = [&](const TState& S, const std::vector<int32_t>& Sfree) {
-      return nk <= 6 && int(Sfree.size()) <= 4;
+      return nk <= stream_max_nk && int(Sfree.size()) <= 4;
     };
     const bool a_small = stream_ok(A, MA), b_small = stream_ok(B, NB);
     if (a_small || b_small) {

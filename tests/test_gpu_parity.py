@@ -36,6 +36,21 @@ def _pair_case(rank_a, rank_b, shared, seed, order_a=None, order_b=None):
     return metrics.rel_error(got, ref), kinds
 
 
+@pytest.mark.parametrize("ra,rb,k", [(12, 7, 5), (13, 8, 6), (11, 6, 6)])
+def test_stream_long_k(ra, rb, k):
+    """The small-operand stream with K = 32 and 64 (taken by default only up to K = 16;
+    TNC_STREAM_MAX_NK=6 moves the limit), against the oracle."""
+    import os
+    os.environ["TNC_STREAM_MAX_NK"] = "6"
+    try:
+        err, kinds = _pair_case(ra, rb, k, seed=ra * 100 + rb + k)
+    finally:
+        os.environ.pop("TNC_STREAM_MAX_NK", None)
+    log(f"stream K 2^{k}: rel err {err:.3e} kinds {kinds}")
+    assert 2 in kinds and 1 not in kinds
+    assert err <= TOL
+
+
 @pytest.mark.parametrize("ra,rb,k,oa,ob,want", [
     # fused small-operand stream: gate-like operand, K labels spread through the big one
     (14, 4, 2, [5, 0, 6, 7, 8, 9, 10, 11, 1, 12, 13, 2, 3, 4], None, 2),
