@@ -427,3 +427,25 @@ def test_chosen_holes_lower_the_planned_cost():
     c["holes"] = holes
     drilled = planner.find_plan(circuit_network(c), open_q, closed, trials=1)
     assert drilled.total_flops < plain.total_flops
+
+
+def test_bench_timed_mode_and_traffic_record_keys():
+    """bench.py times the 53-qubit share on its branch-merged path (unmerged with
+    --plain-path, head reuse with --reuse), and reports committed counter traffic only for
+    the kernel source, workload, path, precision and batch the record was taken for."""
+    import argparse
+    import bench
+    a = lambda **kw: argparse.Namespace(**{"workload": "large", "precision": "c64",
+                                            "reuse": False, "plain_path": False, **kw})
+    assert bench.headline_mode(a()) == "branch"
+    assert bench.headline_mode(a(plain_path=True)) == "default"
+    assert bench.headline_mode(a(reuse=True)) == "reuse"
+    assert bench.headline_mode(a(workload="sliced")) == "default"
+    assert bench.headline_mode(a(workload="small")) == "samples"
+    import json
+    rec = json.load(open(bench.traffic_json("large", "c64")))
+    assert bench.measured_traffic(a(plain_path=True), rec["batch"]) is None
+    assert bench.measured_traffic(a(), rec["batch"] + 1) is None
+    assert bench.measured_traffic(a(precision="bf16x3"), rec["batch"]) is None
+    if rec["kernels_hip_sha256"] == bench.kernels_sha256() and rec["mode"] == "branch":
+        assert bench.measured_traffic(a(), rec["batch"]) == rec["traffic_bytes_per_launch"]
