@@ -32,7 +32,7 @@ def greedy_path(labels: list[tuple], seed: int | None = None) -> list[tuple[int,
     rng = np.random.default_rng(seed) if seed is not None else None
     labs = {i: set(l) for i, l in enumerate(labels)}
     where: dict = {}
-    for i, l in labs.items():
+    for i, l in enumerate(labels):      # fixed label order: no dependence on string hashing
         for x in l:
             where.setdefault(x, set()).add(i)
     path = []
@@ -77,7 +77,7 @@ def random_greedy_path(labels: list[tuple], seed: int, trials: int = 20,
     for _ in range(trials):
         labs = {i: set(l) for i, l in enumerate(labels)}
         where: dict = {}
-        for i, l in labs.items():
+        for i, l in enumerate(labels):  # fixed label order: the draws meet pairs in one order
             for x in l:
                 where.setdefault(x, set()).add(i)
         path, peak, macs = [], 0, 0.0
