@@ -724,8 +724,13 @@ struct Compiler {
     std::vector<int32_t> stk, perm;
     if (!g.fold && rows > 1 && M < 128 && Q.rows() < rows && stacking_enabled() &&
         double(P.elems()) < 2147483648.0) {
-      const double fill_stacked = stack_rows(P, Q, C, M, stk, perm);
-      const double fill_plain = double(M) / (M <= 64 ? 64.0 : 128.0);
+      // tile fill in both directions: unstacked, the better of the 64 x 32 tile and the
+      // 128-row tiles (128 x 8 / 16 / 32 / 64 by N); stacked, the 128-row tile
+      const double nd = double(N);
+      const double n128 = std::min(1.0, nd / (N <= 8 ? 8.0 : N <= 16 ? 16.0 : N <= 32 ? 32.0 : 64.0));
+      const double fill_plain = std::max(std::min(1.0, double(M) / 64.0) * std::min(1.0, nd / 32.0),
+                                         std::min(1.0, double(M) / 128.0) * n128);
+      const double fill_stacked = stack_rows(P, Q, C, M, stk, perm) * n128;
       if (fill_stacked > 1.25 * fill_plain) {
         M = int64_t(stk.size() / 3) * 128;
         rows = 1;
