@@ -677,8 +677,8 @@ def headline_mode(args) -> str:
 def measured_traffic(args, batch: int):
     """HBM bytes per launch of the dominant GEMM kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE passes (calibrated against a plain device copy), or None when
-    they do not describe the kernel that runs now (other source, precision, workload or
-    batch)."""
+    they do not describe the kernel that runs now (other source, precision, workload, path,
+    batch or launch program)."""
     try:
         rec = json.load(open(traffic_json(args.workload, args.precision)))
         sha = kernels_sha256()
@@ -688,7 +688,38 @@ def measured_traffic(args, batch: int):
             rec.get("precision") != args.precision or rec.get("batch") != batch or
             rec.get("mode", "default") != headline_mode(args)):
         return None
+    if rec.get("launch_shapes_sha256") != launch_shapes_sha256(args, batch):
+        return None
     return rec["traffic_bytes_per_launch"]
+
+
+def launch_shapes_sha256(args, batch: int) -> str:
+    """Fingerprint of the launch program the timed run compiles (kind, shape, tile and
+    split of every launch, before autotuning), so that a counter record is used only for
+    the launch mix it was taken on; planner and compiler changes alter it as kernel changes
+    alter the source hash.  Compiled on the host: no device is touched."""
+    import hashlib
+    from paper_2111_03011_amd import tnc
+    from paper_2111_03011_amd.workload import config_workload
+    w = config_workload(args.workload, mode=headline_mode(args))
+    prec = {"c64": tnc.TNC_C64, "bf16x3": tnc.TNC_BF16X3, "fp16x3": tnc.TNC_FP16X3}[args.precision]
+    h = tnc.tnc_net_create(0, w.net.n_qubits, w.net.ranks(), w.net.flat_labels(),
+                           w.net.flat_data(), w.net.out_label)
+    try:
+        tnc.tnc_net_set_path(h, w.plan.path)
+        tnc.set_slices_any(h, w.plan.sliced_labels, w.slice_ids)
+        tnc.tnc_net_set_targets(h, w.open_qubits, w.closed_bits)
+        p = tnc.tnc_plan_create(h, prec, batch)
+        try:
+            rows = []
+            for i in range(tnc.tnc_plan_n_launches(p)):
+                l = tnc.tnc_plan_launch_info(p, i)
+                rows.append((l.kind, l.invariant, l.rows, l.m, l.n, l.k, l.config, l.k_splits))
+        finally:
+            tnc.tnc_plan_destroy(p)
+    finally:
+        tnc.tnc_net_destroy(h)
+    return hashlib.sha256(repr(rows).encode()).hexdigest()
 
 
 def write_traffic(args, batch: int, fetch_csv, write_csv):
@@ -720,6 +751,7 @@ def write_traffic(args, batch: int, fetch_csv, write_csv):
         "kernel": name.strip(":<"), "workload": args.workload, "precision": args.precision,
         "mode": headline_mode(args),
         "batch": batch, "kernels_hip_sha256": kernels_sha256(),
+        "launch_shapes_sha256": launch_shapes_sha256(args, batch),
         "slices_profiled": args.max_slices or "all", "dispatches": [n_f, n_w],
         "fetch_kib_per_launch_raw": round(f_kib, 2), "write_kib_per_launch_raw": round(w_kib, 2),
         "copy_calibration": {"bytes": args.copy_calibration, "fetch_kib": f_copy,

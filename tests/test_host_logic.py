@@ -432,7 +432,8 @@ def test_chosen_holes_lower_the_planned_cost():
 def test_bench_timed_mode_and_traffic_record_keys():
     """bench.py times the 53-qubit share on its branch-merged path (unmerged with
     --plain-path, head reuse with --reuse), and reports committed counter traffic only for
-    the kernel source, workload, path, precision and batch the record was taken for."""
+    the kernel source, workload, path, precision, batch and launch program the record was
+    taken for."""
     import argparse
     import bench
     a = lambda **kw: argparse.Namespace(**{"workload": "large", "precision": "c64",
@@ -447,5 +448,8 @@ def test_bench_timed_mode_and_traffic_record_keys():
     assert bench.measured_traffic(a(plain_path=True), rec["batch"]) is None
     assert bench.measured_traffic(a(), rec["batch"] + 1) is None
     assert bench.measured_traffic(a(precision="bf16x3"), rec["batch"]) is None
-    if rec["kernels_hip_sha256"] == bench.kernels_sha256() and rec["mode"] == "branch":
+    if rec["kernels_hip_sha256"] == bench.kernels_sha256() and rec["mode"] == "branch" and \
+            rec.get("launch_shapes_sha256") == bench.launch_shapes_sha256(a(), rec["batch"]):
         assert bench.measured_traffic(a(), rec["batch"]) == rec["traffic_bytes_per_launch"]
+    # the fingerprint follows the launch program: the unmerged path compiles other launches
+    assert bench.launch_shapes_sha256(a(plain_path=True), 4) != bench.launch_shapes_sha256(a(), 4)
